@@ -1,0 +1,129 @@
+"""FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU path
+(``paper_2503_07439_amd``) and never imports it.
+
+Thin ctypes wrapper around ``liboracle.so`` (built from ``oracle.cpp`` and
+``fks.cpp`` with g++).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, f) for f in ("oracle.cpp", "fks.cpp") if os.path.exists(os.path.join(_HERE, f))]
+
+PROCS = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
+
+
+def build(verbose=False):
+    """Compile the oracle (plain g++, no fast-math)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", _SO] + _SRC
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_me2.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int]
+        L.orc_me2_hel.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int]
+        L.orc_me2_brute.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_int, dp, ctypes.c_int]
+        L.orc_flows.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.orc_colour_matrix.argtypes = [ctypes.c_int, dp]
+        L.orc_wavefunction.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_set_params.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_proc_info.argtypes = [ctypes.c_int, ip, ip, dp, dp, ip, ip]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def pid(proc):
+    return PROCS.index(proc)
+
+
+def set_params(alpha=1.0 / 132.507, alpha_s=0.118, m_top=173.0):
+    lib().orc_set_params(alpha, alpha_s, m_top)
+
+
+def proc_info(proc):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    c, d = ctypes.c_double(), ctypes.c_double()
+    e, f = ctypes.c_int(), ctypes.c_int()
+    lib().orc_proc_info(pid(proc), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                        ctypes.byref(e), ctypes.byref(f))
+    return dict(npart=a.value, ncolour=b.value, avg=c.value, ident=d.value, a_pow=e.value, as_pow=f.value)
+
+
+def me2(proc, mom, nthreads=8):
+    """mom: [npart, 4, n] float64 (SoA).  Returns |M|^2 [n]."""
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    n = mom.shape[2]
+    out = np.empty(n)
+    rc = lib().orc_me2(pid(proc), n, n, _dp(mom), _dp(out), nthreads)
+    assert rc == 0
+    return out
+
+
+def me2_hel(proc, mom, nthreads=8):
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    n = mom.shape[2]
+    nh = 1 << mom.shape[0]
+    out = np.empty((nh, n))
+    rc = lib().orc_me2_hel(pid(proc), n, n, _dp(mom), _dp(out), nthreads)
+    assert rc == 0
+    return out
+
+
+def me2_brute(proc, mom, hel=-1, nthreads=8):
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    n = mom.shape[2]
+    out = np.empty(n)
+    rc = lib().orc_me2_brute(pid(proc), n, n, _dp(mom), hel, _dp(out), nthreads)
+    assert rc == 0
+    return out
+
+
+def flows(proc, p_aos, hel, override_leg=-1, override_vec=None):
+    """Colour-flow (or diagram) amplitudes for one event p_aos [npart, 4]."""
+    p = np.ascontiguousarray(p_aos, dtype=np.float64)
+    nc = proc_info(proc)["ncolour"]
+    out = np.empty(2 * nc)
+    ov = np.zeros(8)
+    if override_vec is not None:
+        ov[0::2] = np.real(override_vec)
+        ov[1::2] = np.imag(override_vec)
+    rc = lib().orc_flows(pid(proc), _dp(p), hel, override_leg, _dp(ov), _dp(out))
+    assert rc == 0
+    return out[0::2] + 1j * out[1::2]
+
+
+def colour_matrix(proc):
+    nc = proc_info(proc)["ncolour"]
+    out = np.empty(2 * nc * nc)
+    lib().orc_colour_matrix(pid(proc), _dp(out))
+    return (out[0::2] + 1j * out[1::2]).reshape(nc, nc)
+
+
+def wavefunction(proc, p_aos, leg, lam):
+    p = np.ascontiguousarray(p_aos, dtype=np.float64)
+    out = np.empty(8)
+    lib().orc_wavefunction(pid(proc), _dp(p), leg, lam, _dp(out))
+    return out[0::2] + 1j * out[1::2]

@@ -1,0 +1,995 @@
+// FP64 CPU ORACLE for tree-level squared matrix elements -- TEST INFRASTRUCTURE.
+//
+// Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+// load this library.  It shares no code with the GPU path.
+//
+// What it computes (the paper's Born and real-emission equations: a tree
+// amplitude is the sum of Feynman diagrams and the cross section follows
+// from its absolute square):
+//     |M|^2 = avg * sum_{helicities} sum_{colours} |sum_{diagrams} M|^2
+// It sums every helicity combination (no filtering) and every colour.
+//
+// Two independent evaluations are provided:
+//  * me2:        colour-ordered Berends-Giele recursion for one quark line plus
+//                n gluons (gg->tt~, gg->tt~g, gg->tt~gg), contracted with a
+//                colour matrix summed by brute force over explicit SU(3)
+//                generators; explicit Feynman diagrams with explicit colour
+//                tensors for the lepton and two-quark-line processes.
+//  * me2_brute:  the full colour-dressed Feynman-rule recursion (f^{abc},
+//                T^a, every external colour assignment summed explicitly),
+//                i.e. the plain definition; slow, used to pin me2 on a few
+//                events.
+//
+// Conventions: metric (+,-,-,-); chiral Dirac representation; Feynman gauge;
+// Peskin-Schroeder vertex rules: quark-gluon  i g gamma^mu T^a,
+// fermion-photon  -i e Q gamma^mu, three-gluon
+// g f^{abc}[g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu]
+// (momenta incoming), four-gluon -i g^2 [f^{abe}f^{cde}(...) + ...],
+// propagators i(pslash+m)/(p^2-m^2) and -i g_{mu nu}/p^2.  T^a = lambda^a/2.
+// Gamma_top = 0.  Helicity index h: bit (npart-1-k) of h set <=> leg k has
+// helicity +1.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <thread>
+#include <vector>
+#include <array>
+#include <algorithm>
+
+using cd = std::complex<double>;
+static const cd I(0.0, 1.0);
+
+// ----------------------------------------------------------------------------
+// parameters
+// ----------------------------------------------------------------------------
+static double g_alpha = 1.0 / 132.507;
+static double g_alpha_s = 0.118;
+static double g_mt = 173.0;
+
+static double e_qed() { return std::sqrt(4.0 * M_PI * g_alpha); }
+static double g_qcd() { return std::sqrt(4.0 * M_PI * g_alpha_s); }
+
+// ----------------------------------------------------------------------------
+// Lorentz algebra
+// ----------------------------------------------------------------------------
+struct V4 { double v[4]; };                    // real four-vector
+typedef std::array<cd, 4> C4;                   // complex four-vector (upper index) or spinor
+typedef std::array<std::array<cd, 4>, 4> M4;    // 4x4 complex matrix
+
+static double dot(const V4& a, const V4& b) {
+  return a.v[0] * b.v[0] - a.v[1] * b.v[1] - a.v[2] * b.v[2] - a.v[3] * b.v[3];
+}
+static cd cdot(const C4& a, const C4& b) {      // Minkowski product, no conjugation
+  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+static cd cdot(const C4& a, const V4& b) {
+  return a[0] * b.v[0] - a[1] * b.v[1] - a[2] * b.v[2] - a[3] * b.v[3];
+}
+static V4 vadd(const V4& a, const V4& b) { V4 r; for (int i = 0; i < 4; ++i) r.v[i] = a.v[i] + b.v[i]; return r; }
+static V4 vneg(const V4& a) { V4 r; for (int i = 0; i < 4; ++i) r.v[i] = -a.v[i]; return r; }
+static C4 c4(const V4& a) { C4 r; for (int i = 0; i < 4; ++i) r[i] = a.v[i]; return r; }
+static C4 c4zero() { C4 r; r.fill(0.0); return r; }
+static C4 add(const C4& a, const C4& b) { C4 r; for (int i = 0; i < 4; ++i) r[i] = a[i] + b[i]; return r; }
+static C4 scale(cd s, const C4& a) { C4 r; for (int i = 0; i < 4; ++i) r[i] = s * a[i]; return r; }
+
+// gamma matrices, chiral representation: gamma^0 = [[0,1],[1,0]],
+// gamma^k = [[0, sigma^k], [-sigma^k, 0]]
+static M4 GAMMA[4];
+static void init_gamma() {
+  static bool done = false;
+  if (done) return;
+  const cd sig[4][2][2] = {
+      {{1, 0}, {0, 1}},
+      {{0, 1}, {1, 0}},
+      {{0, -I}, {I, 0}},
+      {{1, 0}, {0, -1}}};
+  for (int mu = 0; mu < 4; ++mu) {
+    for (auto& row : GAMMA[mu]) row.fill(0.0);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        if (mu == 0) {
+          GAMMA[0][a][2 + b] = sig[0][a][b];
+          GAMMA[0][2 + a][b] = sig[0][a][b];
+        } else {
+          GAMMA[mu][a][2 + b] = sig[mu][a][b];
+          GAMMA[mu][2 + a][b] = -sig[mu][a][b];
+        }
+      }
+  }
+  done = true;
+}
+
+// gamma^mu a_mu
+static M4 slash(const C4& a) {
+  M4 r;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      r[i][j] = GAMMA[0][i][j] * a[0] - GAMMA[1][i][j] * a[1] - GAMMA[2][i][j] * a[2] - GAMMA[3][i][j] * a[3];
+  return r;
+}
+static M4 mmul(const M4& a, const M4& b) {
+  M4 r;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      cd s = 0;
+      for (int k = 0; k < 4; ++k) s += a[i][k] * b[k][j];
+      r[i][j] = s;
+    }
+  return r;
+}
+static C4 mv(const M4& m, const C4& c) {       // matrix * column spinor
+  C4 r;
+  for (int i = 0; i < 4; ++i) { cd s = 0; for (int k = 0; k < 4; ++k) s += m[i][k] * c[k]; r[i] = s; }
+  return r;
+}
+static C4 vm(const C4& row, const M4& m) {     // row spinor * matrix
+  C4 r;
+  for (int j = 0; j < 4; ++j) { cd s = 0; for (int k = 0; k < 4; ++k) s += row[k] * m[k][j]; r[j] = s; }
+  return r;
+}
+static cd rc(const C4& row, const C4& col) { cd s = 0; for (int k = 0; k < 4; ++k) s += row[k] * col[k]; return s; }
+// row gamma^mu col, for mu = 0..3 (upper index)
+static C4 current(const C4& row, const C4& col) {
+  C4 r;
+  for (int mu = 0; mu < 4; ++mu) r[mu] = rc(row, mv(GAMMA[mu], col));
+  return r;
+}
+// fermion propagator i(pslash + m)/(p^2 - m^2), p along the fermion-number arrow
+static M4 fprop(const V4& p, double m) {
+  M4 r = slash(c4(p));
+  cd den = I / (dot(p, p) - m * m);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) r[i][j] = (r[i][j] + (i == j ? cd(m) : cd(0))) * den;
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// external wavefunctions
+// ----------------------------------------------------------------------------
+// two-component helicity eigenstates of sigma.phat
+static void chi(const V4& p, int lam, cd out[2]) {
+  double px = p.v[1], py = p.v[2], pz = p.v[3];
+  double pa = std::sqrt(px * px + py * py + pz * pz);
+  double pt2 = px * px + py * py;
+  double pp = (pz >= 0) ? pa + pz : pt2 / (pa - pz);   // |p| + pz without cancellation
+  if (pp <= 0.0) {                                      // p along -z
+    if (lam > 0) { out[0] = 0; out[1] = 1; }
+    else { out[0] = -1; out[1] = 0; }
+    return;
+  }
+  double nrm = 1.0 / std::sqrt(2.0 * pa * pp);
+  if (lam > 0) { out[0] = pp * nrm; out[1] = cd(px, py) * nrm; }
+  else { out[0] = cd(-px, py) * nrm; out[1] = pp * nrm; }
+}
+static void omegas(const V4& p, double m, double& wp, double& wm) {
+  double pa = std::sqrt(p.v[1] * p.v[1] + p.v[2] * p.v[2] + p.v[3] * p.v[3]);
+  wp = std::sqrt(p.v[0] + pa);                     // sqrt(E + |p|)
+  wm = (m == 0.0) ? 0.0 : m / wp;                  // sqrt(E - |p|), exact zero if massless
+}
+// u(p, lam): (sqrt(E - lam|p|) chi_lam, sqrt(E + lam|p|) chi_lam)
+static C4 u_spinor(const V4& p, double m, int lam) {
+  double wp, wm; omegas(p, m, wp, wm);
+  cd x[2]; chi(p, lam, x);
+  double lo = lam > 0 ? wm : wp, hi = lam > 0 ? wp : wm;
+  return C4{lo * x[0], lo * x[1], hi * x[0], hi * x[1]};
+}
+// v(p, lam): (-lam sqrt(E + lam|p|) chi_{-lam}, lam sqrt(E - lam|p|) chi_{-lam})
+static C4 v_spinor(const V4& p, double m, int lam) {
+  double wp, wm; omegas(p, m, wp, wm);
+  cd x[2]; chi(p, -lam, x);
+  double a = lam > 0 ? wp : wm, b = lam > 0 ? wm : wp;
+  double l = lam;
+  return C4{-l * a * x[0], -l * a * x[1], l * b * x[0], l * b * x[1]};
+}
+static C4 bar(const C4& s) {                      // s^dagger gamma^0
+  C4 r;
+  for (int j = 0; j < 4; ++j) { cd t = 0; for (int k = 0; k < 4; ++k) t += std::conj(s[k]) * GAMMA[0][k][j]; r[j] = t; }
+  return r;
+}
+// massless vector polarisation eps(k, lam) = (-lam eps1 - i eps2)/sqrt2
+static C4 polvec(const V4& k, int lam) {
+  double px = k.v[1], py = k.v[2], pz = k.v[3];
+  double pa = std::sqrt(px * px + py * py + pz * pz);
+  double pt = std::sqrt(px * px + py * py);
+  double ct = pz / pa, st = pt / pa;
+  double cp = pt > 0 ? px / pt : 1.0, sp = pt > 0 ? py / pt : 0.0;
+  double e1[4] = {0, ct * cp, ct * sp, -st};
+  double e2[4] = {0, -sp, cp, 0};
+  C4 r;
+  const double s2 = 1.0 / std::sqrt(2.0);
+  for (int mu = 0; mu < 4; ++mu) r[mu] = (-double(lam) * e1[mu] - I * e2[mu]) * s2;
+  return r;
+}
+static C4 conjv(const C4& a) { C4 r; for (int i = 0; i < 4; ++i) r[i] = std::conj(a[i]); return r; }
+
+// ----------------------------------------------------------------------------
+// SU(3)
+// ----------------------------------------------------------------------------
+typedef std::array<std::array<cd, 3>, 3> M3;
+static M3 TA[8];
+static double FABC[8][8][8];
+static void init_su3() {
+  static bool done = false;
+  if (done) return;
+  for (auto& t : TA) for (auto& r : t) r.fill(0.0);
+  // Gell-Mann matrices / 2
+  TA[0][0][1] = 0.5; TA[0][1][0] = 0.5;
+  TA[1][0][1] = -0.5 * I; TA[1][1][0] = 0.5 * I;
+  TA[2][0][0] = 0.5; TA[2][1][1] = -0.5;
+  TA[3][0][2] = 0.5; TA[3][2][0] = 0.5;
+  TA[4][0][2] = -0.5 * I; TA[4][2][0] = 0.5 * I;
+  TA[5][1][2] = 0.5; TA[5][2][1] = 0.5;
+  TA[6][1][2] = -0.5 * I; TA[6][2][1] = 0.5 * I;
+  const double r3 = 1.0 / std::sqrt(3.0);
+  TA[7][0][0] = 0.5 * r3; TA[7][1][1] = 0.5 * r3; TA[7][2][2] = -r3;
+  // f^{abc} = -2 i Tr([T^a, T^b] T^c)
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int c = 0; c < 8; ++c) {
+        cd tr = 0;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+              tr += (TA[a][i][j] * TA[b][j][k] - TA[b][i][j] * TA[a][j][k]) * TA[c][k][i];
+        double f = (-2.0 * I * tr).real();
+        FABC[a][b][c] = std::fabs(f) < 1e-14 ? 0.0 : f;
+      }
+  done = true;
+}
+
+// ----------------------------------------------------------------------------
+// process table
+// ----------------------------------------------------------------------------
+enum { EE_MUMU = 0, EE_UU, EE_UUG, GG_TT, UU_TT, GG_TTG, UU_TTG, UG_TTU, GG_TTGG, NPROC };
+
+struct ProcDef {
+  const char* name;
+  int npart;
+  int ncolour;          // dimension of the amplitude vector returned by flows()
+  double avg;           // initial spin x colour average
+  double ident;         // identical final-state particle factor (exported, not applied)
+  int nin;
+  // per leg: 'g' gluon, 'q' quark (fermion), 'Q' antiquark, 'l' lepton, 'L' antilepton
+  const char* kinds;
+  int a_pow, as_pow;    // |M|^2 scales as alpha^a alpha_s^b
+};
+static const ProcDef PROCS[NPROC] = {
+    {"ee_mumu", 4, 1, 0.25, 1.0, 2, "lLlL", 2, 0},
+    {"ee_uu", 4, 1, 0.25, 1.0, 2, "lLqQ", 2, 0},
+    {"ee_uug", 5, 2, 0.25, 1.0, 2, "lLqQg", 2, 1},
+    {"gg_tt", 4, 2, 1.0 / 256.0, 1.0, 2, "ggqQ", 0, 2},
+    {"uu_tt", 4, 1, 1.0 / 36.0, 1.0, 2, "qQqQ", 0, 2},
+    {"gg_ttg", 5, 6, 1.0 / 256.0, 1.0, 2, "ggqQg", 0, 3},
+    {"uu_ttg", 5, 5, 1.0 / 36.0, 1.0, 2, "qQqQg", 0, 3},
+    {"ug_ttu", 5, 5, 1.0 / 96.0, 1.0, 2, "qgqQq", 0, 3},
+    {"gg_ttgg", 6, 24, 1.0 / 256.0, 0.5, 2, "ggqQgg", 0, 4},
+};
+
+static double leg_mass(int proc, int k) {
+  // tops are legs 2,3 of every gg/uu/ug process; everything else massless
+  if (proc >= GG_TT && (k == 2 || k == 3)) return g_mt;
+  return 0.0;
+}
+
+// Wavefunction of external leg k.  incoming momenta q_k = +p_k (initial),
+// -p_k (final).  Fermion legs give the row or column spinor according to the
+// particle and its direction; vector legs give eps (incoming) or eps* (outgoing).
+struct Ext {
+  V4 q[8];        // incoming momenta
+  V4 p[8];        // physical momenta
+  C4 w[8];        // wavefunction (vector: upper-index components; spinor: row or column)
+};
+
+// ----------------------------------------------------------------------------
+// colour-ordered Berends-Giele recursion: one quark line + n gluons
+// ----------------------------------------------------------------------------
+// Colour decomposition M = sum_sigma (T^{a_sigma1} ... T^{a_sigman})_{i j} A(sigma),
+// i the colour of the row end, j of the column end.  Colour-ordered rules
+// (T normalised to Tr = 1/2) follow from the vertex rules above after
+// f^{abc} = -2i Tr([T^a,T^b]T^c) and T^c_{ij}T^c_{kl} -> (1/2) d_il d_kj
+// (the U(1) pieces cancel at tree level): quark vertex i g gamma^mu,
+// ordered 3-gluon vertex -2 i g V_{mu nu rho}, ordered 4-gluon vertex
+// 2 i g^2 (2 g^{mu rho} g^{nu sigma} - g^{mu sigma} g^{nu rho} - g^{mu nu} g^{rho sigma}),
+// and a factor 1/2 per internal gluon line.
+struct BGLine {
+  int row, col;                   // leg indices of the row and column ends
+  std::vector<int> gl;            // gluon leg indices
+  double m;                       // quark mass
+};
+
+static BGLine bg_line(int proc) {
+  BGLine L;
+  L.row = 2; L.col = 3; L.m = g_mt;
+  if (proc == GG_TT) L.gl = {0, 1};
+  else if (proc == GG_TTG) L.gl = {0, 1, 4};
+  else L.gl = {0, 1, 4, 5};
+  return L;
+}
+
+struct BGCache {
+  int n;
+  std::vector<char> have;
+  std::vector<C4> J;
+  std::vector<V4> Q;
+  int key(const int* t, int len) const {
+    int k = 0;
+    for (int i = 0; i < len; ++i) k = k * (n + 1) + (t[i] + 1);
+    return k;
+  }
+};
+
+static C4 bg_current(BGCache& c, const Ext& ex, const BGLine& L, const int* t, int len, V4& Qout) {
+  int k = c.key(t, len);
+  if (c.have[k]) { Qout = c.Q[k]; return c.J[k]; }
+  C4 J = c4zero();
+  V4 Q{{0, 0, 0, 0}};
+  for (int i = 0; i < len; ++i) Q = vadd(Q, ex.q[L.gl[t[i]]]);
+  if (len == 1) {
+    J = ex.w[L.gl[t[0]]];
+  } else {
+    const double g = g_qcd();
+    double P2 = dot(Q, Q);
+    for (int s = 1; s < len; ++s) {           // three-gluon vertex, order (A, B, offshell)
+      V4 QA, QB;
+      C4 JA = bg_current(c, ex, L, t, s, QA);
+      C4 JB = bg_current(c, ex, L, t + s, len - s, QB);
+      cd ab = cdot(JA, JB);
+      V4 d1, d2, d3;
+      for (int m = 0; m < 4; ++m) {
+        d1.v[m] = QA.v[m] - QB.v[m];
+        d2.v[m] = QA.v[m] + 2.0 * QB.v[m];
+        d3.v[m] = 2.0 * QA.v[m] + QB.v[m];
+      }
+      cd a2 = cdot(JA, d2), b3 = cdot(JB, d3);
+      C4 V;
+      for (int m = 0; m < 4; ++m) V[m] = ab * d1.v[m] + JB[m] * a2 - JA[m] * b3;
+      // (-i/P^2)(1/2)(-2 i g) V = -g V / P^2
+      J = add(J, scale(-g / P2, V));
+    }
+    for (int s1 = 1; s1 < len; ++s1)           // four-gluon vertex, order (A, B, C, offshell)
+      for (int s2 = s1 + 1; s2 < len; ++s2) {
+        V4 QA, QB, QC;
+        C4 JA = bg_current(c, ex, L, t, s1, QA);
+        C4 JB = bg_current(c, ex, L, t + s1, s2 - s1, QB);
+        C4 JC = bg_current(c, ex, L, t + s2, len - s2, QC);
+        cd ac = cdot(JA, JC), bc = cdot(JB, JC), ab = cdot(JA, JB);
+        C4 V;
+        for (int m = 0; m < 4; ++m) V[m] = 2.0 * ac * JB[m] - bc * JA[m] - ab * JC[m];
+        // (-i/P^2)(1/2)(2 i g^2) V = g^2 V / P^2
+        J = add(J, scale(g * g / P2, V));
+      }
+  }
+  c.have[k] = 1; c.J[k] = J; c.Q[k] = Q;
+  Qout = Q;
+  return J;
+}
+
+// Row current after absorbing the ordered gluons t[0..len): R(A) = sum R(A') (i g Jslash(A'')) S(-Q)
+static C4 bg_row(BGCache& c, std::map<int, C4>& rmemo, const Ext& ex, const BGLine& L, const int* t, int len) {
+  if (len == 0) return ex.w[L.row];
+  int k = c.key(t, len);
+  auto it = rmemo.find(k);
+  if (it != rmemo.end()) return it->second;
+  const double g = g_qcd();
+  C4 acc = c4zero();
+  for (int s = 0; s < len; ++s) {
+    C4 R = bg_row(c, rmemo, ex, L, t, s);
+    V4 Qd;
+    C4 Jd = bg_current(c, ex, L, t + s, len - s, Qd);
+    acc = add(acc, vm(R, slash(scale(I * g, Jd))));
+  }
+  V4 Q = ex.q[L.row];
+  for (int i = 0; i < len; ++i) Q = vadd(Q, ex.q[L.gl[t[i]]]);
+  C4 r = vm(acc, fprop(vneg(Q), L.m));
+  rmemo[k] = r;
+  return r;
+}
+
+static void bg_flows(const BGLine& L, const Ext& ex, cd* out) {
+  int n = (int)L.gl.size();
+  BGCache c;
+  c.n = n;
+  int sz = 1;
+  for (int i = 0; i < n; ++i) sz *= (n + 1);
+  c.have.assign(sz, 0);
+  c.J.resize(sz);
+  c.Q.resize(sz);
+  std::map<int, C4> rmemo;
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  const double g = g_qcd();
+  int idx = 0;
+  do {
+    cd A = 0;
+    for (int s = 0; s < n; ++s) {
+      C4 R = bg_row(c, rmemo, ex, L, perm.data(), s);
+      V4 Qd;
+      C4 Jd = bg_current(c, ex, L, perm.data() + s, n - s, Qd);
+      A += rc(vm(R, slash(scale(I * g, Jd))), ex.w[L.col]);
+    }
+    out[idx++] = A;
+  } while (std::next_permutation(perm.begin(), perm.end()));
+}
+
+// colour matrix of the string basis, by brute force over explicit generators
+static std::vector<double> bg_colour_matrix(int n) {
+  init_su3();
+  std::vector<std::vector<int>> perms;
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  do perms.push_back(perm); while (std::next_permutation(perm.begin(), perm.end()));
+  int nc = (int)perms.size();
+  std::vector<double> C(nc * nc, 0.0);
+  int nadj = 1;
+  for (int i = 0; i < n; ++i) nadj *= 8;
+  std::vector<M3> S(nc);
+  std::vector<int> a(n);
+  for (int code = 0; code < nadj; ++code) {
+    int x = code;
+    for (int i = 0; i < n; ++i) { a[i] = x % 8; x /= 8; }
+    for (int p = 0; p < nc; ++p) {
+      M3 m;
+      for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) m[i][j] = (i == j) ? 1.0 : 0.0;
+      for (int s = 0; s < n; ++s) {
+        const M3& t = TA[a[perms[p][s]]];
+        M3 r;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) { cd v = 0; for (int k = 0; k < 3; ++k) v += m[i][k] * t[k][j]; r[i][j] = v; }
+        m = r;
+      }
+      S[p] = m;
+    }
+    for (int p = 0; p < nc; ++p)
+      for (int q = 0; q < nc; ++q) {
+        cd v = 0;
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) v += std::conj(S[p][i][j]) * S[q][i][j];
+        C[p * nc + q] += v.real();
+      }
+  }
+  return C;
+}
+
+// ----------------------------------------------------------------------------
+// explicit diagrams with explicit colour tensors
+// ----------------------------------------------------------------------------
+// Two quark lines (light line 1 = (r1, c1), top line 2 = (r2, c2)) exchanging a
+// gluon, with an optional extra gluon leg.  Returns the 5 diagram amplitudes
+// (or 1 without the gluon); colour tensors are built by colour_tensors_2line.
+struct TwoLine { int r1, c1, r2, c2, g; };
+
+static TwoLine two_line(int proc) {
+  if (proc == UU_TT) return TwoLine{1, 0, 2, 3, -1};
+  if (proc == UU_TTG) return TwoLine{1, 0, 2, 3, 4};
+  return TwoLine{4, 0, 2, 3, 1};                  // ug -> tt~u: row = outgoing u, col = incoming u
+}
+
+static void two_line_amps(int proc, const Ext& ex, cd* out) {
+  TwoLine T = two_line(proc);
+  const double g = g_qcd();
+  const double m1 = 0.0, m2 = g_mt;
+  const C4 &r1 = ex.w[T.r1], &c1 = ex.w[T.c1], &r2 = ex.w[T.r2], &c2 = ex.w[T.c2];
+  V4 P1 = vadd(ex.q[T.r1], ex.q[T.c1]);
+  V4 P2 = vadd(ex.q[T.r2], ex.q[T.c2]);
+  if (T.g < 0) {
+    // [r2 (i g gamma^mu) c2] (-i g_{mu nu}/P^2) [r1 (i g gamma^nu) c1]
+    cd a = cdot(current(r2, c2), current(r1, c1)) * (I * g) * (I * g) * (-I / dot(P1, P1));
+    out[0] = a;
+    return;
+  }
+  const C4& eg = ex.w[T.g];
+  const V4& qg = ex.q[T.g];
+  M4 ge = slash(scale(I * g, eg));
+  // D1: gluon on line 1, row side
+  {
+    C4 row = vm(vm(r1, ge), fprop(vneg(vadd(ex.q[T.r1], qg)), m1));
+    cd a = cdot(current(row, c1), current(r2, c2)) * (I * g) * (I * g) * (-I / dot(P2, P2));
+    out[0] = a;
+  }
+  // D2: gluon on line 1, column side
+  {
+    C4 col = mv(fprop(vadd(ex.q[T.c1], qg), m1), mv(ge, c1));
+    cd a = cdot(current(r1, col), current(r2, c2)) * (I * g) * (I * g) * (-I / dot(P2, P2));
+    out[1] = a;
+  }
+  // D3: gluon on line 2, row side
+  {
+    C4 row = vm(vm(r2, ge), fprop(vneg(vadd(ex.q[T.r2], qg)), m2));
+    cd a = cdot(current(row, c2), current(r1, c1)) * (I * g) * (I * g) * (-I / dot(P1, P1));
+    out[2] = a;
+  }
+  // D4: gluon on line 2, column side
+  {
+    C4 col = mv(fprop(vadd(ex.q[T.c2], qg), m2), mv(ge, c2));
+    cd a = cdot(current(r2, col), current(r1, c1)) * (I * g) * (I * g) * (-I / dot(P1, P1));
+    out[3] = a;
+  }
+  // D5: three-gluon vertex, legs (b, mu, P1), (c, nu, P2), (a, rho, qg)
+  {
+    C4 L1 = scale(I * g, current(r1, c1));
+    C4 L2 = scale(I * g, current(r2, c2));
+    // propagators -i/P^2 on the two exchanged gluons
+    L1 = scale(-I / dot(P1, P1), L1);
+    L2 = scale(-I / dot(P2, P2), L2);
+    // V(k,p,q) contracted: (L1.L2)(k-p).eg + (L2.eg)(p-q).L1 + (eg.L1)(q-k).L2
+    V4 kmp, pmq, qmk;
+    for (int m = 0; m < 4; ++m) {
+      kmp.v[m] = P1.v[m] - P2.v[m];
+      pmq.v[m] = P2.v[m] - qg.v[m];
+      qmk.v[m] = qg.v[m] - P1.v[m];
+    }
+    cd v = cdot(L1, L2) * cdot(eg, kmp) + cdot(L2, eg) * cdot(L1, pmq) + cdot(eg, L1) * cdot(L2, qmk);
+    out[4] = g * v;
+  }
+}
+
+// colour tensors c_D[i1][j1][i2][j2][a] for the two-line diagrams, and the
+// colour matrix K_{DD'} = sum conj(c_D) c_D'
+static std::vector<cd> two_line_colour_matrix(int proc) {
+  init_su3();
+  bool glu = (proc != UU_TT);
+  int nd = glu ? 5 : 1;
+  int na = glu ? 8 : 1;
+  std::vector<cd> K(nd * nd, 0.0);
+  for (int i1 = 0; i1 < 3; ++i1)
+    for (int j1 = 0; j1 < 3; ++j1)
+      for (int i2 = 0; i2 < 3; ++i2)
+        for (int j2 = 0; j2 < 3; ++j2)
+          for (int a = 0; a < na; ++a) {
+            cd c[5] = {0, 0, 0, 0, 0};
+            for (int b = 0; b < 8; ++b) {
+              if (!glu) { c[0] += TA[b][i1][j1] * TA[b][i2][j2]; continue; }
+              cd ab1 = 0, ba1 = 0, ab2 = 0, ba2 = 0;
+              for (int k = 0; k < 3; ++k) {
+                ab1 += TA[a][i1][k] * TA[b][k][j1];
+                ba1 += TA[b][i1][k] * TA[a][k][j1];
+                ab2 += TA[a][i2][k] * TA[b][k][j2];
+                ba2 += TA[b][i2][k] * TA[a][k][j2];
+              }
+              c[0] += ab1 * TA[b][i2][j2];
+              c[1] += ba1 * TA[b][i2][j2];
+              c[2] += TA[b][i1][j1] * ab2;
+              c[3] += TA[b][i1][j1] * ba2;
+              for (int cc = 0; cc < 8; ++cc)
+                if (FABC[b][cc][a] != 0.0) c[4] += TA[b][i1][j1] * TA[cc][i2][j2] * FABC[b][cc][a];
+            }
+            for (int d = 0; d < nd; ++d)
+              for (int e = 0; e < nd; ++e) K[d * nd + e] += std::conj(c[d]) * c[e];
+          }
+  return K;
+}
+
+// e+e- -> f fbar (g) through one photon
+static void ee_amps(int proc, const Ext& ex, cd* out) {
+  const double e = e_qed(), g = g_qcd();
+  const double Qe = -1.0;
+  const double Qf = (proc == EE_MUMU) ? -1.0 : 2.0 / 3.0;
+  // lepton current vbar(e+) gamma^nu u(e-): row = leg 1, column = leg 0
+  C4 Lc = scale(-I * e * Qe, current(ex.w[1], ex.w[0]));
+  V4 P = vadd(ex.q[0], ex.q[1]);
+  C4 Lp = scale(-I / dot(P, P), Lc);                 // photon propagator
+  if (proc != EE_UUG) {
+    out[0] = cdot(scale(-I * e * Qf, current(ex.w[2], ex.w[3])), Lp);
+    return;
+  }
+  M4 ge = slash(scale(I * g, ex.w[4]));
+  // D1: gluon on the outgoing quark (row, leg 2)
+  C4 row = vm(vm(ex.w[2], ge), fprop(vneg(vadd(ex.q[2], ex.q[4])), 0.0));
+  out[0] = cdot(scale(-I * e * Qf, current(row, ex.w[3])), Lp);
+  // D2: gluon on the outgoing antiquark (column, leg 3)
+  C4 col = mv(fprop(vadd(ex.q[3], ex.q[4]), 0.0), mv(ge, ex.w[3]));
+  out[1] = cdot(scale(-I * e * Qf, current(ex.w[2], col)), Lp);
+}
+
+// ----------------------------------------------------------------------------
+// generic per-event evaluation
+// ----------------------------------------------------------------------------
+static int helicity_of(int h, int npart, int k) { return ((h >> (npart - 1 - k)) & 1) ? +1 : -1; }
+
+// Build external wavefunctions for helicity h.  override_leg >= 0 replaces that
+// vector leg's polarisation by override_vec (gauge and spin-correlation tests).
+static void build_ext(int proc, const V4* p, int h, Ext& ex, int override_leg, const C4* override_vec) {
+  const ProcDef& P = PROCS[proc];
+  for (int k = 0; k < P.npart; ++k) {
+    bool in = k < P.nin;
+    ex.p[k] = p[k];
+    ex.q[k] = in ? p[k] : vneg(p[k]);
+    int lam = helicity_of(h, P.npart, k);
+    double m = leg_mass(proc, k);
+    char kind = P.kinds[k];
+    if (kind == 'g') {
+      C4 e = polvec(p[k], lam);
+      ex.w[k] = in ? e : conjv(e);
+      if (k == override_leg) ex.w[k] = *override_vec;
+    } else if (kind == 'q' || kind == 'l') {
+      // particle: incoming -> column u(p); outgoing -> row ubar(p)
+      ex.w[k] = in ? u_spinor(p[k], m, lam) : bar(u_spinor(p[k], m, lam));
+    } else {
+      // antiparticle: incoming -> row vbar(p); outgoing -> column v(p)
+      ex.w[k] = in ? bar(v_spinor(p[k], m, lam)) : v_spinor(p[k], m, lam);
+    }
+  }
+}
+
+struct ColourData {
+  int nc;
+  std::vector<cd> C;     // nc x nc hermitian
+};
+static ColourData COLOUR[NPROC];
+static void init_colour() {
+  static bool done = false;
+  if (done) return;
+  init_gamma();
+  init_su3();
+  for (int p = 0; p < NPROC; ++p) {
+    ColourData& cdat = COLOUR[p];
+    cdat.nc = PROCS[p].ncolour;
+    cdat.C.assign(cdat.nc * cdat.nc, 0.0);
+    if (p == GG_TT || p == GG_TTG || p == GG_TTGG) {
+      int n = (p == GG_TT) ? 2 : (p == GG_TTG ? 3 : 4);
+      std::vector<double> C = bg_colour_matrix(n);
+      for (size_t i = 0; i < C.size(); ++i) cdat.C[i] = C[i];
+    } else if (p == UU_TT || p == UU_TTG || p == UG_TTU) {
+      cdat.C = two_line_colour_matrix(p);
+    } else if (p == EE_UUG) {
+      // both diagrams carry T^a_{ij}: sum |T^a_ij|^2 = Tr(T^a T^a) = 4
+      for (auto& x : cdat.C) x = 4.0;
+    } else if (p == EE_UU) {
+      cdat.C[0] = 3.0;     // delta_ij delta_ij
+    } else {
+      cdat.C[0] = 1.0;
+    }
+  }
+  done = true;
+}
+
+static void flows(int proc, const Ext& ex, cd* out) {
+  switch (proc) {
+    case EE_MUMU: case EE_UU: case EE_UUG: ee_amps(proc, ex, out); break;
+    case UU_TT: case UU_TTG: case UG_TTU: two_line_amps(proc, ex, out); break;
+    default: bg_flows(bg_line(proc), ex, out); break;
+  }
+}
+
+static double quad(const ColourData& c, const cd* A) {
+  cd s = 0;
+  for (int i = 0; i < c.nc; ++i)
+    for (int j = 0; j < c.nc; ++j) s += std::conj(A[i]) * c.C[i * c.nc + j] * A[j];
+  return s.real();
+}
+
+static void load_event(const double* mom, int64_t ld, int64_t e, int npart, V4* p) {
+  for (int k = 0; k < npart; ++k)
+    for (int mu = 0; mu < 4; ++mu) p[k].v[mu] = mom[(k * 4 + mu) * ld + e];
+}
+
+// sum over helicities of the colour-summed |M_h|^2, times the average factor
+static double me2_event(int proc, const V4* p, double* per_hel) {
+  const ProcDef& P = PROCS[proc];
+  const ColourData& c = COLOUR[proc];
+  int nh = 1 << P.npart;
+  std::vector<cd> A(c.nc);
+  double sum = 0;
+  Ext ex;
+  for (int h = 0; h < nh; ++h) {
+    build_ext(proc, p, h, ex, -1, nullptr);
+    flows(proc, ex, A.data());
+    double v = quad(c, A.data());
+    if (per_hel) per_hel[h] = v * P.avg;
+    sum += v;
+  }
+  return sum * P.avg;
+}
+
+template <class F>
+static void parallel_for(int64_t n, int nthreads, F f) {
+  if (nthreads <= 1 || n < 2) { for (int64_t i = 0; i < n; ++i) f(i); return; }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nthreads - 1) / nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([=, &f]() { for (int64_t i = lo; i < hi; ++i) f(i); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// ----------------------------------------------------------------------------
+// colour-dressed brute force (full Feynman rules, explicit colours)
+// ----------------------------------------------------------------------------
+// Currents over subsets of gluons carry an explicit adjoint index; the quark
+// row current carries a fundamental index.  Summing the recursion equals
+// summing all Feynman diagrams; every external colour assignment is summed.
+struct Brute {
+  const BGLine* L;
+  const Ext* ex;
+  int n;
+  int ag[4];                        // external gluon colours
+  std::vector<std::array<C4, 8>> G; // gluon currents per subset mask
+  std::vector<V4> GQ;
+  std::vector<char> gh;
+  std::vector<std::array<C4, 3>> R; // row currents per subset mask
+  std::vector<char> rh;
+};
+
+static void brute_gluon(Brute& b, int mask) {
+  if (b.gh[mask]) return;
+  const Ext& ex = *b.ex;
+  const BGLine& L = *b.L;
+  std::array<C4, 8> J;
+  for (auto& x : J) x = c4zero();
+  V4 Q{{0, 0, 0, 0}};
+  int cnt = 0, only = -1;
+  for (int i = 0; i < b.n; ++i)
+    if (mask >> i & 1) { Q = vadd(Q, ex.q[L.gl[i]]); ++cnt; only = i; }
+  if (cnt == 1) {
+    J[b.ag[only]] = ex.w[L.gl[only]];
+  } else {
+    const double g = g_qcd();
+    double P2 = dot(Q, Q);
+    // 3-vertex, unordered splits: s1 contains the lowest set bit
+    int low = mask & -mask;
+    for (int s1 = (mask - 1) & mask; s1 > 0; s1 = (s1 - 1) & mask) {
+      if (!(s1 & low)) continue;
+      int s2 = mask ^ s1;
+      brute_gluon(b, s1); brute_gluon(b, s2);
+      const V4 &Q1 = b.GQ[s1], &Q2 = b.GQ[s2];
+      V4 Q3 = vneg(vadd(Q1, Q2));
+      V4 kmp, pmq, qmk;
+      for (int m = 0; m < 4; ++m) { kmp.v[m] = Q1.v[m] - Q2.v[m]; pmq.v[m] = Q2.v[m] - Q3.v[m]; qmk.v[m] = Q3.v[m] - Q1.v[m]; }
+      for (int c1 = 0; c1 < 8; ++c1)
+        for (int c2 = 0; c2 < 8; ++c2) {
+          const C4 &A = b.G[s1][c1], &B = b.G[s2][c2];
+          if (A[0] == 0.0 && A[1] == 0.0 && A[2] == 0.0 && A[3] == 0.0) continue;
+          if (B[0] == 0.0 && B[1] == 0.0 && B[2] == 0.0 && B[3] == 0.0) continue;
+          // V_rho = (A.B)(k-p)_rho + B_rho (p-q).A + A_rho (q-k).B
+          cd ab = cdot(A, B), pa = cdot(A, pmq), qb = cdot(B, qmk);
+          C4 V;
+          for (int m = 0; m < 4; ++m) V[m] = ab * kmp.v[m] + B[m] * pa + A[m] * qb;
+          for (int c = 0; c < 8; ++c) {
+            double f = FABC[c1][c2][c];
+            if (f == 0.0) continue;
+            J[c] = add(J[c], scale((-I / P2) * g * f, V));
+          }
+        }
+    }
+    // 4-vertex, unordered 3-partitions
+    std::vector<int> bits;
+    for (int i = 0; i < b.n; ++i) if (mask >> i & 1) bits.push_back(i);
+    int nb = (int)bits.size();
+    if (nb >= 3) {
+      std::vector<int> lab(nb, 0);
+      int total = 1;
+      for (int i = 0; i < nb; ++i) total *= 3;
+      for (int code = 0; code < total; ++code) {
+        int x = code;
+        int m3[3] = {0, 0, 0};
+        for (int i = 0; i < nb; ++i) { m3[x % 3] |= 1 << bits[i]; x /= 3; }
+        if (!m3[0] || !m3[1] || !m3[2]) continue;
+        // canonical: lowest bits ordered m3[0] < m3[1] < m3[2]
+        auto lowb = [](int m) { return m & -m; };
+        if (!(lowb(m3[0]) < lowb(m3[1]) && lowb(m3[1]) < lowb(m3[2]))) continue;
+        for (int s = 0; s < 3; ++s) brute_gluon(b, m3[s]);
+        for (int c1 = 0; c1 < 8; ++c1)
+          for (int c2 = 0; c2 < 8; ++c2)
+            for (int c3 = 0; c3 < 8; ++c3) {
+              const C4 &A = b.G[m3[0]][c1], &B = b.G[m3[1]][c2], &C = b.G[m3[2]][c3];
+              cd ab = cdot(A, B), ac = cdot(A, C), bc = cdot(B, C);
+              if (ab == 0.0 && ac == 0.0 && bc == 0.0) continue;
+              for (int d = 0; d < 8; ++d) {
+                // legs a=A(mu), b=B(nu), c=C(rho), d=offshell(sigma)
+                double f1 = 0, f2 = 0, f3 = 0;
+                for (int e = 0; e < 8; ++e) {
+                  f1 += FABC[c1][c2][e] * FABC[c3][d][e];
+                  f2 += FABC[c1][c3][e] * FABC[c2][d][e];
+                  f3 += FABC[c1][d][e] * FABC[c2][c3][e];
+                }
+                if (f1 == 0 && f2 == 0 && f3 == 0) continue;
+                C4 V;
+                for (int m = 0; m < 4; ++m)
+                  V[m] = f1 * (ac * B[m] - A[m] * bc) + f2 * (ab * C[m] - A[m] * bc) + f3 * (ab * C[m] - ac * B[m]);
+                // (-i/P^2)(-i g^2) V = -g^2 V / P^2
+                J[d] = add(J[d], scale(-g * g / P2, V));
+              }
+            }
+      }
+    }
+  }
+  b.G[mask] = J;
+  b.GQ[mask] = Q;
+  b.gh[mask] = 1;
+}
+
+static void brute_row(Brute& b, int mask, int irow) {
+  if (b.rh[mask]) return;
+  const Ext& ex = *b.ex;
+  const BGLine& L = *b.L;
+  std::array<C4, 3> R;
+  for (auto& x : R) x = c4zero();
+  if (mask == 0) {
+    R[irow] = ex.w[L.row];
+  } else {
+    const double g = g_qcd();
+    std::array<C4, 3> acc;
+    for (auto& x : acc) x = c4zero();
+    for (int sg = mask; sg > 0; sg = (sg - 1) & mask) {   // gluons absorbed at the last vertex
+      int sr = mask ^ sg;
+      brute_row(b, sr, irow);
+      brute_gluon(b, sg);
+      for (int c = 0; c < 8; ++c) {
+        const C4& G = b.G[sg][c];
+        if (G[0] == 0.0 && G[1] == 0.0 && G[2] == 0.0 && G[3] == 0.0) continue;
+        M4 gs = slash(scale(I * g, G));
+        for (int j = 0; j < 3; ++j) {
+          C4 t = vm(b.R[sr][j], gs);
+          for (int k = 0; k < 3; ++k)
+            if (TA[c][j][k] != 0.0) acc[k] = add(acc[k], scale(TA[c][j][k], t));
+        }
+      }
+    }
+    V4 Q = ex.q[L.row];
+    for (int i = 0; i < b.n; ++i) if (mask >> i & 1) Q = vadd(Q, ex.q[L.gl[i]]);
+    M4 S = fprop(vneg(Q), L.m);
+    for (int k = 0; k < 3; ++k) R[k] = vm(acc[k], S);
+  }
+  b.R[mask] = R;
+  b.rh[mask] = 1;
+}
+
+static double brute_event_hel(int proc, const V4* p, int h) {
+  BGLine L = bg_line(proc);
+  Ext ex;
+  build_ext(proc, p, h, ex, -1, nullptr);
+  int n = (int)L.gl.size();
+  int full = (1 << n) - 1;
+  int ncol = 1;
+  for (int i = 0; i < n; ++i) ncol *= 8;
+  const double g = g_qcd();
+  double sum = 0;
+  for (int code = 0; code < ncol; ++code) {
+    Brute b;
+    b.L = &L; b.ex = &ex; b.n = n;
+    int x = code;
+    for (int i = 0; i < n; ++i) { b.ag[i] = x % 8; x /= 8; }
+    b.G.assign(1 << n, std::array<C4, 8>{});
+    b.GQ.assign(1 << n, V4{});
+    b.gh.assign(1 << n, 0);
+    for (int irow = 0; irow < 3; ++irow) {
+      b.R.assign(1 << n, std::array<C4, 3>{});
+      b.rh.assign(1 << n, 0);
+      cd M[3] = {0, 0, 0};
+      for (int sg = full; sg > 0; sg = (sg - 1) & full) {
+        int sr = full ^ sg;
+        brute_row(b, sr, irow);
+        brute_gluon(b, sg);
+        for (int c = 0; c < 8; ++c) {
+          const C4& G = b.G[sg][c];
+          if (G[0] == 0.0 && G[1] == 0.0 && G[2] == 0.0 && G[3] == 0.0) continue;
+          M4 gs = slash(scale(I * g, G));
+          for (int j = 0; j < 3; ++j) {
+            cd t = rc(vm(b.R[sr][j], gs), ex.w[L.col]);
+            for (int k = 0; k < 3; ++k) M[k] += TA[c][j][k] * t;
+          }
+        }
+      }
+      for (int k = 0; k < 3; ++k) sum += std::norm(M[k]);
+    }
+  }
+  return sum;
+}
+
+// ----------------------------------------------------------------------------
+// C ABI (test infrastructure)
+// ----------------------------------------------------------------------------
+extern "C" {
+
+int orc_nproc() { return NPROC; }
+
+const char* orc_proc_name(int proc) { return (proc >= 0 && proc < NPROC) ? PROCS[proc].name : nullptr; }
+
+void orc_set_params(double alpha, double alpha_s, double m_top) {
+  g_alpha = alpha; g_alpha_s = alpha_s; g_mt = m_top;
+}
+
+int orc_proc_info(int proc, int* npart, int* ncolour, double* avg, double* ident, int* a_pow, int* as_pow) {
+  if (proc < 0 || proc >= NPROC) return 1;
+  const ProcDef& P = PROCS[proc];
+  *npart = P.npart; *ncolour = P.ncolour; *avg = P.avg; *ident = P.ident;
+  *a_pow = P.a_pow; *as_pow = P.as_pow;
+  return 0;
+}
+
+// mom: [npart][4][ld] SoA; out[n]
+int orc_me2(int proc, int64_t n, int64_t ld, const double* mom, double* out, int nthreads) {
+  if (proc < 0 || proc >= NPROC) return 1;
+  init_colour();
+  const int np = PROCS[proc].npart;
+  parallel_for(n, nthreads, [&](int64_t e) {
+    V4 p[8];
+    load_event(mom, ld, e, np, p);
+    out[e] = me2_event(proc, p, nullptr);
+  });
+  return 0;
+}
+
+// per-helicity colour-summed values times the average: out[h * n + e]
+int orc_me2_hel(int proc, int64_t n, int64_t ld, const double* mom, double* out, int nthreads) {
+  if (proc < 0 || proc >= NPROC) return 1;
+  init_colour();
+  const int np = PROCS[proc].npart;
+  const int nh = 1 << np;
+  parallel_for(n, nthreads, [&](int64_t e) {
+    V4 p[8];
+    load_event(mom, ld, e, np, p);
+    std::vector<double> ph(nh);
+    me2_event(proc, p, ph.data());
+    for (int h = 0; h < nh; ++h) out[h * n + e] = ph[h];
+  });
+  return 0;
+}
+
+// colour-flow (or diagram) amplitude vector for one event (AoS p[npart][4]) and
+// helicity h; override_leg >= 0 replaces that vector leg's wavefunction by
+// ovec (4 complex as 8 doubles, upper index).  out: 2*ncolour doubles.
+int orc_flows(int proc, const double* p_aos, int h, int override_leg, const double* ovec, double* out) {
+  if (proc < 0 || proc >= NPROC) return 1;
+  init_colour();
+  const ProcDef& P = PROCS[proc];
+  V4 p[8];
+  for (int k = 0; k < P.npart; ++k) for (int mu = 0; mu < 4; ++mu) p[k].v[mu] = p_aos[k * 4 + mu];
+  C4 ov;
+  if (override_leg >= 0) for (int mu = 0; mu < 4; ++mu) ov[mu] = cd(ovec[2 * mu], ovec[2 * mu + 1]);
+  Ext ex;
+  build_ext(proc, p, h, ex, override_leg, &ov);
+  std::vector<cd> A(P.ncolour);
+  flows(proc, ex, A.data());
+  for (int i = 0; i < P.ncolour; ++i) { out[2 * i] = A[i].real(); out[2 * i + 1] = A[i].imag(); }
+  return 0;
+}
+
+// colour matrix of the amplitude vector (2*nc*nc doubles: re, im)
+int orc_colour_matrix(int proc, double* out) {
+  if (proc < 0 || proc >= NPROC) return 1;
+  init_colour();
+  const ColourData& c = COLOUR[proc];
+  for (int i = 0; i < c.nc * c.nc; ++i) { out[2 * i] = c.C[i].real(); out[2 * i + 1] = c.C[i].imag(); }
+  return 0;
+}
+
+// external wavefunction of leg k at helicity lam (+-1) for an event (AoS):
+// 8 doubles (4 complex).  Used by the wavefunction pins.
+int orc_wavefunction(int proc, const double* p_aos, int k, int lam, double* out) {
+  if (proc < 0 || proc >= NPROC) return 1;
+  init_colour();
+  const ProcDef& P = PROCS[proc];
+  V4 p[8];
+  for (int j = 0; j < P.npart; ++j) for (int mu = 0; mu < 4; ++mu) p[j].v[mu] = p_aos[j * 4 + mu];
+  int h = 0;
+  if (lam > 0) h |= 1 << (P.npart - 1 - k);
+  Ext ex;
+  build_ext(proc, p, h, ex, -1, nullptr);
+  for (int mu = 0; mu < 4; ++mu) { out[2 * mu] = ex.w[k][mu].real(); out[2 * mu + 1] = ex.w[k][mu].imag(); }
+  return 0;
+}
+
+// colour-dressed brute force: raw sum over colours for helicity h (h < 0: all
+// helicities), times the average factor.  gg processes only.
+int orc_me2_brute(int proc, int64_t n, int64_t ld, const double* mom, int h, double* out, int nthreads) {
+  if (proc != GG_TT && proc != GG_TTG && proc != GG_TTGG) return 1;
+  init_colour();
+  const int np = PROCS[proc].npart;
+  const int nh = 1 << np;
+  parallel_for(n, nthreads, [&](int64_t e) {
+    V4 p[8];
+    load_event(mom, ld, e, np, p);
+    double s = 0;
+    if (h >= 0) s = brute_event_hel(proc, p, h);
+    else for (int hh = 0; hh < nh; ++hh) s += brute_event_hel(proc, p, hh);
+    out[e] = s * PROCS[proc].avg;
+  });
+  return 0;
+}
+
+}  // extern "C"

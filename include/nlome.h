@@ -1,0 +1,127 @@
+/* nlome.h -- C ABI of the event-parallel tree-level matrix-element library
+ * for AMD MI355X (gfx950).
+ *
+ * The library evaluates, for large batches of phase-space points, the
+ * quantities the paper's branch-free NLO event loop (its second algorithm)
+ * needs at every point: tree-level squared matrix elements of Born and
+ * real-emission processes (helicity- and colour-summed |M|^2, the paper's
+ * Born and real equations) and, for real emissions, the FKS-subtracted
+ * real-minus-counterterm weight.  One event is one GPU lane.
+ *
+ * Conventions shared by every entry point
+ *  - All functions return nlo_status; none throws, aborts or exits.  On a
+ *    non-zero status nlo_last_error() describes the failure.
+ *  - Pointers named "device" are HIP device pointers owned by the caller
+ *    (e.g. torch.Tensor.data_ptr()); the library never frees them.
+ *  - Momenta are float64, GeV, structure of arrays:
+ *        mom[(ip * 4 + mu) * ld + e],   ip = particle, mu = 0:E 1:px 2:py 3:pz,
+ *    e = event in [0, n), ld >= n the leading dimension.  Incoming particles
+ *    come first, in the order of the process name, in their centre-of-mass
+ *    frame; then the outgoing particles in the order of the name.
+ *  - Evaluation calls are asynchronous on the given HIP stream (NULL = the
+ *    default stream); host-detectable argument errors return before any
+ *    launch.  n == 0 is a valid no-op.
+ *  - One context may be used from several threads; calls are serialised
+ *    internally.  Distinct contexts are independent.
+ */
+#ifndef NLOME_H
+#define NLOME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NLO_ABI_VERSION 1u
+
+typedef struct nlo_ctx nlo_ctx;   /* opaque, library-owned */
+
+typedef enum {
+  NLO_OK = 0,
+  NLO_EINVAL = 1,        /* bad argument (null pointer, n < 0, ld < n, ...) */
+  NLO_EPROC = 2,         /* unknown process id */
+  NLO_EDEVICE = 3,       /* HIP runtime error */
+  NLO_ENOMEM = 4,        /* device allocation failed */
+  NLO_EUNSUPPORTED = 5   /* valid but unsupported combination */
+} nlo_status;
+
+/* Arithmetic of the amplitude evaluation.  Inputs and outputs are always
+ * float64.  NLO_FP64: everything in double.  NLO_FP32: spinors, currents,
+ * vertices and the colour contraction in float; helicity-independent
+ * quantities (internal momenta, propagator denominators, external-state
+ * set-up) and the per-event helicity sum in double.  NLO_MIXED for |M|^2 is
+ * NLO_FP32 with the colour contraction on the matrix cores; for subtracted
+ * weights it routes events near soft/collinear limits to FP64. */
+typedef enum { NLO_FP64 = 0, NLO_FP32 = 1, NLO_FP16 = 2, NLO_BF16 = 3, NLO_MIXED = 4 } nlo_prec;
+
+/* Physics parameters: fixed couplings (no running), top mass, zero widths,
+ * all other masses zero; device = HIP device ordinal. */
+typedef struct {
+  double alpha;      /* e^2/(4 pi), e.g. 1/132.507 */
+  double alpha_s;    /* g_s^2/(4 pi), e.g. 0.118 */
+  double m_top;      /* GeV, e.g. 173 */
+  int device;
+} nlo_params;
+
+typedef struct {
+  const char* name;      /* e.g. "gg_ttg"; static storage */
+  int npart, ninitial;
+  int ncolour;           /* colour flows */
+  int nhel, ngood_hel;   /* helicity combinations, structurally non-zero ones */
+  int ndiagrams;         /* Feynman diagrams */
+  int nterms;            /* amplitude terms (a four-gluon diagram gives three) */
+  int ncurrents;         /* off-shell currents evaluated per helicity */
+  double avg_factor;     /* initial spin x colour average, applied by nlo_me2 */
+  double ident_factor;   /* identical final-state factor, NOT applied */
+  int gs_pow, e_pow;     /* |M|^2 is proportional to g_s^(2 gs_pow) e^(2 e_pow) */
+} nlo_proc_info;
+
+/* Kernel launch configuration of one (process, precision) pair. */
+typedef struct {
+  int block;        /* threads per block, multiple of 64, <= 1024 */
+  int colour_mode;  /* 0 = automatic, 1 = vector ALU, 2 = matrix cores (FP32 family only) */
+} nlo_kernel_config;
+
+uint32_t nlo_abi_version(void);
+
+/* Create a context on params->device; *out receives it.  Allocates nothing on
+ * the device beyond HIP's own context. */
+nlo_status nlo_create(nlo_ctx** out, const nlo_params* params);
+
+/* Destroy a context (NULL is a no-op).  Waits for nothing: the caller must
+ * have synchronised the streams it used. */
+nlo_status nlo_destroy(nlo_ctx* ctx);
+
+/* Thread-local description of the last failure on this thread; valid until
+ * the next call from the same thread.  Never NULL. */
+const char* nlo_last_error(void);
+
+/* Number of processes; ids are 0 .. n-1:
+ *   0 ee_mumu  e+e- -> mu+mu- (photon)     5 gg_ttg   g g -> t tbar g
+ *   1 ee_uu    e+e- -> u ubar (photon)     6 uu_ttg   u ubar -> t tbar g
+ *   2 ee_uug   e+e- -> u ubar g (photon)   7 ug_ttu   u g -> t tbar u
+ *   3 gg_tt    g g -> t tbar               8 gg_ttgg  g g -> t tbar g g
+ *   4 uu_tt    u ubar -> t tbar                                          */
+int nlo_num_processes(void);
+
+/* Static description of process proc_id. */
+nlo_status nlo_process_info(const nlo_ctx* ctx, int proc_id, nlo_proc_info* out);
+
+/* Override the launch configuration used for (proc_id, prec). */
+nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const nlo_kernel_config* cfg);
+nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec, nlo_kernel_config* cfg);
+
+/* Squared matrix elements (the paper's Born and real equations):
+ *   me2[e] = avg_factor * sum_{helicities} sum_{colours} |M(mom_e)|^2
+ * for e in [0, n).  mom: device, layout above, npart particles.  me2: device
+ * float64 [n].  prec: NLO_FP64, NLO_FP32 or NLO_MIXED.  Per-event values are
+ * written only; nothing is accumulated. */
+nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
+                   nlo_prec prec, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLOME_H */

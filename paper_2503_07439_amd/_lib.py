@@ -1,0 +1,118 @@
+"""ctypes binding of libnlome.so (include/nlome.h): same names, argument
+marshalling only.  Every step of the computation runs in the HIP kernels;
+there is no CPU fallback -- a missing library raises."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnlome.so")
+
+NLO_OK, NLO_EINVAL, NLO_EPROC, NLO_EDEVICE, NLO_ENOMEM, NLO_EUNSUPPORTED = range(6)
+NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED = range(5)
+PREC = {"fp64": NLO_FP64, "fp32": NLO_FP32, "fp16": NLO_FP16, "bf16": NLO_BF16, "mixed": NLO_MIXED}
+
+
+class nlo_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("alpha_s", ctypes.c_double), ("m_top", ctypes.c_double),
+                ("device", ctypes.c_int)]
+
+
+class nlo_proc_info(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("npart", ctypes.c_int), ("ninitial", ctypes.c_int),
+                ("ncolour", ctypes.c_int), ("nhel", ctypes.c_int), ("ngood_hel", ctypes.c_int),
+                ("ndiagrams", ctypes.c_int), ("nterms", ctypes.c_int), ("ncurrents", ctypes.c_int),
+                ("avg_factor", ctypes.c_double), ("ident_factor", ctypes.c_double),
+                ("gs_pow", ctypes.c_int), ("e_pow", ctypes.c_int)]
+
+
+class nlo_kernel_config(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("colour_mode", ctypes.c_int)]
+
+
+class NloError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("nlome status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+# exported symbols and their signatures (argtypes, restype)
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+SIGNATURES = {
+    "nlo_abi_version": ([], ctypes.c_uint32),
+    "nlo_create": ([ctypes.POINTER(_VP), ctypes.POINTER(nlo_params)], ctypes.c_int),
+    "nlo_destroy": ([_VP], ctypes.c_int),
+    "nlo_last_error": ([], ctypes.c_char_p),
+    "nlo_num_processes": ([], ctypes.c_int),
+    "nlo_process_info": ([_VP, ctypes.c_int, ctypes.POINTER(nlo_proc_info)], ctypes.c_int),
+    "nlo_set_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
+    "nlo_get_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
+    "nlo_me2": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libnlome.so is not built (run paper_2503_07439_amd.build or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != NLO_OK:
+        raise NloError(status, lib().nlo_last_error().decode())
+    return status
+
+
+# thin same-name wrappers ----------------------------------------------------
+def nlo_abi_version():
+    return lib().nlo_abi_version()
+
+
+def nlo_create(alpha=1.0 / 132.507, alpha_s=0.118, m_top=173.0, device=0):
+    ctx = _VP()
+    p = nlo_params(alpha, alpha_s, m_top, device)
+    check(lib().nlo_create(ctypes.byref(ctx), ctypes.byref(p)))
+    return ctx
+
+
+def nlo_destroy(ctx):
+    return check(lib().nlo_destroy(ctx))
+
+
+def nlo_last_error():
+    return lib().nlo_last_error().decode()
+
+
+def nlo_num_processes():
+    return lib().nlo_num_processes()
+
+
+def nlo_process_info(ctx, proc_id):
+    info = nlo_proc_info()
+    check(lib().nlo_process_info(ctx, proc_id, ctypes.byref(info)))
+    return info
+
+
+def nlo_set_kernel_config(ctx, proc_id, prec, block, colour_mode=0):
+    cfg = nlo_kernel_config(block, colour_mode)
+    return check(lib().nlo_set_kernel_config(ctx, proc_id, prec, ctypes.byref(cfg)))
+
+
+def nlo_get_kernel_config(ctx, proc_id, prec):
+    cfg = nlo_kernel_config()
+    check(lib().nlo_get_kernel_config(ctx, proc_id, prec, ctypes.byref(cfg)))
+    return cfg.block, cfg.colour_mode
+
+
+def nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr):
+    return check(lib().nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr))

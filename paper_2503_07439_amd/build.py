@@ -1,0 +1,81 @@
+"""Build step: regenerate the per-process HIP code and compile libnlome.so
+for gfx950 in-tree (one object per process and kernel variant, compiled in
+parallel, then linked)."""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libnlome.so")
+
+HIPCC_FLAGS = [
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+    # packed FP32 instructions are disabled on purpose (plain FP32 FMAs only)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
+]
+
+
+def _hipcc():
+    return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def generate():
+    sys.path.insert(0, ROOT)
+    from paper_2503_07439_amd import codegen
+    return codegen.generate(os.path.join(CSRC, "generated"))
+
+
+def _deps(src):
+    """Sources an object depends on: the unit, the shared headers and, for a
+    process unit, its generated header."""
+    deps = [src] + [os.path.join(CSRC, h) for h in ("helas.hpp", "kernels.hpp", "launch.hpp")]
+    deps.append(os.path.join(ROOT, "include", "nlome.h"))
+    base = os.path.basename(src)
+    if base.startswith("tu_"):
+        deps.append(os.path.join(os.path.dirname(src), base[3:].rsplit("_", 1)[0] + ".hpp"))
+    else:
+        deps.append(os.path.join(CSRC, "generated", "index.hpp"))
+    return deps
+
+
+def _compile(src, extra, verbose, force):
+    obj = os.path.join(OBJ, os.path.splitext(os.path.basename(src))[0] + ".o")
+    if not force and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if all(os.path.getmtime(d) <= t for d in _deps(src) if os.path.exists(d)):
+            return obj
+    cmd = [_hipcc()] + HIPCC_FLAGS + list(extra) + ["-c", "-o", obj, src]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr[-4000:]))
+    if verbose:
+        print("  built", os.path.basename(obj), flush=True)
+    return obj
+
+
+def build(verbose=True, extra_flags=(), jobs=None, force=True):
+    """Compile every unit (force=True) or only those older than their sources."""
+    tus = generate()
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = [os.path.join(CSRC, "capi.hip")] + list(tus)
+    # the largest process first so the long poles start early
+    srcs.sort(key=lambda p: 0 if "gg_ttgg" in p else (1 if "gg_ttg" in p else 2))
+    jobs = jobs or min(16, os.cpu_count() or 8)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, extra_flags, verbose, force), srcs))
+    tmp = LIB + ".tmp"
+    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("linked", LIB, flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(force="--incremental" not in sys.argv)

@@ -1,0 +1,890 @@
+"""Tree-level Feynman-diagram generator that emits the per-process HIP code of
+the GPU path (build-time only; not used at run time).
+
+The paper's Born and real-emission equations define a tree amplitude as the
+sum of Feynman diagrams, |M|^2 as its absolute square summed over helicities
+and colours.  For every process this module:
+
+1. enumerates the tree diagrams of a QCD+QED model (Feynman gauge, quark-
+   gluon / fermion-photon / three-gluon / four-gluon vertices, the four-gluon
+   vertex split into its three colour structures), sharing every off-shell
+   sub-current between the diagrams that contain it;
+2. computes each diagram's colour factor numerically from explicit SU(3)
+   generators and projects it on the colour-flow basis (strings of generators
+   along the quark lines), giving exact rational complex coefficients;
+3. builds the colour matrix of that basis and its Cholesky factor;
+4. finds the helicity combinations that are not identically zero by the
+   chirality of massless fermion lines;
+5. emits straight-line HIP device code: a helicity-independent FP64 prologue
+   (internal momenta, propagator denominators, external-state data) and a
+   per-helicity body that evaluates every sub-current once and accumulates
+   the flow vector J.
+
+Conventions: all particles are treated as incoming; an outgoing particle is
+an incoming antiparticle with momentum -p.  Vertex rules are those of
+Peskin-Schroeder (quark-gluon i g gamma^mu T^a, fermion-photon -i e Q gamma^mu,
+three-gluon g f^{abc} V_{mu nu rho}, four-gluon -i g^2 sum f f (g g - g g),
+propagators i(pslash+m)/(p^2-m^2) and -i g_{mu nu}/p^2).  Coupling
+magnitudes and the factors of i are tracked symbolically and folded into the
+colour coefficients and one overall FP64 factor, so the device routines
+carry neither.
+"""
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# model
+# ---------------------------------------------------------------------------
+FERMIONS = {  # name: (mass symbol, charge, coloured)
+    "t": ("MT", Fraction(2, 3), True),
+    "u": ("0", Fraction(2, 3), True),
+    "e-": ("0", Fraction(-1), False),
+    "mu-": ("0", Fraction(-1), False),
+}
+ANTI = {"t": "t~", "u": "u~", "e-": "e+", "mu-": "mu+"}
+ANTI.update({v: k for k, v in list(ANTI.items())})
+ANTI["g"] = "g"
+ANTI["a"] = "a"
+
+
+def is_fermion(t):
+    return t in FERMIONS
+
+
+def is_antifermion(t):
+    return t in ANTI and ANTI[t] in FERMIONS
+
+
+def flavour(t):
+    return t if is_fermion(t) else ANTI[t]
+
+
+def coloured(t):
+    if t == "g":
+        return True
+    if t == "a":
+        return False
+    return FERMIONS[flavour(t)][2]
+
+
+def cdim(t):
+    if t == "g":
+        return 8
+    if t == "a":
+        return 1
+    return 3 if coloured(t) else 1
+
+
+# ---------------------------------------------------------------------------
+# SU(3), built here from the Gell-Mann matrices
+# ---------------------------------------------------------------------------
+def _su3():
+    T = np.zeros((8, 3, 3), complex)
+    T[0][0, 1] = T[0][1, 0] = 0.5
+    T[1][0, 1], T[1][1, 0] = -0.5j, 0.5j
+    T[2][0, 0], T[2][1, 1] = 0.5, -0.5
+    T[3][0, 2] = T[3][2, 0] = 0.5
+    T[4][0, 2], T[4][2, 0] = -0.5j, 0.5j
+    T[5][1, 2] = T[5][2, 1] = 0.5
+    T[6][1, 2], T[6][2, 1] = -0.5j, 0.5j
+    T[7] = np.diag([1.0, 1.0, -2.0]) / (2.0 * math.sqrt(3.0))
+    # [T^a, T^b] = i f^{abc} T^c  and Tr(T^c T^d) = delta/2
+    comm = np.einsum('aij,bjk->abik', T, T) - np.einsum('bij,ajk->abik', T, T)
+    f = np.real(-2j * np.einsum('abik,cki->abc', comm, T))
+    f[np.abs(f) < 1e-14] = 0.0
+    return T, f
+
+
+TGEN, FSTR = _su3()
+
+
+# ---------------------------------------------------------------------------
+# diagram enumeration
+# ---------------------------------------------------------------------------
+class Node:
+    """An external wavefunction or an off-shell sub-current."""
+
+    def __init__(self, kind, legs, ptype, children=(), phase=0, qfac=Fraction(1), ncoup=(0, 0)):
+        self.kind = kind
+        self.legs = frozenset(legs)
+        self.ptype = ptype
+        self.children = list(children)
+        self.phase = phase      # power of i
+        self.qfac = qfac        # product of electric charges
+        self.ncoup = ncoup      # (powers of g_s, powers of e)
+        self.ctens = None
+        self.caxes = None
+        self.id = None
+        self.mass = "0"
+        self.boson = None
+
+
+class Amp:
+    """One diagram amplitude (a four-gluon diagram gives three, one per colour structure)."""
+
+    def __init__(self, kind, children, phase, qfac, ncoup, diagram):
+        self.kind = kind
+        self.children = children
+        self.phase = phase
+        self.qfac = qfac
+        self.ncoup = ncoup
+        self.diagram = diagram
+        self.ctens = None
+        self.coef = None
+        self.boson = None
+
+
+def _vertex_bosons(ptype, bosons):
+    """Vector bosons that couple to fermion flavour ptype in the model."""
+    out = []
+    f = flavour(ptype)
+    if "g" in bosons and FERMIONS[f][2]:
+        out.append("g")
+    if "a" in bosons:
+        out.append("a")
+    return out
+
+
+class Process:
+    def __init__(self, name, incoming, outgoing, bosons, avg, ident=1.0):
+        self.name = name
+        self.incoming = list(incoming)
+        self.outgoing = list(outgoing)
+        self.bosons = bosons
+        self.avg = avg
+        self.ident = ident
+        self.phys = self.incoming + self.outgoing
+        self.npart = len(self.phys)
+        # all-incoming particle type of every leg
+        self.itype = [p for p in self.incoming] + [ANTI[p] for p in self.outgoing]
+        self.memo = {}
+        self.nodes = []
+        self.amps = []
+        self.ndiagrams = 0
+
+    # -- enumeration ---------------------------------------------------------
+    def _ext(self, k):
+        key = (frozenset([k]), self.itype[k])
+        if key not in self.memo:
+            n = Node("ext", [k], self.itype[k])
+            t = self.itype[k]
+            n.mass = FERMIONS[flavour(t)][0] if t not in ("g", "a") else "0"
+            self.memo[key] = [n]
+        return self.memo[key]
+
+    def subtrees(self, S, X):
+        """All distinct sub-currents over leg set S whose off-shell line enters
+        its parent vertex as an incoming particle of type X."""
+        S = frozenset(S)
+        key = (S, X)
+        if key in self.memo:
+            return self.memo[key]
+        if len(S) == 1:
+            (k,) = tuple(S)
+            res = self._ext(k) if self.itype[k] == X else []
+            self.memo[key] = res
+            return res
+        res = []
+        items = sorted(S)
+        subsets = [frozenset(c) for r in range(1, len(items)) for c in itertools.combinations(items, r)]
+        if X in ("g", "a"):
+            # fermion pair -> vector
+            for f in FERMIONS:
+                if X not in _vertex_bosons(f, self.bosons):
+                    continue
+                for S1 in subsets:
+                    S2 = S - S1
+                    for r in self.subtrees(S1, ANTI[f]):
+                        for c in self.subtrees(S2, f):
+                            res.append(self._mk("ffv_vec", S, X, [r, c], boson=X, flav=f))
+            if X == "g" and "g" in self.bosons:
+                lo = min(items)
+                for S1 in subsets:
+                    if lo not in S1:
+                        continue
+                    S2 = S - S1
+                    for a in self.subtrees(S1, "g"):
+                        for b in self.subtrees(S2, "g"):
+                            res.append(self._mk("vvv_vec", S, X, [a, b]))
+                for parts in _three_partitions(items):
+                    A = self.subtrees(parts[0], "g")
+                    B = self.subtrees(parts[1], "g")
+                    C = self.subtrees(parts[2], "g")
+                    for a in A:
+                        for b in B:
+                            for c in C:
+                                for k in range(3):
+                                    res.append(self._mk("vvvv_vec%d" % k, S, X, [a, b, c]))
+        elif is_fermion(X):
+            # column current: this vertex sees it in the row slot; children column + vector
+            for V in _vertex_bosons(X, self.bosons):
+                for S1 in subsets:
+                    S2 = S - S1
+                    for c in self.subtrees(S1, X):
+                        for v in self.subtrees(S2, V):
+                            res.append(self._mk("ffv_col", S, X, [c, v], boson=V, flav=X))
+        else:
+            f = flavour(X)
+            for V in _vertex_bosons(f, self.bosons):
+                for S1 in subsets:
+                    S2 = S - S1
+                    for r in self.subtrees(S1, X):
+                        for v in self.subtrees(S2, V):
+                            res.append(self._mk("ffv_row", S, X, [r, v], boson=V, flav=f))
+        self.memo[key] = res
+        return res
+
+    def _mk(self, kind, S, X, ch, boson=None, flav=None):
+        n = Node(kind, S, X, ch)
+        ph = sum(c.phase for c in ch)
+        q = Fraction(1)
+        gs = sum(c.ncoup[0] for c in ch)
+        ee = sum(c.ncoup[1] for c in ch)
+        for c in ch:
+            q *= c.qfac
+        if kind.startswith("ffv"):
+            if boson == "g":
+                ph += 1          # vertex i g
+                gs += 1
+            else:
+                ph += 3          # vertex -i e Q
+                ee += 1
+                q *= FERMIONS[flav][1]
+            if kind == "ffv_vec":
+                ph += 3          # vector propagator -i
+            else:
+                ph += 1          # fermion propagator i
+                n.mass = FERMIONS[flav][0]
+        elif kind == "vvv_vec":
+            ph += 3              # vertex g (no i), propagator -i
+            gs += 1
+        else:                    # four-gluon: vertex -i g^2, propagator -i
+            ph += 3 + 3
+            gs += 2
+        n.phase = ph % 4
+        n.qfac = q
+        n.ncoup = (gs, ee)
+        n.boson = boson
+        return n
+
+    def enumerate(self):
+        root = self.npart - 1
+        X = self.itype[root]
+        rest = frozenset(range(self.npart - 1))
+        items = sorted(rest)
+        subsets = [frozenset(c) for r in range(1, len(items)) for c in itertools.combinations(items, r)]
+        L = self._ext(root)[0]
+        amps = []
+        diag = 0
+
+        def add(kind, ch, boson=None, flav=None):
+            nonlocal diag
+            ph = sum(c.phase for c in ch) + L.phase
+            q = Fraction(1)
+            gs = sum(c.ncoup[0] for c in ch)
+            ee = sum(c.ncoup[1] for c in ch)
+            for c in ch:
+                q *= c.qfac
+            if kind.startswith("ffv"):
+                if boson == "g":
+                    ph += 1
+                    gs += 1
+                else:
+                    ph += 3
+                    ee += 1
+                    q *= FERMIONS[flav][1]
+            elif kind == "vvv_amp":
+                gs += 1
+            else:
+                ph += 3
+                gs += 2
+            a = Amp(kind, list(ch) + [L], ph % 4, q, (gs, ee), diag)
+            a.boson = boson
+            amps.append(a)
+
+        if X in ("g", "a"):
+            for f in FERMIONS:
+                if X not in _vertex_bosons(f, self.bosons):
+                    continue
+                for S1 in subsets:
+                    for r in self.subtrees(S1, ANTI[f]):
+                        for c in self.subtrees(rest - S1, f):
+                            add("ffv_amp", [r, c], boson=X, flav=f)
+                            diag += 1
+            if X == "g" and "g" in self.bosons:
+                lo = min(items)
+                for S1 in subsets:
+                    if lo not in S1:
+                        continue
+                    for a in self.subtrees(S1, "g"):
+                        for b in self.subtrees(rest - S1, "g"):
+                            add("vvv_amp", [a, b])
+                            diag += 1
+                for parts in _three_partitions(items):
+                    for a in self.subtrees(parts[0], "g"):
+                        for b in self.subtrees(parts[1], "g"):
+                            for c in self.subtrees(parts[2], "g"):
+                                for k in range(3):
+                                    add("vvvv_amp%d" % k, [a, b, c])
+                                diag += 1
+        elif is_fermion(X):
+            # root is a column spinor: children row + vector
+            for V in _vertex_bosons(X, self.bosons):
+                for S1 in subsets:
+                    for r in self.subtrees(S1, ANTI[X]):
+                        for v in self.subtrees(rest - S1, V):
+                            a = [r, v]
+                            add("ffv_amp_rootcol", a, boson=V, flav=X)
+                            diag += 1
+        else:
+            f = flavour(X)
+            for V in _vertex_bosons(f, self.bosons):
+                for S1 in subsets:
+                    for c in self.subtrees(S1, f):
+                        for v in self.subtrees(rest - S1, V):
+                            add("ffv_amp_rootrow", [c, v], boson=V, flav=f)
+                            diag += 1
+        self.amps = amps
+
+        # Feynman-diagram count: a four-gluon vertex contributes three colour
+        # structures (three terms) but is one diagram
+        def sig(n):
+            if n.kind == "ext":
+                return ("e", min(n.legs))
+            k = "vvvv" if n.kind.startswith("vvvv") else n.kind
+            return (k,) + tuple(sig(c) for c in n.children)
+
+        self.ndiagrams = len({sig(Node(a.kind, [], None, a.children)) for a in amps})
+        # collect nodes in dependency order
+        order = []
+        seen = set()
+
+        def visit(n):
+            if id(n) in seen:
+                return
+            for c in n.children:
+                visit(c)
+            seen.add(id(n))
+            order.append(n)
+
+        for a in amps:
+            for c in a.children:
+                visit(c)
+        for i, n in enumerate(order):
+            n.id = i
+        self.nodes = order
+        return self
+
+    # -- colour ---------------------------------------------------------------
+    def coloured_legs(self):
+        return [k for k in range(self.npart) if coloured(self.itype[k])]
+
+    def colour(self):
+        legs = self.coloured_legs()
+        pos = {k: i for i, k in enumerate(legs)}
+        dims = [cdim(self.itype[k]) for k in legs]
+        full_shape = tuple(dims)
+
+        def expand(n):
+            """Colour tensor of node n over (its coloured external legs, off-shell axis)."""
+            if n.ctens is not None:
+                return n.ctens, n.caxes
+            if n.kind == "ext":
+                t = n.ptype
+                if coloured(t):
+                    n.ctens, n.caxes = np.eye(cdim(t), dtype=complex), [min(n.legs), None]
+                else:
+                    n.ctens, n.caxes = np.ones((), complex), []
+                return n.ctens, n.caxes
+            ch = [expand(c) for c in n.children]
+            n.ctens, n.caxes = _combine(n.kind, n.children, ch, n.boson)
+            return n.ctens, n.caxes
+
+        for a in self.amps:
+            ch = [expand(c) for c in a.children]
+            t, axes = _combine(a.kind, a.children, ch, a.boson)
+            # reorder to the canonical leg order
+            if axes:
+                perm = [axes.index(k) for k in legs]
+                t = np.transpose(t, perm)
+            a.ctens = t.reshape(full_shape) if legs else t.reshape(())
+        # flow basis
+        self.flows = _flow_basis(self)
+        B = np.array([b.ravel() for b in self.flows])
+        self.colour_matrix = np.real(np.conj(B) @ B.T)
+        assert np.allclose(np.imag(np.conj(B) @ B.T), 0, atol=1e-12)
+        for a in self.amps:
+            d = a.ctens.ravel()
+            c, res, rank, _ = np.linalg.lstsq(B.T, d, rcond=None)
+            assert np.allclose(B.T @ c, d, atol=1e-12), (self.name, a.kind)
+            a.coef = [_crational(x) for x in c]
+        self.colour_matrix = np.array([[float(Fraction(x).limit_denominator(10000)) for x in row]
+                                       for row in self.colour_matrix])
+        return self
+
+    # -- helicities -------------------------------------------------------------
+    def good_helicities(self):
+        """Helicity combinations not identically zero: on every massless
+        fermion line the row and column spinors must sit in opposite chiral
+        blocks (an odd number of gamma matrices connects them)."""
+        lines = []
+        for k in range(self.npart):
+            t = self.itype[k]
+            if is_antifermion(t) and FERMIONS[flavour(t)][0] == "0":
+                cols = [j for j in range(self.npart) if self.itype[j] == flavour(t)]
+                assert len(cols) == 1
+                lines.append((k, cols[0]))
+        good = []
+        for h in range(1 << self.npart):
+            lam = [1 if (h >> (self.npart - 1 - k)) & 1 else -1 for k in range(self.npart)]
+            ok = True
+            for r, c in lines:
+                out_r = r >= len(self.incoming)     # row is an outgoing fermion (ubar) or incoming antifermion (vbar)
+                rb = (1 if lam[r] > 0 else 2) if out_r else (2 if lam[r] > 0 else 1)
+                out_c = c >= len(self.incoming)     # column is an outgoing antifermion (v) or incoming fermion (u)
+                cb = (1 if lam[c] > 0 else 2) if out_c else (2 if lam[c] > 0 else 1)
+                if rb == cb:
+                    ok = False
+            if ok:
+                good.append(h)
+        return good
+
+    def coupling_powers(self):
+        p = {a.ncoup for a in self.amps}
+        assert len(p) == 1, p
+        return p.pop()
+
+
+def _three_partitions(items):
+    """Unordered partitions of items into three nonempty blocks (canonical:
+    blocks ordered by their smallest element)."""
+    out = []
+    n = len(items)
+    for labels in itertools.product(range(3), repeat=n):
+        blocks = [frozenset(items[i] for i in range(n) if labels[i] == b) for b in range(3)]
+        if any(len(b) == 0 for b in blocks):
+            continue
+        mins = [min(b) for b in blocks]
+        if mins[0] < mins[1] < mins[2]:
+            out.append(blocks)
+    return out
+
+
+def _combine(kind, children, ch, boson):
+    """Contract the children's colour tensors with the vertex colour factor.
+    Each child tensor has its external axes (labelled by leg) and, last, its
+    off-shell axis.  Returns (tensor, axis labels) where the off-shell axis
+    (if any) is last and labelled None."""
+    letters = iter("abcdefghijklmnopqrstuvwxyz")
+    ext_axes = []
+    specs = []
+    ops = []
+    offs = []
+    for (t, axes), c in zip(ch, children):
+        s = ""
+        for ax in axes:
+            if ax is None:
+                continue
+            L = next(letters)
+            s += L
+            ext_axes.append((ax, L))
+        if t.ndim > len([a for a in axes if a is not None]):
+            o = next(letters)
+            s += o
+            offs.append(o)
+        else:
+            offs.append(None)
+        specs.append(s)
+        ops.append(t)
+    out_off = next(letters)
+    vs = ""
+    vops = []
+    k = kind
+    if k in ("ffv_vec", "ffv_col", "ffv_row", "ffv_amp", "ffv_amp_rootcol", "ffv_amp_rootrow"):
+        # slots: row index i, column index j, gluon a ; photon: delta_ij
+        if k == "ffv_vec":
+            r, c = offs
+            if boson == "g":
+                vs, vops, off = "%s%s%s" % (out_off, r, c), [TGEN], out_off   # T^a_{ij}
+            elif r:
+                vs, vops, off = "%s%s" % (r, c), [np.eye(3)], None
+            else:
+                vs, vops, off = "", [], None
+        elif k == "ffv_col":          # children: column c, vector v ; result index = row slot
+            c, v = offs
+            if boson == "g":
+                vs, vops, off = "%s%s%s" % (v, out_off, c), [TGEN], out_off
+            else:
+                if c:
+                    vs, vops, off = "%s%s" % (out_off, c), [np.eye(3)], out_off
+                else:
+                    vs, vops, off = "", [], None
+        elif k == "ffv_row":          # children: row r, vector v ; result index = column slot
+            r, v = offs
+            if boson == "g":
+                vs, vops, off = "%s%s%s" % (v, r, out_off), [TGEN], out_off
+            else:
+                if r:
+                    vs, vops, off = "%s%s" % (r, out_off), [np.eye(3)], out_off
+                else:
+                    vs, vops, off = "", [], None
+        else:
+            # amplitude: children (row, col, vector) in some order
+            if k == "ffv_amp":
+                r, c, v = offs[0], offs[1], offs[2]
+            elif k == "ffv_amp_rootcol":
+                r, v, c = offs[0], offs[1], offs[2]
+            else:
+                c, v, r = offs[0], offs[1], offs[2]
+            if boson == "g":
+                vs, vops = "%s%s%s" % (v, r, c), [TGEN]
+            else:
+                vs, vops = ("%s%s" % (r, c), [np.eye(3)]) if r else ("", [])
+            off = None
+    elif k in ("vvv_vec", "vvv_amp"):
+        a, b = offs[0], offs[1]
+        if k == "vvv_vec":
+            vs, vops, off = "%s%s%s" % (a, b, out_off), [FSTR], out_off
+        else:
+            vs, vops, off = "%s%s%s" % (a, b, offs[2]), [FSTR], None
+    else:
+        idx = int(k[-1])
+        a, b, c = offs[0], offs[1], offs[2]
+        d = out_off if "vec" in k else offs[3]
+        e = next(letters)
+        F = FSTR
+        if idx == 0:
+            vs = "%s%s%s,%s%s%s" % (a, b, e, c, d, e)
+        elif idx == 1:
+            vs = "%s%s%s,%s%s%s" % (a, c, e, b, d, e)
+        else:
+            vs = "%s%s%s,%s%s%s" % (a, d, e, b, c, e)
+        vops = [F, F]
+        off = out_off if "vec" in k else None
+    out_spec = "".join(L for _, L in ext_axes) + (off or "")
+    all_specs = [s for s in specs]
+    all_ops = list(ops)
+    if vs:
+        all_specs += vs.split(",")
+        all_ops += vops
+    t = np.einsum(",".join(all_specs) + "->" + out_spec, *all_ops, optimize=True)
+    axes = [ax for ax, _ in ext_axes] + ([None] if off else [])
+    return t, axes
+
+
+def _flow_basis(proc):
+    """Colour-flow basis: for every pairing of row-type and column-type
+    coloured external quarks, and every distribution of the external gluons
+    into ordered strings along those pairings, the product of generator
+    strings.  Returns tensors over the coloured legs in leg order."""
+    legs = proc.coloured_legs()
+    if not legs:
+        return [np.ones(())]
+    rows = [k for k in legs if is_antifermion(proc.itype[k])]
+    cols = [k for k in legs if is_fermion(proc.itype[k])]
+    gls = [k for k in legs if proc.itype[k] == "g"]
+    letter = {k: chr(ord("a") + i) for i, k in enumerate(legs)}
+    out_spec = "".join(letter[k] for k in legs)
+    basis = []
+    nl = len(rows)
+    for pairing in itertools.permutations(cols):
+        for assign in itertools.product(range(nl), repeat=len(gls)):
+            groups = [[g for g, a in zip(gls, assign) if a == l] for l in range(nl)]
+            for orders in itertools.product(*[list(itertools.permutations(gr)) for gr in groups]):
+                specs, ops = [], []
+                extra = iter("zyxwvutsrq")
+                for l in range(nl):
+                    seq = list(orders[l])
+                    if not seq:
+                        specs.append(letter[rows[l]] + letter[pairing[l]])
+                        ops.append(np.eye(3))
+                        continue
+                    prev = letter[rows[l]]
+                    for j, g in enumerate(seq):
+                        nxt = letter[pairing[l]] if j == len(seq) - 1 else next(extra)
+                        specs.append(letter[g] + prev + nxt)
+                        ops.append(TGEN)
+                        prev = nxt
+                basis.append(np.einsum(",".join(specs) + "->" + out_spec, *ops, optimize=True))
+    return basis
+
+
+def _crational(x):
+    r = Fraction(float(np.real(x))).limit_denominator(2000)
+    i = Fraction(float(np.imag(x))).limit_denominator(2000)
+    assert abs(float(r) - np.real(x)) < 1e-12 and abs(float(i) - np.imag(x)) < 1e-12, x
+    return (r, i)
+
+
+# ---------------------------------------------------------------------------
+# process list
+# ---------------------------------------------------------------------------
+def process_list():
+    return [
+        Process("ee_mumu", ["e-", "e+"], ["mu-", "mu+"], {"a"}, 0.25),
+        Process("ee_uu", ["e-", "e+"], ["u", "u~"], {"a"}, 0.25),
+        Process("ee_uug", ["e-", "e+"], ["u", "u~", "g"], {"a", "g"}, 0.25),
+        Process("gg_tt", ["g", "g"], ["t", "t~"], {"g"}, 1.0 / 256.0),
+        Process("uu_tt", ["u", "u~"], ["t", "t~"], {"g"}, 1.0 / 36.0),
+        Process("gg_ttg", ["g", "g"], ["t", "t~", "g"], {"g"}, 1.0 / 256.0),
+        Process("uu_ttg", ["u", "u~"], ["t", "t~", "g"], {"g"}, 1.0 / 36.0),
+        Process("ug_ttu", ["u", "g"], ["t", "t~", "u"], {"g"}, 1.0 / 96.0),
+        Process("gg_ttgg", ["g", "g"], ["t", "t~", "g", "g"], {"g"}, 1.0 / 256.0, ident=0.5),
+    ]
+
+
+# ---------------------------------------------------------------------------
+# HIP emission
+# ---------------------------------------------------------------------------
+def _cplx_lit(fr):
+    return "%.17g" % float(fr)
+
+
+def _phase_coef(coef, phase, qfac):
+    """coef (re, im) * i^phase * qfac as a complex Fraction pair."""
+    re, im = coef
+    for _ in range(phase % 4):
+        re, im = -im, re
+    return (re * qfac, im * qfac)
+
+
+def _acc_code(J, c, a):
+    """J += c * a for a rational complex constant c."""
+    re, im = c
+    out = []
+    if re == 0 and im == 0:
+        return out
+    def term(k, x):
+        if k == 1:
+            return " + " + x
+        if k == -1:
+            return " - " + x
+        return " + T(%s) * %s" % (_cplx_lit(k), x)
+    if im == 0:
+        out.append("%s.r = %s.r%s;" % (J, J, term(re, a + ".r")))
+        out.append("%s.i = %s.i%s;" % (J, J, term(re, a + ".i")))
+    elif re == 0:
+        out.append("%s.r = %s.r%s;" % (J, J, term(-im, a + ".i")))
+        out.append("%s.i = %s.i%s;" % (J, J, term(im, a + ".r")))
+    else:
+        out.append("%s.r = %s.r%s%s;" % (J, J, term(re, a + ".r"), term(-im, a + ".i")))
+        out.append("%s.i = %s.i%s%s;" % (J, J, term(re, a + ".i"), term(im, a + ".r")))
+    return out
+
+
+def cholesky_lower(C):
+    return np.linalg.cholesky(C)
+
+
+def emit_process(p):
+    """HIP source for one process (a struct with static device functions)."""
+    good = p.good_helicities()
+    gs, ee = p.coupling_powers()
+    nflow = len(p.flows)
+    N = p.npart
+    nin = len(p.incoming)
+    # momentum slots: one per distinct leg set
+    msets = []
+    for n in p.nodes:
+        if n.legs not in msets:
+            msets.append(n.legs)
+    root = p.npart - 1
+    if frozenset([root]) not in msets:
+        msets.append(frozenset([root]))
+    mslot = {s: i for i, s in enumerate(msets)}
+    # denominators: internal nodes by (leg set, mass)
+    dens = []
+    for n in p.nodes:
+        if n.kind == "ext":
+            continue
+        key = (n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")
+        if key not in dens:
+            dens.append(key)
+    dslot = {k: i for i, k in enumerate(dens)}
+    L = []
+    nm = p.name
+    L.append("// %s: %d diagrams, %d amplitude terms, %d off-shell currents, %d colour flows, %d/%d helicities"
+             % (nm, p.ndiagrams, len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), nflow,
+                len(good), 1 << N))
+    L.append("static __constant__ unsigned char %s_good[%d] = {%s};" % (nm, len(good), ", ".join(str(h) for h in good)))
+    L.append("struct %s {" % nm)
+    L.append("  static constexpr int NPART = %d, NIN = %d, NFLOW = %d, NHEL = %d, NGOOD = %d;" % (N, nin, nflow, 1 << N, len(good)))
+    L.append("  static constexpr int NDIAG = %d, NTERM = %d, NCUR = %d, GS_POW = %d, E_POW = %d;"
+             % (p.ndiagrams, len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee))
+    L.append("  static constexpr double AVG = %.17g, IDENT = %.17g;" % (p.avg, p.ident))
+    L.append("  static constexpr int NMOM = %d, NDEN = %d;" % (len(msets), len(dens)))
+    L.append("  static constexpr const char* NAME = \"%s\";" % nm)
+    L.append("  __device__ static int good(int i) { return %s_good[i]; }" % nm)
+    # per-event data
+    L.append("  template <class T> struct Pre {")
+    L.append("    r4<T> Q[NMOM];")
+    L.append("    T den[NDEN];")
+    for k in range(N):
+        t = p.itype[k]
+        if t in ("g", "a"):
+            L.append("    vec_data<T> x%d;" % k)
+        else:
+            L.append("    ferm_data<T> x%d;" % k)
+    L.append("  };")
+    # prologue
+    L.append("  template <class T> NLO_HD static void prologue(const double (&p)[NPART][4], Pre<T>& s, double mt) {")
+    L.append("    double q[NPART][4];")
+    for k in range(N):
+        sgn = "" if k < nin else "-"
+        L.append("    for (int m = 0; m < 4; ++m) q[%d][m] = %sp[%d][m];" % (k, sgn, k))
+    for k in range(N):
+        t = p.itype[k]
+        if t in ("g", "a"):
+            L.append("    { vec_data<double> d; vec_setup(p[%d], d); s.x%d = cast<T>(d); }" % (k, k))
+        else:
+            mass = FERMIONS[flavour(t)][0]
+            L.append("    { ferm_data<double> d; ferm_setup(p[%d], %s, d); s.x%d = cast<T>(d); }"
+                     % (k, "mt" if mass == "MT" else "0.0", k))
+    for S, i in mslot.items():
+        legs = sorted(S)
+        expr = " + ".join("q[%d][m]" % k for k in legs)
+        L.append("    { double Q[4]; for (int m = 0; m < 4; ++m) Q[m] = %s;" % expr)
+        L.append("      for (int m = 0; m < 4; ++m) s.Q[%d].v[m] = T(Q[m]);" % i)
+        for (S2, mass), j in dslot.items():
+            if S2 == S:
+                mterm = " - mt * mt" if mass == "MT" else ""
+                L.append("      s.den[%d] = T(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]%s)); }"
+                         % (j, mterm) if False else
+                         "      s.den[%d] = T(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]%s));"
+                         % (j, mterm))
+        L.append("    }")
+    L.append("  }")
+    # amplitudes for one helicity
+    L.append("  template <class T> NLO_HD static void amplitudes(const Pre<T>& s, int h, T mt, cx<T> (&J)[NFLOW]) {")
+    L.append("    for (int f = 0; f < NFLOW; ++f) J[f] = czero<T>();")
+    for n in p.nodes:
+        v = "v%d" % n.id
+        if n.kind == "ext":
+            k = min(n.legs)
+            bit = "((h >> %d) & 1)" % (N - 1 - k)
+            t = n.ptype
+            out = k >= nin
+            if t in ("g", "a"):
+                L.append("    const w4<T> %s = wf_eps(s.x%d, %s, %s);" % (v, k, bit, "true" if out else "false"))
+            elif is_fermion(t):
+                # column spinor: incoming fermion u(p) or outgoing antifermion v(p)
+                fn = "wf_v" if out else "wf_u"
+                L.append("    const w4<T> %s = %s(s.x%d, %s);" % (v, fn, k, bit))
+            else:
+                # row spinor: outgoing fermion ubar(p) or incoming antifermion vbar(p)
+                fn = "wf_u" if out else "wf_v"
+                L.append("    const w4<T> %s = wf_bar(%s(s.x%d, %s));" % (v, fn, k, bit))
+            continue
+        ch = ["v%d" % c.id for c in n.children]
+        Q = "s.Q[%d]" % mslot[n.legs]
+        dkey = (n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")
+        D = "s.den[%d]" % dslot[dkey]
+        if n.kind == "ffv_vec":
+            L.append("    const w4<T> %s = ffv_vec(%s, %s, %s);" % (v, ch[0], ch[1], D))
+        elif n.kind in ("ffv_col", "ffv_row"):
+            if n.mass == "MT":
+                L.append("    const w4<T> %s = %s(%s, %s, %s, %s, mt);" % (v, n.kind, ch[0], ch[1], Q, D))
+            else:
+                L.append("    const w4<T> %s = %s0(%s, %s, %s, %s);" % (v, n.kind, ch[0], ch[1], Q, D))
+        elif n.kind == "vvv_vec":
+            QA = "s.Q[%d]" % mslot[n.children[0].legs]
+            QB = "s.Q[%d]" % mslot[n.children[1].legs]
+            L.append("    const w4<T> %s = vvv_vec(%s, %s, %s, %s, %s);" % (v, ch[0], QA, ch[1], QB, D))
+        else:
+            L.append("    const w4<T> %s = %s(%s, %s, %s, %s);" % (v, n.kind, ch[0], ch[1], ch[2], D))
+    for i, a in enumerate(p.amps):
+        ch = ["v%d" % c.id for c in a.children]
+        av = "a%d" % i
+        if a.kind == "ffv_amp":
+            L.append("    const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[0], ch[2], ch[1]))
+        elif a.kind == "ffv_amp_rootcol":
+            L.append("    const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[0], ch[1], ch[2]))
+        elif a.kind == "ffv_amp_rootrow":
+            L.append("    const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[2], ch[1], ch[0]))
+        elif a.kind == "vvv_amp":
+            Qs = ["s.Q[%d]" % mslot[c.legs] for c in a.children]
+            L.append("    const cx<T> %s = vvv_amp(%s, %s, %s, %s, %s, %s);" % (av, ch[0], Qs[0], ch[1], Qs[1], ch[2], Qs[2]))
+        else:
+            L.append("    const cx<T> %s = %s(%s, %s, %s, %s);" % (av, a.kind, ch[0], ch[1], ch[2], ch[3]))
+        for f in range(nflow):
+            c = _phase_coef(a.coef[f], a.phase, a.qfac)
+            for line in _acc_code("J[%d]" % f, c, av):
+                L.append("    " + line)
+    L.append("  }")
+    # colour sum: J^dagger C J = |L^T Re J|^2 + |L^T Im J|^2, C = L L^T
+    Lc = cholesky_lower(p.colour_matrix)
+    L.append("  // colour matrix (rows):")
+    for row in p.colour_matrix:
+        L.append("  //   " + " ".join("%9.5f" % x for x in row))
+    L.append("  template <class T> NLO_HD static T colour_sum(const cx<T> (&J)[NFLOW]) {")
+    L.append("    T m2 = T(0), y;")
+    for part in ("r", "i"):
+        for k in range(nflow):
+            terms = ["T(%.17g) * J[%d].%s" % (Lc[j, k], j, part) for j in range(k, nflow) if abs(Lc[j, k]) > 1e-15]
+            if not terms:
+                continue
+            L.append("    y = %s; m2 += y * y;" % " + ".join(terms))
+    L.append("    return m2;")
+    L.append("  }")
+    # transposed Cholesky factor for the matrix-core colour contraction: LT[k][j] = L[j][k]
+    L.append("  static constexpr float LT[%d][%d] = {%s};" % (
+        nflow, nflow, ", ".join("{" + ", ".join("%.9ef" % Lc[j, k] for j in range(nflow)) + "}" for k in range(nflow))))
+    L.append("};")
+    return "\n".join(L)
+
+
+VARIANTS = ("VAR_F64", "VAR_F32", "VAR_MFMA")
+
+
+def _write_if_changed(path, src):
+    old = open(path).read() if os.path.exists(path) else None
+    if old != src:
+        with open(path, "w") as f:
+            f.write(src)
+
+
+def generate(out_dir):
+    """Write one header per process, one translation unit per (process,
+    kernel variant) and an index consumed by the C ABI.  Returns the list of
+    translation units."""
+    procs = process_list()
+    os.makedirs(out_dir, exist_ok=True)
+    tus = []
+    index = ["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "../launch.hpp"', "namespace nlo {"]
+    for p in procs:
+        p.enumerate()
+        p.colour()
+        hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "../helas.hpp"',
+                          "namespace nlo {", emit_process(p), "}  // namespace nlo", ""])
+        _write_if_changed(os.path.join(out_dir, p.name + ".hpp"), hdr)
+        for v, var in enumerate(VARIANTS):
+            tu = "\n".join(["// GENERATED by codegen.py -- do not edit.", '#include "../kernels.hpp"',
+                             '#include "%s.hpp"' % p.name, "namespace nlo {",
+                             "hipError_t me2_%s_%d(const LaunchArgs& a) { return launch_me2<%s, %s>(a); }"
+                             % (p.name, v, p.name, var), "}  // namespace nlo", ""])
+            path = os.path.join(out_dir, "tu_%s_%d.hip" % (p.name, v))
+            _write_if_changed(path, tu)
+            tus.append(path)
+            index.append("hipError_t me2_%s_%d(const LaunchArgs&);" % (p.name, v))
+    index.append("constexpr int NPROC = %d;" % len(procs))
+    index.append("static const ProcStatic PROC_STATIC[NPROC] = {")
+    for p in procs:
+        gs, ee = p.coupling_powers()
+        index.append('  {"%s", %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %.17g, %.17g},' % (
+            p.name, p.npart, len(p.incoming), len(p.flows), 1 << p.npart, len(p.good_helicities()), p.ndiagrams,
+            len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee, p.avg, p.ident))
+    index.append("};")
+    index.append("static const me2_launcher ME2_LAUNCH[NPROC][NVAR] = {")
+    for p in procs:
+        index.append("  {%s}," % ", ".join("me2_%s_%d" % (p.name, v) for v in range(len(VARIANTS))))
+    index.append("};")
+    index.append("}  // namespace nlo")
+    _write_if_changed(os.path.join(out_dir, "index.hpp"), "\n".join(index) + "\n")
+    stale = os.path.join(out_dir, "processes.hpp")
+    if os.path.exists(stale):
+        os.remove(stale)
+    return tus

@@ -1,0 +1,30 @@
+// Launch descriptors shared by the C ABI and the per-process kernel units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace nlo {
+
+// kernel variants of one process: FP64 vector ALU, FP32 vector ALU, FP32 with
+// the colour contraction on the matrix cores
+enum { VAR_F64 = 0, VAR_F32 = 1, VAR_MFMA = 2, NVAR = 3 };
+
+struct LaunchArgs {
+  int64_t n, ld;
+  const double* mom;
+  double* out;
+  double scale;   // average factor x coupling powers
+  double mt;
+  int block;
+  hipStream_t stream;
+};
+
+struct ProcStatic {
+  const char* name;
+  int npart, nin, nflow, nhel, ngood, ndiag, nterm, ncur, gs_pow, e_pow;
+  double avg, ident;
+};
+
+typedef hipError_t (*me2_launcher)(const LaunchArgs&);
+
+}  // namespace nlo

@@ -1,0 +1,133 @@
+"""Parity of the HIP |M|^2 path (through the C ABI) with the FP64 oracle,
+element by element on the same seeded inputs.
+
+Tolerances (relative, per event):
+  FP64           : 1e-12  (same arithmetic type; differences are rounding order)
+  FP32 / MIXED   : median 1e-5, every event 1e-3 (float amplitudes; see the
+                   accuracy notes of the library)
+"""
+import numpy as np
+import pytest
+
+from nlo_inputs.workloads import events
+
+pytestmark = pytest.mark.gpu
+
+PROCS = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    import paper_2503_07439_amd as nl
+    assert torch.cuda.is_available()
+    ctx = nl.Context()
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _rs(proc):
+    return 1000.0 if proc.startswith("ee") else (400.0, 2000.0)
+
+
+def _run(gpu, proc, mom, prec, block=None, colour_mode=0):
+    import torch
+    if block is not None:
+        gpu.set_kernel_config(proc, prec, block, colour_mode)
+    m = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
+    out = gpu.me2(proc, m, prec)
+    torch.cuda.synchronize()
+    if block is not None:
+        gpu.set_kernel_config(proc, prec, 256, 0)
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("proc", PROCS)
+def test_fp64_parity(gpu, orc, proc):
+    # several blocks plus a ragged tail
+    n = 1000 if proc != "gg_ttgg" else 333
+    mom, _ = events(proc, n, _rs(proc), stream=101)
+    ref = orc.me2(proc, mom)
+    got = _run(gpu, proc, mom, "fp64")
+    print(proc, "fp64 max rel", np.max(np.abs(got / ref - 1)), flush=True)
+    assert np.all(np.abs(got / ref - 1) < 1e-12)
+
+
+@pytest.mark.parametrize("prec,mode", [("fp32", 1), ("mixed", 2)])
+@pytest.mark.parametrize("proc", PROCS)
+def test_fp32_parity(gpu, orc, proc, prec, mode):
+    n = 1000 if proc != "gg_ttgg" else 333
+    mom, _ = events(proc, n, _rs(proc), stream=102)
+    ref = orc.me2(proc, mom)
+    got = _run(gpu, proc, mom, prec, block=256, colour_mode=mode)
+    r = np.abs(got / ref - 1)
+    print(proc, prec, "median", np.median(r), "max", r.max(), flush=True)
+    assert np.median(r) < 1e-5
+    assert np.all(r < 1e-3)
+
+
+@pytest.mark.parametrize("block", [64, 128, 512])
+def test_launch_shapes_bitwise_fp64(gpu, block):
+    """FP64 results do not depend on the launch shape (bitwise)."""
+    proc = "gg_ttg"
+    mom, _ = events(proc, 777, _rs(proc), stream=103)
+    a = _run(gpu, proc, mom, "fp64")
+    b = _run(gpu, proc, mom, "fp64", block=block, colour_mode=1)
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases(gpu, orc):
+    import torch
+    import paper_2503_07439_amd as nl
+    proc = "gg_tt"
+    # n = 0 is a no-op
+    m = torch.zeros((4, 4, 1), dtype=torch.float64, device="cuda")
+    out = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    nl.nlo_me2(gpu.ctx, nl.proc_id(proc), 0, 1, m.data_ptr(), out.data_ptr(), nl.NLO_FP64, 0)
+    torch.cuda.synchronize()
+    assert out.item() == -1.0
+    # single event, ld > n (strided batch), and a one-lane MFMA wave
+    mom, _ = events(proc, 5, _rs(proc), stream=104)
+    big = np.zeros((4, 4, 9))
+    big[:, :, :5] = mom
+    m = torch.from_numpy(big).cuda()
+    for prec in ("fp64", "mixed"):
+        out = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gpu.me2(proc, m, prec, out=out)
+        torch.cuda.synchronize()
+        ref = orc.me2(proc, mom[:, :, :1])
+        assert abs(out.item() / ref[0] - 1) < (1e-12 if prec == "fp64" else 1e-4)
+    # host-detected argument errors return before any launch
+    with pytest.raises(nl.NloError) as e:
+        nl.nlo_me2(gpu.ctx, 99, 1, 1, m.data_ptr(), out.data_ptr(), nl.NLO_FP64, 0)
+    assert e.value.status == 2
+    with pytest.raises(nl.NloError) as e:
+        nl.nlo_me2(gpu.ctx, 3, 4, 2, m.data_ptr(), out.data_ptr(), nl.NLO_FP64, 0)
+    assert e.value.status == 1
+    with pytest.raises(nl.NloError) as e:
+        nl.nlo_me2(gpu.ctx, 3, 1, 1, 0, out.data_ptr(), nl.NLO_FP64, 0)
+    assert e.value.status == 1
+    with pytest.raises(nl.NloError) as e:
+        nl.nlo_me2(gpu.ctx, 3, 1, 1, m.data_ptr(), out.data_ptr(), nl.NLO_FP16, 0)
+    assert e.value.status == 5
+
+
+def test_full_size_sampled_gg_ttg(gpu, orc):
+    """The headline workload at its full size (2^22 events, the benchmark's
+    launch configuration): every event is finite and positive, and a strided
+    sample of 512 events matches the oracle."""
+    import torch
+    from nlo_inputs.workloads import config_events
+    mom, _ = config_events("gg_ttg_400_2000")
+    m = torch.from_numpy(mom).cuda()
+    for prec, tol in (("mixed", 1e-3), ("fp64", 1e-12)):
+        out = gpu.me2("gg_ttg", m, prec)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        assert np.all(np.isfinite(o)) and np.all(o > 0)
+        idx = np.linspace(0, mom.shape[2] - 1, 512).astype(np.int64)
+        ref = orc.me2("gg_ttg", mom[:, :, idx])
+        r = np.abs(o[idx] / ref - 1)
+        print("full size", prec, "median", np.median(r), "max", r.max(), flush=True)
+        assert np.all(r < tol)

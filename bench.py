@@ -1,0 +1,149 @@
+"""Throughput benchmark: helicity- and colour-summed gg -> t tbar g |M|^2 on
+one MI355X, mixed precision (FP32 amplitudes, matrix-core colour
+contraction, FP64 helicity sum) against the plain FP64 GPU path, with the
+relative error of every event against the FP64 result and of a sample
+against the FP64 CPU oracle.
+
+One step = one nlo_me2 call over the whole batch (2^22 RAMBO events, m_t =
+173 GeV, sqrt(s_hat) uniform in [400, 2000] GeV), inputs resident in HBM.
+Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--no-cpu-baseline] [--prec mixed|fp32|fp64]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gg→tt̄g |M|^2 events/s (hel+colour summed) mixed vs FP64, at stated rel err"
+PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector ALU, TFLOP/s (published)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gg_ttg_400_2000")
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--events", type=int, default=0, help="override the batch size")
+    return ap.parse_args()
+
+
+def timed(ctx, proc, mom, out, prec, steps, warmup):
+    """Average duration of one launch, with HIP events on the launch stream."""
+    import torch
+    for _ in range(warmup):
+        ctx.me2(proc, mom, prec, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        ctx.me2(proc, mom, prec, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def cpu_baseline(proc, mom_full, target_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload (the first events of the batch)."""
+    import oracle
+    oracle.build()
+    oracle.set_params()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    probe = 2048
+    t = time.perf_counter()
+    oracle.me2(proc, mom_full[:, :, :probe], nthreads=threads)
+    rate = probe / (time.perf_counter() - t)
+    n = int(min(mom_full.shape[2], max(probe, rate * target_s)))
+    t = time.perf_counter()
+    ref = oracle.me2(proc, np.ascontiguousarray(mom_full[:, :, :n]), nthreads=threads)
+    dt = time.perf_counter() - t
+    return ref, {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+                 "sample": "first %d events of the batch (FP64 oracle: colour-ordered recursion, "
+                           "std::thread over events, g++ -O2), %.1f s" % (n, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (requested --gpus %d); events shard "
+              "trivially across GPUs, see the design notes" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2503_07439_amd as nl
+    from nlo_inputs.workloads import CONFIGS, config_events
+
+    proc, nfull, rs, stream = CONFIGS[args.workload]
+    n = args.events or nfull
+    t = time.perf_counter()
+    mom_np, _ = config_events(args.workload, n=n)
+    print("inputs: %d %s events generated in %.1f s" % (n, proc, time.perf_counter() - t), file=sys.stderr, flush=True)
+    ctx = nl.Context()
+    mom = torch.from_numpy(mom_np).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    info = ctx.info(proc)
+
+    ms = timed(ctx, proc, mom, out, args.prec, args.steps, args.warmup)
+    res = out.clone()
+    print("%s %s: %.3f ms per step" % (proc, args.prec, ms), file=sys.stderr, flush=True)
+
+    fp64 = None
+    if not args.no_fp64 and args.prec != "fp64":
+        out64 = torch.empty_like(out)
+        ms64 = timed(ctx, proc, mom, out64, "fp64", max(3, args.steps // 4), 1)
+        rel = (res / out64 - 1).abs().cpu().numpy()
+        sum_rel = abs(float(res.sum()) / float(out64.sum()) - 1)
+        fp64 = {"ms_per_step": ms64, "events_per_s": n / (ms64 * 1e-3), "speedup_mixed_vs_fp64": ms64 / ms,
+                "rel_err_vs_gpu_fp64": {"median": float(np.median(rel)), "p99_9": float(np.quantile(rel, 0.999)),
+                                        "max": float(rel.max()), "summed": sum_rel}}
+        print("fp64: %.3f ms per step" % ms64, file=sys.stderr, flush=True)
+
+    # algorithmic flops of the helicity loop (amplitudes + colour contraction)
+    with open(os.path.join(ROOT, "paper_2503_07439_amd", "flops.json")) as f:
+        fl = json.load(f)[proc]
+    flops_event = fl["ngood"] * (fl["amp_flops_per_hel"] + fl["colour_flops_per_hel"])
+    achieved = flops_event * n / (ms * 1e-3) / 1e12
+    peak = PEAK["fp64" if args.prec == "fp64" else "fp32"]
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "flops_per_event": flops_event,
+                "kernel": "k_me2_%s<%s>" % ("mfma" if args.prec == "mixed" else "valu", proc)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        ref, cpu = cpu_baseline(proc, mom_np)
+        k = ref.shape[0]
+        r = np.abs(res[:k].cpu().numpy() / ref - 1)
+        cpu["rel_err_of_gpu_%s_on_sample" % args.prec] = {
+            "median": float(np.median(r)), "p99_9": float(np.quantile(r, 0.999)), "max": float(r.max()),
+            "summed": abs(float(res[:k].sum().item()) / float(ref.sum()) - 1)}
+
+    line = {
+        "metric": METRIC, "value": n / (ms * 1e-3), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "process": info.name.decode(), "events": n,
+                   "sqrt_s_hat_GeV": list(rs) if isinstance(rs, tuple) else rs, "m_top_GeV": 173.0,
+                   "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
+                   "helicities": info.ngood_hel},
+        "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -79,7 +79,7 @@ typedef struct {
 
 /* Kernel launch configuration of one (process, precision) pair. */
 typedef struct {
-  int block;        /* threads per block, multiple of 64, <= 1024 */
+  int block;        /* threads per block: 64, 128, 192 or 256 */
   int colour_mode;  /* 0 = automatic, 1 = vector ALU, 2 = matrix cores (FP32 family only) */
 } nlo_kernel_config;
 

@@ -74,7 +74,26 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     os.replace(tmp, LIB)
     if verbose:
         print("linked", LIB, flush=True)
+    count_flops(verbose)
     return LIB
+
+
+def count_flops(verbose=True):
+    """Compile and run the host operation counter; writes flops.json (the
+    algorithmic flop count per event used for the roofline)."""
+    exe = os.path.join(OBJ, "opcount")
+    src = os.path.join(CSRC, "opcount.hip")
+    cmd = [_hipcc(), "-O1", "-std=c++17", "--offload-arch=gfx950", "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
+           "-o", exe, src]
+    subprocess.run(cmd, check=True, capture_output=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    import json
+    data = json.loads(out)
+    with open(os.path.join(HERE, "flops.json"), "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    if verbose:
+        print("flop counts written", flush=True)
+    return data
 
 
 if __name__ == "__main__":

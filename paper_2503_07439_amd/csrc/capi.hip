@@ -150,8 +150,9 @@ nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const
   if (st) return st;
   if (!cfg) return fail(NLO_EINVAL, "nlo_set_kernel_config: cfg is NULL");
   if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "nlo_set_kernel_config: bad precision");
-  if (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64)
-    return fail(NLO_EINVAL, "nlo_set_kernel_config: block %d must be a multiple of 64 in [64, 1024]", cfg->block);
+  if (cfg->block < 64 || cfg->block > NLO_MAX_BLOCK || cfg->block % 64)
+    return fail(NLO_EINVAL, "nlo_set_kernel_config: block %d must be a multiple of 64 in [64, %d]", cfg->block,
+                NLO_MAX_BLOCK);
   if (cfg->colour_mode < 0 || cfg->colour_mode > 2) return fail(NLO_EINVAL, "nlo_set_kernel_config: bad colour_mode");
   if (cfg->colour_mode == 2 && prec == NLO_FP64)
     return fail(NLO_EUNSUPPORTED, "nlo_set_kernel_config: matrix-core colour contraction is FP32 only");

@@ -32,7 +32,7 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
 // vector-ALU kernel: any arithmetic type T
 // ---------------------------------------------------------------------------
 template <class P, class T>
-__global__ __launch_bounds__(256) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
+__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -65,7 +65,7 @@ struct MfmaShape {
 };
 
 template <class P>
-__global__ __launch_bounds__(256) void k_me2_mfma(int64_t n, int64_t ld, const double* __restrict__ mom,
+__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt) {
   using S = MfmaShape<P>;
   extern __shared__ float smem[];

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+// largest block the kernels are compiled for (their __launch_bounds__)
+#define NLO_MAX_BLOCK 256
+
 namespace nlo {
 
 // kernel variants of one process: FP64 vector ALU, FP32 vector ALU, FP32 with

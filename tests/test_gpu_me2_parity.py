@@ -2,7 +2,9 @@
 element by element on the same seeded inputs.
 
 Tolerances (relative, per event):
-  FP64           : 1e-12  (same arithmetic type; differences are rounding order)
+  FP64           : median 1e-13, every event 1e-11 (same arithmetic type; the
+                   differences are rounding order over up to 159 amplitude
+                   terms with cancellations between them)
   FP32 / MIXED   : median 1e-5, every event 1e-3 (float amplitudes; see the
                    accuracy notes of the library)
 """
@@ -50,8 +52,10 @@ def test_fp64_parity(gpu, orc, proc):
     mom, _ = events(proc, n, _rs(proc), stream=101)
     ref = orc.me2(proc, mom)
     got = _run(gpu, proc, mom, "fp64")
-    print(proc, "fp64 max rel", np.max(np.abs(got / ref - 1)), flush=True)
-    assert np.all(np.abs(got / ref - 1) < 1e-12)
+    r = np.abs(got / ref - 1)
+    print(proc, "fp64 median", np.median(r), "max", r.max(), flush=True)
+    assert np.median(r) < 1e-13
+    assert np.all(r < 1e-11)
 
 
 @pytest.mark.parametrize("prec,mode", [("fp32", 1), ("mixed", 2)])
@@ -67,7 +71,7 @@ def test_fp32_parity(gpu, orc, proc, prec, mode):
     assert np.all(r < 1e-3)
 
 
-@pytest.mark.parametrize("block", [64, 128, 512])
+@pytest.mark.parametrize("block", [64, 128, 192])
 def test_launch_shapes_bitwise_fp64(gpu, block):
     """FP64 results do not depend on the launch shape (bitwise)."""
     proc = "gg_ttg"
@@ -97,7 +101,7 @@ def test_edge_cases(gpu, orc):
         gpu.me2(proc, m, prec, out=out)
         torch.cuda.synchronize()
         ref = orc.me2(proc, mom[:, :, :1])
-        assert abs(out.item() / ref[0] - 1) < (1e-12 if prec == "fp64" else 1e-4)
+        assert abs(out.item() / ref[0] - 1) < (1e-11 if prec == "fp64" else 1e-4)
     # host-detected argument errors return before any launch
     with pytest.raises(nl.NloError) as e:
         nl.nlo_me2(gpu.ctx, 99, 1, 1, m.data_ptr(), out.data_ptr(), nl.NLO_FP64, 0)
@@ -111,6 +115,11 @@ def test_edge_cases(gpu, orc):
     with pytest.raises(nl.NloError) as e:
         nl.nlo_me2(gpu.ctx, 3, 1, 1, m.data_ptr(), out.data_ptr(), nl.NLO_FP16, 0)
     assert e.value.status == 5
+    # launch shapes beyond the kernels' launch bounds are rejected on the host
+    for bad in (0, 32, 320, 512, 1024):
+        with pytest.raises(nl.NloError) as e:
+            nl.nlo_set_kernel_config(gpu.ctx, 3, nl.NLO_FP64, bad, 1)
+        assert e.value.status == 1
 
 
 def test_full_size_sampled_gg_ttg(gpu, orc):
@@ -121,7 +130,7 @@ def test_full_size_sampled_gg_ttg(gpu, orc):
     from nlo_inputs.workloads import config_events
     mom, _ = config_events("gg_ttg_400_2000")
     m = torch.from_numpy(mom).cuda()
-    for prec, tol in (("mixed", 1e-3), ("fp64", 1e-12)):
+    for prec, tol in (("mixed", 1e-3), ("fp64", 1e-11)):
         out = gpu.me2("gg_ttg", m, prec)
         torch.cuda.synchronize()
         o = out.cpu().numpy()

@@ -4,8 +4,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU path
 (``paper_2503_07439_amd``) and never imports it.
 
-Thin ctypes wrapper around ``liboracle.so`` (built from ``oracle.cpp`` and
-``fks.cpp`` with g++).
+Thin ctypes wrapper around ``liboracle.so`` (built from ``oracle.cpp`` with
+g++).
 """
 import ctypes
 import os
@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, f) for f in ("oracle.cpp", "fks.cpp") if os.path.exists(os.path.join(_HERE, f))]
+_SRC = [os.path.join(_HERE, "oracle.cpp")]
 
 PROCS = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -127,3 +127,71 @@ def wavefunction(proc, p_aos, leg, lam):
     out = np.empty(8)
     lib().orc_wavefunction(pid(proc), _dp(p), leg, lam, _dp(out))
     return out[0::2] + 1j * out[1::2]
+
+
+FKS_FIELDS = ["xi", "y", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "W", "me2_R", "B", "S"]
+
+
+def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=8, want_real=False):
+    """FKS-subtracted real emission for pair (i, j) (j = -1: initial state).
+    Returns dict of arrays (FKS_FIELDS) and optionally the real momenta."""
+    L = lib()
+    f = L.orc_fks
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.POINTER(ctypes.c_double)] * 6 + [ctypes.c_int]
+    born_mom = np.ascontiguousarray(born_mom, dtype=np.float64)
+    n = born_mom.shape[2]
+    xi_tilde = np.ascontiguousarray(np.broadcast_to(xi_tilde, (n,)), dtype=np.float64)
+    y = np.ascontiguousarray(np.broadcast_to(y, (n,)), dtype=np.float64)
+    phi = np.ascontiguousarray(np.broadcast_to(phi, (n,)), dtype=np.float64)
+    out = np.empty((n, 12))
+    nreal = born_mom.shape[0] + 1
+    real = np.empty((nreal, 4, n)) if want_real else None
+    rc = f(pid(real_proc), i, j, n, _dp(born_mom), _dp(xi_tilde), _dp(y), _dp(phi), _dp(out),
+           _dp(real) if want_real else ctypes.POINTER(ctypes.c_double)(), nthreads)
+    assert rc == 0, rc
+    res = {k: out[:, q].copy() for q, k in enumerate(FKS_FIELDS)}
+    if want_real:
+        res["real_mom"] = real
+    return res
+
+
+def born_correlations(proc, mom):
+    L = lib()
+    f = L.orc_born_correlations
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    n = mom.shape[2]
+    nl = ctypes.c_int()
+    B = np.empty(n)
+    Bkl = np.empty(n * 64)
+    rc = f(pid(proc), n, _dp(mom), _dp(B), _dp(Bkl), ctypes.byref(nl))
+    assert rc == 0
+    k = nl.value
+    return B, Bkl[:n * k * k].reshape(n, k, k)
+
+
+def sector_functions(real_proc, real_mom):
+    L = lib()
+    f = L.orc_sector_functions
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_int)]
+    real_mom = np.ascontiguousarray(real_mom, dtype=np.float64)
+    n = real_mom.shape[2]
+    out = np.empty(n * 8)
+    k = ctypes.c_int()
+    assert f(pid(real_proc), n, _dp(real_mom), _dp(out), ctypes.byref(k)) == 0
+    return out[:n * k.value].reshape(n, k.value)
+
+
+def born_spin_correlated(proc, mom, leg, eperp):
+    L = lib()
+    f = L.orc_born_spin_correlated
+    f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    n = mom.shape[2]
+    ep = np.ascontiguousarray(np.broadcast_to(eperp, (n, 4)), dtype=np.float64)
+    out = np.empty(n)
+    assert f(pid(proc), n, _dp(mom), leg, _dp(ep), _dp(out)) == 0
+    return out

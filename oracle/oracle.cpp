@@ -33,6 +33,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <map>
 #include <thread>
 #include <vector>
@@ -993,3 +994,562 @@ int orc_me2_brute(int proc, int64_t n, int64_t ld, const double* mom, int h, dou
 }
 
 }  // extern "C"
+
+// ============================================================================
+// FKS subtraction (ORACLE) -- the paper names FKS subtraction as the scheme
+// whose soft and collinear counterterms make the real emission locally
+// integrable, and splits the phase space into FKS sectors.  The paper does
+// not spell out maps, sector functions or plus-distribution parameters; the
+// fixed reading implemented here:
+//   xi = 2 k_i^0 / sqrt(s_R) in the real partonic frame, y = cos(k_i, k_j)
+//   (final j) or cos(k_i, beam 1) (initial j), phi = azimuth of k_i about the
+//   emitter direction measured from the (emitter, z) plane.
+//   FSR map: recoil boost along the emitter direction; ISR map: s_R =
+//   s_B/(1-xi), Born final state pure-boosted to K = p1 + p2 - k_i.
+//   xi = xi_tilde * xi_max; xi_max = 1 - M_rec^2/s (FSR), 1 - s_B/s_cap with
+//   sqrt(s_cap) = 4000 GeV (ISR).
+//   f(xi, y) = xi^2 (1-y) |M_R|^2 S_ij (FSR), xi^2 (1-y^2) |M_R|^2 S_i0 (ISR);
+//   always-subtract (xi_c = xi_max, delta = 2):
+//   W_FSR = [f(xi,y) - f(0,y) - f(xi,1) + f(0,1)] / (xi (1-y))
+//   W_ISR = [f(xi,y) - f(0,y) - (1+y)/2 (f(xi,1) - f(0,1))
+//                              - (1-y)/2 (f(xi,-1) - f(0,-1))] / (xi (1-y^2))
+//   Sector functions S_ij = (h_ij/d_ij) / sum_P (h_kl/d_kl), d_kl = xi_k xi_l
+//   (1-y_kl) (final l), xi_k (1-y_k^2) (beams), h = xi_l/(xi_k+xi_l) for
+//   gluon-gluon pairs, else 1.
+// The soft limit uses the eikonal factor with colour-linked Borns, the
+// collinear limits the Altarelli-Parisi kernels with the spin-correlated Born
+// for gluon splittings.
+// ============================================================================
+static const double FKS_SQRT_SCAP = 4000.0;
+
+// colour charge operators on explicit colour tensors ---------------------------
+// leg kinds: 'r' fundamental (row end), 'c' antifundamental (column end),
+// 'g' adjoint.  T^a acts as T^a on 'r', as -(T^a)^T on 'c', as -i f^{abc} on 'g'.
+struct ColTensor {
+  std::vector<char> kind;    // per coloured leg
+  std::vector<int> dim;
+  std::vector<cd> v;         // row-major over legs
+};
+static size_t ct_size(const ColTensor& t) { size_t s = 1; for (int d : t.dim) s *= d; return s; }
+static ColTensor apply_charge(const ColTensor& t, int leg, int a) {
+  ColTensor r = t;
+  std::fill(r.v.begin(), r.v.end(), cd(0));
+  size_t n = ct_size(t);
+  size_t stride = 1;
+  for (int k = (int)t.dim.size() - 1; k > leg; --k) stride *= t.dim[k];
+  int d = t.dim[leg];
+  for (size_t idx = 0; idx < n; ++idx) {
+    if (t.v[idx] == 0.0) continue;
+    int c = (int)((idx / stride) % d);
+    size_t base = idx - (size_t)c * stride;
+    for (int c2 = 0; c2 < d; ++c2) {
+      cd f;
+      if (t.kind[leg] == 'r') f = TA[a][c2][c];             // (T^a X)_{c2} = T^a_{c2 c} X_c
+      else if (t.kind[leg] == 'c') f = -TA[a][c][c2];       // -(X T^a)_{c2} = -X_c T^a_{c c2}
+      else f = -I * FABC[a][c2][c];                          // (F^a)_{c2 c} = -i f^{a c2 c}
+      if (f != 0.0) r.v[base + (size_t)c2 * stride] += f * t.v[idx];
+    }
+  }
+  return r;
+}
+static cd ct_dot(const ColTensor& a, const ColTensor& b) {
+  cd s = 0;
+  for (size_t i = 0; i < a.v.size(); ++i) s += std::conj(a.v[i]) * b.v[i];
+  return s;
+}
+
+// explicit colour tensors of the amplitude basis of a Born process, legs in
+// process order (coloured legs only), and the process-leg index of each
+struct BornColour {
+  std::vector<int> legs;              // process leg index of each coloured leg
+  std::vector<ColTensor> basis;
+  std::vector<std::vector<cd>> Ckl;   // per pair (k,l) over coloured legs, nc x nc
+};
+
+static void build_basis(int proc, BornColour& bc) {
+  init_su3();
+  bc.basis.clear();
+  if (proc == EE_UU) {
+    bc.legs = {2, 3};
+    ColTensor t; t.kind = {'r', 'c'}; t.dim = {3, 3}; t.v.assign(9, 0.0);
+    for (int i = 0; i < 3; ++i) t.v[i * 3 + i] = 1.0;
+    bc.basis.push_back(t);
+  } else if (proc == GG_TT || proc == GG_TTG) {
+    BGLine L = bg_line(proc);
+    int n = (int)L.gl.size();
+    // coloured legs in process order
+    bc.legs.clear();
+    for (int k = 0; k < PROCS[proc].npart; ++k) bc.legs.push_back(k);
+    std::vector<int> perm(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    do {
+      ColTensor t;
+      for (int k : bc.legs) {
+        if (k == L.row) { t.kind.push_back('r'); t.dim.push_back(3); }
+        else if (k == L.col) { t.kind.push_back('c'); t.dim.push_back(3); }
+        else { t.kind.push_back('g'); t.dim.push_back(8); }
+      }
+      t.v.assign(ct_size(t), 0.0);
+      // position of each gluon leg in the tensor
+      std::vector<int> gpos(n);
+      for (int g = 0; g < n; ++g)
+        for (size_t q = 0; q < bc.legs.size(); ++q) if (bc.legs[q] == L.gl[g]) gpos[g] = (int)q;
+      int rpos = -1, cpos = -1;
+      for (size_t q = 0; q < bc.legs.size(); ++q) { if (bc.legs[q] == L.row) rpos = (int)q; if (bc.legs[q] == L.col) cpos = (int)q; }
+      size_t N = ct_size(t);
+      std::vector<int> idx(t.dim.size());
+      for (size_t lin = 0; lin < N; ++lin) {
+        size_t x = lin;
+        for (int q = (int)t.dim.size() - 1; q >= 0; --q) { idx[q] = (int)(x % t.dim[q]); x /= t.dim[q]; }
+        M3 m;
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) m[i][j] = (i == j) ? 1.0 : 0.0;
+        for (int s = 0; s < n; ++s) {
+          const M3& T = TA[idx[gpos[perm[s]]]];
+          M3 r;
+          for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) { cd v = 0; for (int k = 0; k < 3; ++k) v += m[i][k] * T[k][j]; r[i][j] = v; }
+          m = r;
+        }
+        t.v[lin] = m[idx[rpos]][idx[cpos]];
+      }
+      bc.basis.push_back(t);
+    } while (std::next_permutation(perm.begin(), perm.end()));
+  } else if (proc == UU_TT) {
+    // single diagram, colour sum_b T^b_{i1 j1} T^b_{i2 j2}; legs 0 u(in, col), 1 ubar(in, row), 2 t(row), 3 tbar(col)
+    bc.legs = {0, 1, 2, 3};
+    ColTensor t; t.kind = {'c', 'r', 'r', 'c'}; t.dim = {3, 3, 3, 3}; t.v.assign(81, 0.0);
+    for (int j1 = 0; j1 < 3; ++j1)
+      for (int i1 = 0; i1 < 3; ++i1)
+        for (int i2 = 0; i2 < 3; ++i2)
+          for (int j2 = 0; j2 < 3; ++j2) {
+            cd s = 0;
+            for (int b = 0; b < 8; ++b) s += TA[b][i1][j1] * TA[b][i2][j2];
+            t.v[((j1 * 3 + i1) * 3 + i2) * 3 + j2] = s;
+          }
+    bc.basis.push_back(t);
+  }
+  int nl = (int)bc.legs.size();
+  int nc = (int)bc.basis.size();
+  bc.Ckl.assign(nl * nl, std::vector<cd>(nc * nc, 0.0));
+  for (int k = 0; k < nl; ++k)
+    for (int l = 0; l < nl; ++l)
+      for (int a = 0; a < 8; ++a)
+        for (int tau = 0; tau < nc; ++tau) {
+          ColTensor t2 = apply_charge(apply_charge(bc.basis[tau], l, a), k, a);
+          for (int sig = 0; sig < nc; ++sig) bc.Ckl[k * nl + l][sig * nc + tau] += ct_dot(bc.basis[sig], t2);
+        }
+}
+
+static BornColour BORNCOL[NPROC];
+static bool BORNCOL_DONE[NPROC];
+static const BornColour& born_colour(int proc) {
+  static std::mutex m;
+  std::lock_guard<std::mutex> g(m);
+  if (!BORNCOL_DONE[proc]) { build_basis(proc, BORNCOL[proc]); BORNCOL_DONE[proc] = true; }
+  return BORNCOL[proc];
+}
+
+// Born |M|^2 and colour-linked Borns B_kl (coloured legs, k,l in bc.legs order),
+// both including the average factor
+static void born_correlations(int proc, const V4* p, double& B, std::vector<double>& Bkl) {
+  const ProcDef& P = PROCS[proc];
+  const BornColour& bc = born_colour(proc);
+  const ColourData& c = COLOUR[proc];
+  int nl = (int)bc.legs.size();
+  int nc = c.nc;
+  Bkl.assign(nl * nl, 0.0);
+  B = 0;
+  std::vector<cd> A(nc);
+  Ext ex;
+  for (int h = 0; h < (1 << P.npart); ++h) {
+    build_ext(proc, p, h, ex, -1, nullptr);
+    flows(proc, ex, A.data());
+    B += quad(c, A.data());
+    for (int q = 0; q < nl * nl; ++q) {
+      cd s = 0;
+      for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) s += std::conj(A[i]) * bc.Ckl[q][i * nc + j] * A[j];
+      Bkl[q] += s.real();
+    }
+  }
+  B *= P.avg;
+  for (auto& x : Bkl) x *= P.avg;
+}
+
+// spin-correlated Born: emitter leg's polarisation replaced by the real unit
+// vector eperp (eperp.eperp = -1), summed over the other helicities
+static double born_spin_correlated(int proc, const V4* p, int leg, const V4& eperp) {
+  const ProcDef& P = PROCS[proc];
+  const ColourData& c = COLOUR[proc];
+  std::vector<cd> A(c.nc);
+  C4 ov = c4(eperp);
+  Ext ex;
+  double s = 0;
+  int bit = 1 << (P.npart - 1 - leg);
+  for (int h = 0; h < (1 << P.npart); ++h) {
+    if (h & bit) continue;
+    build_ext(proc, p, h, ex, leg, &ov);
+    flows(proc, ex, A.data());
+    s += quad(c, A.data());
+  }
+  return s * P.avg;
+}
+
+// FKS sector description ----------------------------------------------------
+struct FksPair { int i, j; };            // j = -1: initial state (both beams)
+struct FksDef {
+  int real, born;
+  int nreal, nborn;
+  std::vector<FksPair> pairs;            // all FKS pairs of the real process
+  std::vector<char> gluon;               // per real leg
+  std::vector<char> quark;               // per real leg (massless quark)
+};
+static FksDef fks_def(int real) {
+  FksDef d;
+  d.real = real;
+  d.nreal = PROCS[real].npart;
+  if (real == EE_UUG) { d.born = EE_UU; d.pairs = {{4, 2}, {4, 3}}; }
+  else if (real == GG_TTG) { d.born = GG_TT; d.pairs = {{4, -1}}; }
+  else if (real == GG_TTGG) { d.born = GG_TTG; d.pairs = {{4, 5}, {5, 4}, {4, -1}, {5, -1}}; }
+  else if (real == UU_TTG) { d.born = UU_TT; d.pairs = {{4, -1}}; }
+  else d.born = -1;
+  d.nborn = d.born >= 0 ? PROCS[d.born].npart : 0;
+  d.gluon.assign(d.nreal, 0);
+  d.quark.assign(d.nreal, 0);
+  for (int k = 0; k < d.nreal; ++k) {
+    char kind = PROCS[real].kinds[k];
+    d.gluon[k] = kind == 'g';
+    d.quark[k] = (kind == 'q' || kind == 'Q') && leg_mass(real, k) == 0.0;
+  }
+  return d;
+}
+
+static double v3dot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// polar basis around a unit vector khat: e1 in the (khat, z) plane, e2 = khat x e1
+static void perp_basis(const double* kh, double* e1, double* e2) {
+  double st = std::sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
+  double ct = kh[2];
+  double cp = st > 0 ? kh[0] / st : 1.0, sp = st > 0 ? kh[1] / st : 0.0;
+  e1[0] = ct * cp; e1[1] = ct * sp; e1[2] = -st;
+  e2[0] = -sp; e2[1] = cp; e2[2] = 0.0;
+}
+
+// boost along unit vector u that multiplies the light-cone component E + p.u
+// by rho (and E - p.u by 1/rho); finite also for a massless recoil system
+static V4 boost_along(const V4& p, const double* u, double rho) {
+  double pl = p.v[1] * u[0] + p.v[2] * u[1] + p.v[3] * u[2];
+  double pp = p.v[0] + pl, pm = p.v[0] - pl;
+  double e2 = 0.5 * (rho * pp + pm / rho);
+  double pl2 = 0.5 * (rho * pp - pm / rho);
+  V4 r;
+  r.v[0] = e2;
+  for (int k = 0; k < 3; ++k) r.v[1 + k] = p.v[1 + k] + (pl2 - pl) * u[k];
+  return r;
+}
+// pure boost taking a vector at rest (mass M) to total momentum K
+static V4 boost_to(const V4& p, const V4& K, double M) {
+  double g = K.v[0] / M;
+  double bp = (K.v[1] * p.v[1] + K.v[2] * p.v[2] + K.v[3] * p.v[3]) / M;   // gamma beta . p
+  V4 r;
+  r.v[0] = g * p.v[0] + bp;
+  double f = p.v[0] / M + bp / (K.v[0] + M);
+  for (int k = 0; k < 3; ++k) r.v[1 + k] = p.v[1 + k] + f * K.v[1 + k];
+  return r;
+}
+
+// sector function of pair (i, j) at real momenta k (real frame)
+static double sector_value(const FksDef& d, const V4* k, double sqrt_s, int i, int j) {
+  auto xi = [&](int a) { return 2.0 * k[a].v[0] / sqrt_s; };
+  auto ycos = [&](int a, int b) {
+    double pa = std::sqrt(v3dot(k[a].v + 1, k[a].v + 1)), pb = std::sqrt(v3dot(k[b].v + 1, k[b].v + 1));
+    return v3dot(k[a].v + 1, k[b].v + 1) / (pa * pb);
+  };
+  auto term = [&](int a, int b) {
+    if (b < 0) {
+      double pa = std::sqrt(v3dot(k[a].v + 1, k[a].v + 1));
+      double ya = k[a].v[3] / pa;
+      return 1.0 / (xi(a) * (1.0 - ya) * (1.0 + ya));
+    }
+    double h = (d.gluon[a] && d.gluon[b]) ? xi(b) / (xi(a) + xi(b)) : 1.0;
+    return h / (xi(a) * xi(b) * (1.0 - ycos(a, b)));
+  };
+  double num = 0, den = 0;
+  for (const FksPair& q : d.pairs) {
+    double t = term(q.i, q.j);
+    den += t;
+    if (q.i == i && q.j == j) num = t;
+  }
+  return num / den;
+}
+
+// soft limit of the sector function: direction nh of the soft parton i,
+// Born momenta kb in Born leg order, bmap[real leg] = Born leg (or -1)
+static double sector_soft(const FksDef& d, const V4* kb, const int* bmap, double sqrt_s, const double* nh, int i, int j) {
+  double num = 0, den = 0;
+  for (const FksPair& q : d.pairs) {
+    if (q.i != i) continue;
+    double t;
+    if (q.j < 0) t = 1.0 / ((1.0 - nh[2]) * (1.0 + nh[2]));
+    else {
+      const V4& pl = kb[bmap[q.j]];
+      double pa = std::sqrt(v3dot(pl.v + 1, pl.v + 1));
+      double y = v3dot(nh, pl.v + 1) / pa;
+      t = 1.0 / ((2.0 * pl.v[0] / sqrt_s) * (1.0 - y));
+    }
+    den += t;
+    if (q.j == j) num = t;
+  }
+  return num / den;
+}
+
+struct FksOut {
+  double xi, y, gR, gS, gC, gCm, gSC, gSCm, W, me2R, B, S;
+};
+
+// one event of the FKS-subtracted real emission for pair (i, j)
+static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit, double y, double phi, V4* kreal) {
+  const double g2 = 4.0 * M_PI * g_alpha_s;
+  const double CF = 4.0 / 3.0, CA = 3.0;
+  FksOut o{};
+  o.y = y;
+  int nb = d.nborn;
+  double sqs_b = kb[0].v[0] + kb[1].v[0];
+  double sb = sqs_b * sqs_b;
+  int bmap[8];                           // real leg -> Born leg (-1 for i)
+  double nh[3];                          // soft direction of i
+  V4 eperp{{0, 0, 0, 0}};
+  double s_real, sqs_real;
+  if (j >= 0) {
+    // ---------------- final-state emitter --------------------------------
+    // real legs: Born legs keep their positions; i is the extra leg
+    int jb = -1;
+    for (int r = 0, b = 0; r < d.nreal; ++r) {
+      if (r == i) { bmap[r] = -1; continue; }
+      bmap[r] = b++;
+      if (r == j) jb = bmap[r];
+    }
+    const V4& kj = kb[jb];
+    V4 q{{sqs_b, 0, 0, 0}};
+    V4 krec{{q.v[0] - kj.v[0], -kj.v[1], -kj.v[2], -kj.v[3]}};
+    double mrec2 = dot(krec, krec);
+    double xmax = 1.0 - mrec2 / sb;
+    double xi = xit * xmax;
+    double Ei = 0.5 * xi * sqs_b;
+    double Ej = (sb - mrec2 - 2.0 * sqs_b * Ei) / (2.0 * sqs_b - 2.0 * Ei * (1.0 - y));
+    double kabs = std::sqrt(Ei * Ei + Ej * Ej + 2.0 * Ei * Ej * y);
+    double kjabs = std::sqrt(v3dot(kj.v + 1, kj.v + 1));
+    double kh[3] = {kj.v[1] / kjabs, kj.v[2] / kjabs, kj.v[3] / kjabs};
+    double e1[3], e2[3];
+    perp_basis(kh, e1, e2);
+    double sy = std::sqrt((1.0 - y) * (1.0 + y));
+    double cti = (Ei + Ej * y) / kabs, sti = Ej * sy / kabs;
+    double cphi = std::cos(phi), sphi = std::sin(phi);
+    double ki_dir[3], ep[3];
+    for (int m = 0; m < 3; ++m) {
+      ep[m] = cphi * e1[m] + sphi * e2[m];
+      ki_dir[m] = cti * kh[m] + sti * ep[m];
+      nh[m] = y * kh[m] + sy * ep[m];
+    }
+    V4 ki{{Ei, Ei * ki_dir[0], Ei * ki_dir[1], Ei * ki_dir[2]}};
+    V4 kjn{{Ej, kabs * kh[0] - ki.v[1], kabs * kh[1] - ki.v[2], kabs * kh[2] - ki.v[3]}};
+    double u[3] = {-kh[0], -kh[1], -kh[2]};
+    // recoil system along u = -khat: light-cone component (E + |p|) scaled from
+    // (sqrt(s) - Ebar_j + |kbar_j|) to (sqrt(s) - E_i - E_j + |k|)
+    double dyr = (sqs_b - Ei - Ej + kabs) / (sqs_b - kj.v[0] + kjabs);
+    for (int r = 0; r < d.nreal; ++r) {
+      if (r == i) kreal[r] = ki;
+      else if (r == j) kreal[r] = kjn;
+      else if (r < 2) kreal[r] = kb[bmap[r]];
+      else kreal[r] = boost_along(kb[bmap[r]], u, dyr);
+    }
+    s_real = sb; sqs_real = sqs_b;
+    o.xi = xi;
+    eperp = V4{{0, ep[0], ep[1], ep[2]}};
+    // real matrix element and sector function
+    o.me2R = me2_event(d.real, kreal, nullptr);
+    o.S = sector_value(d, kreal, sqs_real, i, j);
+    o.gR = xi * xi * (1.0 - y) * o.me2R * o.S;
+    // Born correlations at the Born kinematics
+    double B;
+    std::vector<double> Bkl;
+    born_correlations(d.born, kb, B, Bkl);
+    o.B = B;
+    const BornColour& bc = born_colour(d.born);
+    int nl = (int)bc.legs.size();
+    // eikonal: -sum_{kl} (p_k.p_l)/((p_k.n)(p_l.n)) B_kl with n = (1, nh)
+    V4 n{{1.0, nh[0], nh[1], nh[2]}};
+    double eik = 0;
+    for (int a = 0; a < nl; ++a)
+      for (int b = 0; b < nl; ++b) {
+        const V4 &pa = kb[bc.legs[a]], &pb = kb[bc.legs[b]];
+        eik -= dot(pa, pb) / (dot(pa, n) * dot(pb, n)) * Bkl[a * nl + b];
+      }
+    double Ss = sector_soft(d, kb, bmap, sqs_b, nh, i, j);
+    o.gS = (1.0 - y) * 4.0 / sb * g2 * eik * Ss;
+    // collinear limit y -> 1: E_j^c = Ebar_j - E_i, z = E_j^c / Ebar_j
+    double Ejc = kj.v[0] - Ei;
+    double z = Ejc / kj.v[0];
+    double Sc = (d.gluon[i] && d.gluon[j]) ? z : 1.0;
+    double P;
+    double Cj;
+    if (d.gluon[j]) {
+      double Bp = born_spin_correlated(d.born, kb, jb, eperp);
+      P = 2.0 * CA * ((z / (1.0 - z) + (1.0 - z) / z) * B + 2.0 * z * (1.0 - z) * Bp);
+      Cj = CA;
+    } else {
+      P = CF * (1.0 + z * z) / (1.0 - z) * B;
+      Cj = CF;
+    }
+    o.gC = 2.0 * xi * g2 / (sqs_b * Ejc) * P * Sc;
+    o.gSC = 8.0 * g2 * Cj / sb * B;
+    o.W = (o.gR - o.gS - o.gC + o.gSC) / (xi * (1.0 - y));
+  } else {
+    // ---------------- initial-state emitter (both beams) ------------------
+    for (int r = 0, b = 0; r < d.nreal; ++r) {
+      if (r == i) { bmap[r] = -1; continue; }
+      bmap[r] = b++;
+    }
+    double xmax = 1.0 - sb / (FKS_SQRT_SCAP * FKS_SQRT_SCAP);
+    double xi = xit * xmax;
+    double sr = sb / (1.0 - xi);
+    double sqr = std::sqrt(sr);
+    double Ei = 0.5 * xi * sqr;
+    double sy = std::sqrt((1.0 - y) * (1.0 + y));
+    double cphi = std::cos(phi), sphi = std::sin(phi);
+    nh[0] = sy * cphi; nh[1] = sy * sphi; nh[2] = y;
+    V4 p1{{0.5 * sqr, 0, 0, 0.5 * sqr}}, p2{{0.5 * sqr, 0, 0, -0.5 * sqr}};
+    V4 ki{{Ei, Ei * nh[0], Ei * nh[1], Ei * nh[2]}};
+    V4 K{{sqr - Ei, -ki.v[1], -ki.v[2], -ki.v[3]}};
+    for (int r = 0; r < d.nreal; ++r) {
+      if (r == 0) kreal[r] = p1;
+      else if (r == 1) kreal[r] = p2;
+      else if (r == i) kreal[r] = ki;
+      else kreal[r] = boost_to(kb[bmap[r]], K, sqs_b);
+    }
+    s_real = sr; sqs_real = sqr;
+    o.xi = xi;
+    eperp = V4{{0, cphi, sphi, 0}};
+    o.me2R = me2_event(d.real, kreal, nullptr);
+    o.S = sector_value(d, kreal, sqs_real, i, -1);
+    o.gR = xi * xi * (1.0 - y) * (1.0 + y) * o.me2R * o.S;
+    double B;
+    std::vector<double> Bkl;
+    born_correlations(d.born, kb, B, Bkl);
+    o.B = B;
+    const BornColour& bc = born_colour(d.born);
+    int nl = (int)bc.legs.size();
+    V4 n{{1.0, nh[0], nh[1], nh[2]}};
+    double eik = 0;
+    for (int a = 0; a < nl; ++a)
+      for (int b = 0; b < nl; ++b) {
+        const V4 &pa = kb[bc.legs[a]], &pb = kb[bc.legs[b]];
+        eik -= dot(pa, pb) / (dot(pa, n) * dot(pb, n)) * Bkl[a * nl + b];
+      }
+    double Ss = sector_soft(d, kb, bmap, sqs_b, nh, i, -1);
+    o.gS = (1.0 - y) * (1.0 + y) * 4.0 / sb * g2 * eik * Ss;
+    // collinear limits y -> +1 (beam 1) and y -> -1 (beam 2), x = 1 - xi
+    double x = 1.0 - xi;
+    double gc[2], gsc[2];
+    for (int side = 0; side < 2; ++side) {
+      int beam = side;                           // Born leg of the incoming parton
+      double P, Ca;
+      if (d.gluon[beam]) {
+        double Bp = born_spin_correlated(d.born, kb, beam, eperp);
+        P = 2.0 * CA * ((x / (1.0 - x) + x * (1.0 - x)) * B + 2.0 * (1.0 - x) / x * Bp);
+        Ca = CA;
+      } else {
+        P = CF * (1.0 + x * x) / (1.0 - x) * B;
+        Ca = CF;
+      }
+      gc[side] = 8.0 * xi * g2 / sb * P;          // S^coll = 1
+      gsc[side] = 16.0 * g2 * Ca / sb * B;
+    }
+    o.gC = gc[0]; o.gCm = gc[1]; o.gSC = gsc[0]; o.gSCm = gsc[1];
+    o.W = (o.gR - o.gS - 0.5 * (1.0 + y) * (o.gC - o.gSC) - 0.5 * (1.0 - y) * (o.gCm - o.gSCm))
+          / (xi * (1.0 - y) * (1.0 + y));
+  }
+  (void)s_real;
+  return o;
+}
+
+extern "C" {
+
+// FKS-subtracted real emission.  real_proc in {ee_uug, gg_ttg, gg_ttgg, uu_ttg};
+// (i, j) an FKS pair of that process (j = -1: initial state).  born_mom: SoA
+// [nborn][4][n]; xi_tilde, y, phi: [n].  out: [n][12] = xi, y, g_R, g_S, g_C,
+// g_Cm, g_SC, g_SCm, W, |M_R|^2, B, S.  real_out (optional): SoA [nreal][4][n].
+int orc_fks(int real_proc, int i, int j, int64_t n, const double* born_mom, const double* xit, const double* y,
+            const double* phi, double* out, double* real_out, int nthreads) {
+  init_colour();
+  FksDef d = fks_def(real_proc);
+  if (d.born < 0) return 1;
+  bool ok = false;
+  for (const FksPair& q : d.pairs) if (q.i == i && q.j == j) ok = true;
+  if (!ok) return 2;
+  born_colour(d.born);
+  parallel_for(n, nthreads, [&](int64_t e) {
+    V4 kb[8], kr[8];
+    load_event(born_mom, n, e, d.nborn, kb);
+    FksOut o = fks_event(d, i, j, kb, xit[e], y[e], phi[e], kr);
+    double* r = out + e * 12;
+    r[0] = o.xi; r[1] = o.y; r[2] = o.gR; r[3] = o.gS; r[4] = o.gC; r[5] = o.gCm; r[6] = o.gSC; r[7] = o.gSCm;
+    r[8] = o.W; r[9] = o.me2R; r[10] = o.B; r[11] = o.S;
+    if (real_out)
+      for (int k = 0; k < d.nreal; ++k)
+        for (int m = 0; m < 4; ++m) real_out[(k * 4 + m) * n + e] = kr[k].v[m];
+  });
+  return 0;
+}
+
+// colour-linked Borns B_kl for a Born process (legs in process order of its
+// coloured legs): out [n][nl*nl], plus B [n]
+int orc_born_correlations(int proc, int64_t n, const double* mom, double* B, double* Bkl, int* nl_out) {
+  init_colour();
+  if (proc != EE_UU && proc != GG_TT && proc != GG_TTG && proc != UU_TT) return 1;
+  const BornColour& bc = born_colour(proc);
+  int nl = (int)bc.legs.size();
+  *nl_out = nl;
+  if (n == 0) return 0;
+  parallel_for(n, 8, [&](int64_t e) {
+    V4 p[8];
+    load_event(mom, n, e, PROCS[proc].npart, p);
+    double b;
+    std::vector<double> kl;
+    born_correlations(proc, p, b, kl);
+    B[e] = b;
+    for (int q = 0; q < nl * nl; ++q) Bkl[e * nl * nl + q] = kl[q];
+  });
+  return 0;
+}
+
+}  // extern "C"
+
+extern "C" {
+// every sector function of the real process at real momenta (SoA [nreal][4][n]):
+// out [n][npairs] in the order of the process's FKS pairs
+int orc_sector_functions(int real_proc, int64_t n, const double* real_mom, double* out, int* npairs) {
+  FksDef d = fks_def(real_proc);
+  if (d.born < 0) return 1;
+  *npairs = (int)d.pairs.size();
+  for (int64_t e = 0; e < n; ++e) {
+    V4 k[8];
+    load_event(real_mom, n, e, d.nreal, k);
+    double sq = k[0].v[0] + k[1].v[0];
+    for (size_t q = 0; q < d.pairs.size(); ++q) out[e * d.pairs.size() + q] = sector_value(d, k, sq, d.pairs[q].i, d.pairs[q].j);
+  }
+  return 0;
+}
+
+// spin-correlated Born of a Born process with leg `leg`'s polarisation replaced
+// by the real vector eperp (4 doubles, upper index) -- per event, SoA momenta
+int orc_born_spin_correlated(int proc, int64_t n, const double* mom, int leg, const double* eperp, double* out) {
+  init_colour();
+  for (int64_t e = 0; e < n; ++e) {
+    V4 p[8];
+    load_event(mom, n, e, PROCS[proc].npart, p);
+    V4 ev{{eperp[4 * e], eperp[4 * e + 1], eperp[4 * e + 2], eperp[4 * e + 3]}};
+    out[e] = born_spin_correlated(proc, p, leg, ev);
+  }
+  return 0;
+}
+}

@@ -120,6 +120,48 @@ nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec,
 nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
                    nlo_prec prec, void* hip_stream);
 
+/* Outputs of nlo_subtracted: device arrays owned by the caller.  W is
+ * required; every other pointer may be NULL (not written). */
+typedef struct {
+  double* W;          /* [n] subtracted weight (g_R - g_S - g_C + g_SC)/(xi (1-y)), or the
+                         two-sided initial-state form */
+  double* xi;         /* [n] xi = xi_tilde * xi_max */
+  double* born;       /* [n] Born |M|^2 at the Born point (with its average factor) */
+  double *g_R, *g_S;  /* [n] real and soft terms */
+  double *g_C, *g_Cm; /* [n] collinear terms, y -> +1 and (initial state only) y -> -1 */
+  double *g_SC, *g_SCm; /* [n] soft-collinear terms */
+  uint8_t* status;    /* [n] bit0 non-finite W, bit1 evaluated in FP64, bit2 a mask zeroed a term */
+  double* real_mom;   /* [npart_real][4][ld] real-emission momenta in event order */
+  double* w_sum;      /* [1] fixed-order FP64 sum of W over the batch */
+} nlo_fks_out;
+
+/* FKS-subtracted real emission for one FKS sector (the paper's FKS
+ * subtraction; its branch-free loop evaluates Born, real, soft and collinear
+ * terms at every point, then zeroes those whose cuts fail).
+ *   real_proc: ee_uug (pairs (4,2), (4,3)), gg_ttg (4,-1), uu_ttg (4,-1),
+ *              gg_ttgg ((4,5), (5,4), (4,-1), (5,-1));  fks_j = -1: both beams.
+ *   born_mom:  device, Born momenta (the real process without particle
+ *              fks_i), layout above, in the Born centre-of-mass frame.
+ *   xi_tilde, y, phi: device [n] radiation variables: xi = xi_tilde * xi_max
+ *              is the energy fraction 2 k_i^0/sqrt(s_R) of parton fks_i, y the
+ *              cosine of its angle to parton fks_j (to beam 1 if fks_j = -1),
+ *              phi its azimuth about that axis.
+ *   mask:      device [4][ld] bytes for B, R, S, C (non-zero = passes its cuts)
+ *              or NULL (all pass).  A failed cut zeroes its term after
+ *              evaluation; the soft-collinear terms need both S and C.
+ *   prec:      NLO_FP64, NLO_FP32 (amplitudes in float, kinematics and
+ *              assembly in double) or NLO_MIXED (float unless
+ *              min(xi, 1-|y|) < threshold, see nlo_set_fks_threshold).
+ * Uses a workspace owned by the context (grown on the first call with a
+ * larger n after synchronising the stream); calls that overlap on different
+ * streams with the same context race. */
+nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                          const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                          const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream);
+
+/* Routing threshold of NLO_MIXED subtracted weights (default 1e-4). */
+nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold);
+
 #ifdef __cplusplus
 }
 #endif

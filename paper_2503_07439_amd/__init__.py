@@ -7,7 +7,8 @@ build-time diagram generator."""
 from . import _lib
 from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloError,  # noqa: F401
                    nlo_abi_version, nlo_create, nlo_destroy, nlo_last_error, nlo_num_processes,
-                   nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2)
+                   nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
+                   nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -56,6 +57,41 @@ class Context:
             out = torch.empty(n, dtype=torch.float64, device=mom.device)
         nlo_me2(self.ctx, proc_id(proc), n, ld, mom.data_ptr(), out.data_ptr(), PREC[prec], self._stream())
         return out
+
+    FKS_FIELDS = ("W", "xi", "born", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm")
+
+    def subtracted(self, real, fks_i, fks_j, born_mom, xi_tilde, y, phi, prec="fp64", mask=None,
+                   want_real=False, want_sum=False):
+        """FKS-subtracted real emission.  born_mom: float64 CUDA tensor
+        [npart_born, 4, n]; xi_tilde, y, phi: float64 CUDA [n]; mask: uint8
+        CUDA [4, n] or None.  Returns a dict of CUDA tensors."""
+        import torch
+        npart, _, n = born_mom.shape
+        dev = born_mom.device
+        res = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in self.FKS_FIELDS}
+        res["status"] = torch.empty(n, dtype=torch.uint8, device=dev)
+        out = nlo_fks_out()
+        for k in self.FKS_FIELDS:
+            setattr(out, k, res[k].data_ptr())
+        out.status = res["status"].data_ptr()
+        if want_real:
+            res["real_mom"] = torch.empty((npart + 1, 4, n), dtype=torch.float64, device=dev)
+            out.real_mom = res["real_mom"].data_ptr()
+        if want_sum:
+            res["w_sum"] = torch.empty(1, dtype=torch.float64, device=dev)
+            out.w_sum = res["w_sum"].data_ptr()
+        for t in (born_mom, xi_tilde, y, phi):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        mptr = 0
+        if mask is not None:
+            assert mask.dtype == torch.uint8 and mask.shape == (4, n) and mask.is_contiguous()
+            mptr = mask.data_ptr()
+        nlo_subtracted(self.ctx, proc_id(real), fks_i, fks_j, n, n, born_mom.data_ptr(), xi_tilde.data_ptr(),
+                       y.data_ptr(), phi.data_ptr(), mptr, PREC[prec], out, self._stream())
+        return res
+
+    def set_fks_threshold(self, thr):
+        nlo_set_fks_threshold(self.ctx, thr)
 
     def set_kernel_config(self, proc, prec, block, colour_mode=0):
         nlo_set_kernel_config(self.ctx, proc_id(proc), PREC[prec], block, colour_mode)

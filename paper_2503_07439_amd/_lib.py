@@ -29,6 +29,13 @@ class nlo_kernel_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("colour_mode", ctypes.c_int)]
 
 
+class nlo_fks_out(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("born", ctypes.c_void_p),
+                ("g_R", ctypes.c_void_p), ("g_S", ctypes.c_void_p), ("g_C", ctypes.c_void_p),
+                ("g_Cm", ctypes.c_void_p), ("g_SC", ctypes.c_void_p), ("g_SCm", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("real_mom", ctypes.c_void_p), ("w_sum", ctypes.c_void_p)]
+
+
 class NloError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("nlome status %d: %s" % (status, msg))
@@ -50,6 +57,9 @@ SIGNATURES = {
     "nlo_set_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
     "nlo_get_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
     "nlo_me2": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "nlo_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
+                        ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
+    "nlo_set_fks_threshold": ([_VP, ctypes.c_double], ctypes.c_int),
 }
 
 
@@ -116,3 +126,13 @@ def nlo_get_kernel_config(ctx, proc_id, prec):
 
 def nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr):
     return check(lib().nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr))
+
+
+def nlo_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, mask_ptr, prec, out,
+                   stream_ptr):
+    return check(lib().nlo_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr,
+                                      mask_ptr, prec, ctypes.byref(out), stream_ptr))
+
+
+def nlo_set_fks_threshold(ctx, threshold):
+    return check(lib().nlo_set_fks_threshold(ctx, threshold))

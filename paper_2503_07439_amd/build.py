@@ -33,10 +33,15 @@ def generate():
 def _deps(src):
     """Sources an object depends on: the unit, the shared headers and, for a
     process unit, its generated header."""
-    deps = [src] + [os.path.join(CSRC, h) for h in ("helas.hpp", "kernels.hpp", "launch.hpp")]
+    deps = [src] + [os.path.join(CSRC, h) for h in ("helas.hpp", "kernels.hpp", "launch.hpp", "fks.hpp")]
     deps.append(os.path.join(ROOT, "include", "nlome.h"))
     base = os.path.basename(src)
-    if base.startswith("tu_"):
+    if base.startswith("tu_fks_"):
+        stem = base[3:].rsplit("_", 1)[0]
+        deps.append(os.path.join(os.path.dirname(src), stem + ".hpp"))
+        real = stem[4:].rsplit("_", 2)[0]
+        deps.append(os.path.join(os.path.dirname(src), real + ".hpp"))
+    elif base.startswith("tu_"):
         deps.append(os.path.join(os.path.dirname(src), base[3:].rsplit("_", 1)[0] + ".hpp"))
     else:
         deps.append(os.path.join(CSRC, "generated", "index.hpp"))
@@ -64,7 +69,7 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     os.makedirs(OBJ, exist_ok=True)
     srcs = [os.path.join(CSRC, "capi.hip")] + list(tus)
     # the largest process first so the long poles start early
-    srcs.sort(key=lambda p: 0 if "gg_ttgg" in p else (1 if "gg_ttg" in p else 2))
+    srcs.sort(key=lambda p: 0 if ("gg_ttgg" in p and "fks" not in p) else (1 if "gg_ttg" in p else 2))
     jobs = jobs or min(16, os.cpu_count() or 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra_flags, verbose, force), srcs))

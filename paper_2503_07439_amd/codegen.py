@@ -680,6 +680,69 @@ def cholesky_lower(C):
     return np.linalg.cholesky(C)
 
 
+FKS_BORNS = ("ee_uu", "gg_tt", "uu_tt", "gg_ttg")
+
+
+def _charge(t, pos, kind, a):
+    """Colour charge T^a of one leg applied to a colour tensor: T^a on a
+    fundamental (row) index, -(T^a)^T on an antifundamental (column) index,
+    -i f^{a..} on an adjoint index."""
+    if kind == "r":
+        M = TGEN[a]
+    elif kind == "c":
+        M = -TGEN[a].T
+    else:
+        M = -1j * FSTR[a]
+    t = np.moveaxis(t, pos, 0)
+    return np.moveaxis(np.tensordot(M, t, axes=([1], [0])), 0, pos)
+
+
+def colour_correlators(p):
+    """C^(kl)_{ab} = <flow a| T_k . T_l |flow b> over the coloured legs."""
+    legs = p.coloured_legs()
+    kinds = ["g" if p.itype[k] == "g" else ("r" if is_antifermion(p.itype[k]) else "c") for k in legs]
+    nl, nf = len(legs), len(p.flows)
+    C = np.zeros((nl, nl, nf, nf), complex)
+    for k in range(nl):
+        for l in range(nl):
+            for b in range(nf):
+                for a8 in range(8):
+                    t2 = _charge(_charge(p.flows[b], l, kinds[l], a8), k, kinds[k], a8)
+                    for a in range(nf):
+                        C[k, l, a, b] += np.vdot(p.flows[a], t2)
+    assert np.abs(C.imag).max() < 1e-12
+    C = C.real
+    assert np.abs(C.sum(axis=1)).max() < 1e-11          # colour conservation
+    return legs, C
+
+
+def emit_colour_corr(p):
+    """Code for B_kl = sum_ab C^(kl)_ab rho_ab from the helicity-summed real
+    symmetric density rho (packed upper triangle, row-major)."""
+    legs, C = colour_correlators(p)
+    nf = len(p.flows)
+    L = ["  static constexpr int NCL = %d;" % len(legs),
+         "  static constexpr int CLEG[NCL] = {%s};" % ", ".join(str(k) for k in legs),
+         "  static constexpr int NRHO = %d;" % (nf * (nf + 1) // 2),
+         "  template <class D> NLO_HD static void colour_corr(const D (&rho)[NRHO], D (&bkl)[NCL][NCL]) {"]
+    for k in range(len(legs)):
+        for l in range(len(legs)):
+            if l < k:
+                L.append("    bkl[%d][%d] = bkl[%d][%d];" % (k, l, l, k))
+                continue
+            terms = []
+            idx = 0
+            for a in range(nf):
+                for b in range(a, nf):
+                    c = C[k, l, a, b] * (1.0 if a == b else 2.0)
+                    if abs(c) > 1e-14:
+                        terms.append("D(%.17g) * rho[%d]" % (c, idx))
+                    idx += 1
+            L.append("    bkl[%d][%d] = %s;" % (k, l, " + ".join(terms) if terms else "D(0)"))
+    L.append("  }")
+    return L
+
+
 def emit_process(p):
     """HIP source for one process (a struct with static device functions)."""
     good = p.good_helicities()
@@ -759,7 +822,9 @@ def emit_process(p):
         L.append("    }")
     L.append("  }")
     # amplitudes for one helicity
-    L.append("  template <class T> NLO_HD static void amplitudes(const Pre<T>& s, int h, T mt, cx<T> (&J)[NFLOW]) {")
+    L.append("  // OVR >= 0: the external wavefunction of leg OVR is replaced by *ov")
+    L.append("  template <class T, int OVR = -1> NLO_HD static void amplitudes(const Pre<T>& s, int h, T mt, cx<T> (&J)[NFLOW],")
+    L.append("                                                       const w4<T>* ov = nullptr) {")
     L.append("    for (int f = 0; f < NFLOW; ++f) J[f] = czero<T>();")
     for n in p.nodes:
         v = "v%d" % n.id
@@ -769,15 +834,14 @@ def emit_process(p):
             t = n.ptype
             out = k >= nin
             if t in ("g", "a"):
-                L.append("    const w4<T> %s = wf_eps(s.x%d, %s, %s);" % (v, k, bit, "true" if out else "false"))
+                expr = "wf_eps(s.x%d, %s, %s)" % (k, bit, "true" if out else "false")
             elif is_fermion(t):
                 # column spinor: incoming fermion u(p) or outgoing antifermion v(p)
-                fn = "wf_v" if out else "wf_u"
-                L.append("    const w4<T> %s = %s(s.x%d, %s);" % (v, fn, k, bit))
+                expr = "%s(s.x%d, %s)" % ("wf_v" if out else "wf_u", k, bit)
             else:
                 # row spinor: outgoing fermion ubar(p) or incoming antifermion vbar(p)
-                fn = "wf_u" if out else "wf_v"
-                L.append("    const w4<T> %s = wf_bar(%s(s.x%d, %s));" % (v, fn, k, bit))
+                expr = "wf_bar(%s(s.x%d, %s))" % ("wf_u" if out else "wf_v", k, bit)
+            L.append("    const w4<T> %s = (OVR == %d) ? *ov : %s;" % (v, k, expr))
             continue
         ch = ["v%d" % c.id for c in n.children]
         Q = "s.Q[%d]" % mslot[n.legs]
@@ -831,6 +895,8 @@ def emit_process(p):
     L.append("    return m2;")
     L.append("  }")
     # transposed Cholesky factor for the matrix-core colour contraction: LT[k][j] = L[j][k]
+    if p.name in FKS_BORNS:
+        L.extend(emit_colour_corr(p))
     L.append("  static constexpr float LT[%d][%d] = {%s};" % (
         nflow, nflow, ", ".join("{" + ", ".join("%.9ef" % Lc[j, k] for j in range(nflow)) + "}" for k in range(nflow))))
     L.append("};")
@@ -847,6 +913,53 @@ def _write_if_changed(path, src):
             f.write(src)
 
 
+# FKS sectors: (real process, Born process, I, J (-1: both beams), all FKS pairs of the real process)
+FKS_SECTORS = [
+    ("ee_uug", "ee_uu", 4, 2, [(4, 2), (4, 3)]),
+    ("ee_uug", "ee_uu", 4, 3, [(4, 2), (4, 3)]),
+    ("gg_ttg", "gg_tt", 4, -1, [(4, -1)]),
+    ("uu_ttg", "uu_tt", 4, -1, [(4, -1)]),
+    ("gg_ttgg", "gg_ttg", 4, 5, [(4, 5), (5, 4), (4, -1), (5, -1)]),
+    ("gg_ttgg", "gg_ttg", 5, 4, [(4, 5), (5, 4), (4, -1), (5, -1)]),
+    ("gg_ttgg", "gg_ttg", 4, -1, [(4, 5), (5, 4), (4, -1), (5, -1)]),
+    ("gg_ttgg", "gg_ttg", 5, -1, [(4, 5), (5, 4), (4, -1), (5, -1)]),
+]
+
+
+def sector_name(real, i, j):
+    return "fks_%s_%d_%s" % (real, i, "0" if j < 0 else str(j))
+
+
+def emit_sector(procs, real, born, i, j, pairs):
+    R = procs[real]
+    B = procs[born]
+    nr, nb = R.npart, B.npart
+    bmap = []
+    b = 0
+    for r in range(nr):
+        if r == i:
+            bmap.append(-1)
+        else:
+            bmap.append(b)
+            b += 1
+    gluon = [R.itype[r] == "g" for r in range(nr)]
+    name = sector_name(real, i, j)
+    L = ["struct %s {" % name,
+         "  using Real = %s;" % real,
+         "  using Born = %s;" % born,
+         "  static constexpr int I = %d, J = %d, JB = %d, NR = %d, NB = %d, NPAIR = %d;"
+         % (i, j, bmap[j] if j >= 0 else -1, nr, nb, len(pairs)),
+         "  static constexpr int BMAP[NR] = {%s};" % ", ".join(str(x) for x in bmap),
+         "  static constexpr int PI[NPAIR] = {%s};" % ", ".join(str(a) for a, _ in pairs),
+         "  static constexpr int PJ[NPAIR] = {%s};" % ", ".join(str(c) for _, c in pairs),
+         "  static constexpr bool GLUON[NR] = {%s};" % ", ".join("true" if g else "false" for g in gluon),
+         "  static constexpr bool J_GLUON = %s;" % ("true" if j >= 0 and gluon[j] else "false"),
+         "  static constexpr bool BEAM_GLUON0 = %s, BEAM_GLUON1 = %s;"
+         % ("true" if B.itype[0] == "g" else "false", "true" if B.itype[1] == "g" else "false"),
+         "};"]
+    return name, "\n".join(L)
+
+
 def generate(out_dir):
     """Write one header per process, one translation unit per (process,
     kernel variant) and an index consumed by the C ABI.  Returns the list of
@@ -854,7 +967,8 @@ def generate(out_dir):
     procs = process_list()
     os.makedirs(out_dir, exist_ok=True)
     tus = []
-    index = ["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "../launch.hpp"', "namespace nlo {"]
+    index = ["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "../launch.hpp"',
+             '#include "../fks.hpp"', "namespace nlo {"]
     for p in procs:
         p.enumerate()
         p.colour()
@@ -881,6 +995,38 @@ def generate(out_dir):
     index.append("static const me2_launcher ME2_LAUNCH[NPROC][NVAR] = {")
     for p in procs:
         index.append("  {%s}," % ", ".join("me2_%s_%d" % (p.name, v) for v in range(len(VARIANTS))))
+    index.append("};")
+    # FKS sectors
+    byname = {p.name: p for p in procs}
+    index.append("struct FksSector {")
+    index.append("  const char* name; int real, born, i, j;")
+    index.append("  hipError_t (*map)(const FksArgs&, int, hipStream_t);")
+    index.append("  hipError_t (*born_fn[2])(const FksArgs&, int, int, hipStream_t);   // [0] double, [1] float")
+    index.append("};")
+    decl, rows = [], []
+    pid = {p.name: k for k, p in enumerate(procs)}
+    for real, born, i, j, pairs in FKS_SECTORS:
+        name, struct = emit_sector(byname, real, born, i, j, pairs)
+        hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "%s.hpp"' % real,
+                          '#include "%s.hpp"' % born, "namespace nlo {", struct, "}  // namespace nlo", ""])
+        _write_if_changed(os.path.join(out_dir, name + ".hpp"), hdr)
+        for v, T in enumerate(("double", "float")):
+            body = ['#include "../fks.hpp"', '#include "%s.hpp"' % name, "namespace nlo {"]
+            if v == 0:
+                body.append("hipError_t %s_map(const FksArgs& a, int block, hipStream_t st) { return launch_fks_map<%s>(a, block, st); }" % (name, name))
+            body.append("hipError_t %s_born%d(const FksArgs& a, int which, int block, hipStream_t st) { return launch_fks_born<%s, %s>(a, which, block, st); }" % (name, v, name, T))
+            body.append("}  // namespace nlo")
+            path = os.path.join(out_dir, "tu_%s_%d.hip" % (name, v))
+            _write_if_changed(path, "\n".join(["// GENERATED by codegen.py -- do not edit."] + body + [""]))
+            tus.append(path)
+        decl.append("hipError_t %s_map(const FksArgs&, int, hipStream_t);" % name)
+        decl.append("hipError_t %s_born0(const FksArgs&, int, int, hipStream_t);" % name)
+        decl.append("hipError_t %s_born1(const FksArgs&, int, int, hipStream_t);" % name)
+        rows.append('  {"%s", %d, %d, %d, %d, %s_map, {%s_born0, %s_born1}},' % (name, pid[real], pid[born], i, j, name, name, name))
+    index.extend(decl)
+    index.append("constexpr int NFKS = %d;" % len(FKS_SECTORS))
+    index.append("static const FksSector FKS_TABLE[NFKS] = {")
+    index.extend(rows)
     index.append("};")
     index.append("}  // namespace nlo")
     _write_if_changed(os.path.join(out_dir, "index.hpp"), "\n".join(index) + "\n")

@@ -43,6 +43,10 @@ struct nlo_ctx {
   nlo_params params;
   std::mutex mu;
   nlo_kernel_config cfg[NPROC_][5];
+  double fks_thr = 1e-4;
+  // FKS workspace: real momenta, real |M|^2, bucket permutation, bucket sizes
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
 };
 
 namespace {
@@ -133,7 +137,105 @@ nlo_status nlo_create(nlo_ctx** out, const nlo_params* params) {
 }
 
 nlo_status nlo_destroy(nlo_ctx* ctx) {
+  if (ctx && ctx->ws) (void)hipFree(ctx->ws);
   delete ctx;
+  return NLO_OK;
+}
+
+nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold) {
+  if (!ctx) return fail(NLO_EINVAL, "nlo_set_fks_threshold: ctx is NULL");
+  if (!(threshold >= 0.0) || !(threshold <= 1.0))
+    return fail(NLO_EINVAL, "nlo_set_fks_threshold: threshold must be in [0, 1]");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->fks_thr = threshold;
+  return NLO_OK;
+}
+
+nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                          const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                          const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream) {
+  nlo_status st = check_ctx(ctx, real_proc, "nlo_subtracted");
+  if (st) return st;
+  const FksSector* sec = nullptr;
+  for (const FksSector& f : FKS_TABLE)
+    if (f.real == real_proc && f.i == fks_i && f.j == fks_j) sec = &f;
+  if (!sec)
+    return fail(NLO_EUNSUPPORTED, "nlo_subtracted: no FKS sector (%d, %d) for process %s", fks_i, fks_j,
+                PROC_STATIC[real_proc].name);
+  if (n < 0) return fail(NLO_EINVAL, "nlo_subtracted: n = %lld < 0", (long long)n);
+  if (ld < n) return fail(NLO_EINVAL, "nlo_subtracted: ld = %lld < n = %lld", (long long)ld, (long long)n);
+  if (n > 0x7fffffffLL) return fail(NLO_EINVAL, "nlo_subtracted: n too large");
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "nlo_subtracted: precision %d not supported (FP64, FP32, MIXED)", (int)prec);
+  if (!out) return fail(NLO_EINVAL, "nlo_subtracted: out is NULL");
+  if (n == 0) return NLO_OK;
+  if (!born_mom || !xi_tilde || !y || !phi || !out->W) return fail(NLO_EINVAL, "nlo_subtracted: NULL device pointer");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, "nlo_subtracted");
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nr = PROC_STATIC[real_proc].npart;
+  const size_t need = (size_t)n * (nr * 4 + 1) * sizeof(double) + (size_t)n * sizeof(unsigned) + 64;
+  if (need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      if (hipStreamSynchronize(s) != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: stream sync failed");
+      (void)hipFree(ctx->ws);
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+      ctx->ws = nullptr;
+      return fail(NLO_ENOMEM, "nlo_subtracted: workspace of %zu bytes", need);
+    }
+    ctx->ws_bytes = need;
+  }
+  char* base = static_cast<char*>(ctx->ws);
+  FksArgs a{};
+  a.n = n;
+  a.ld = ld;
+  a.born = born_mom;
+  a.xit = xi_tilde;
+  a.y = y;
+  a.phi = phi;
+  a.mask = mask;
+  a.real = reinterpret_cast<double*>(base);
+  a.me2r = a.real + (size_t)n * nr * 4;
+  a.inv = reinterpret_cast<unsigned*>(a.me2r + n);
+  a.cnt = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(a.inv + n) + (64 - ((n * sizeof(unsigned)) % 64)) % 64);
+  a.thr = ctx->fks_thr;
+  a.mode = prec == NLO_FP64 ? 1 : (prec == NLO_FP32 ? 0 : 2);
+  a.scale_b = coupling_scale(sec->born, ctx->params);
+  a.g2 = 4.0 * M_PI * ctx->params.alpha_s;
+  a.mt = ctx->params.m_top;
+  a.xi_out = out->xi;
+  a.born_out = out->born;
+  a.gR = out->g_R;
+  a.gS = out->g_S;
+  a.gC = out->g_C;
+  a.gCm = out->g_Cm;
+  a.gSC = out->g_SC;
+  a.gSCm = out->g_SCm;
+  a.W = out->W;
+  a.status = out->status;
+  a.real_out = out->real_mom;
+  const int block = 256;
+  hipError_t err = sec->map(a, block, s);
+  // real |M|^2 per bucket: FP32 (matrix-core colour in MIXED) from the front, FP64 from the back
+  const nlo_kernel_config& kc = ctx->cfg[real_proc][prec];
+  LaunchArgs la{n, n, a.real, a.me2r, coupling_scale(real_proc, ctx->params), ctx->params.m_top, kc.block, s,
+                a.cnt, 0};
+  if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][a.mode == 2 ? VAR_MFMA : VAR_F32](la);
+  if (err == hipSuccess && a.mode != 0) {
+    la.which = 1;
+    err = ME2_LAUNCH[real_proc][VAR_F64](la);
+  }
+  if (err == hipSuccess && a.mode != 1) err = sec->born_fn[1](a, 0, block, s);
+  if (err == hipSuccess && a.mode != 0) err = sec->born_fn[0](a, 1, block, s);
+  if (err == hipSuccess && out->w_sum) {
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, s, n, (const double*)out->W, out->w_sum);
+    err = hipGetLastError();
+  }
+  if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: launch failed: %s", hipGetErrorString(err));
   return NLO_OK;
 }
 

@@ -1,0 +1,438 @@
+// FKS-subtracted real emission on the GPU (the paper's FKS subtraction and
+// the branch-free evaluation of Born, real, soft and collinear terms per
+// phase-space point, with masks applied afterwards).
+//
+// Per FKS sector (real process R, Born process B, FKS pair (I, J), J < 0 for
+// the initial state) three launches:
+//  1. k_fks_map (FP64): Born momenta + (xi_tilde, y, phi) -> real momenta,
+//     written to a workspace in bucket order (FP32 bucket from the front,
+//     FP64 bucket from the back) with the inverse permutation;
+//  2. the |M|^2 kernels of R on each bucket, each in its own precision;
+//  3. k_fks_born (per bucket, T = float or double): recomputes the FP64
+//     kinematics, evaluates B, the colour-linked Borns B_kl (from the
+//     helicity-summed density of the flow vector) and the spin-correlated Born
+//     with the emitter polarisation replaced by the transverse unit vector,
+//     then assembles the counterterms and the subtracted weight in FP64.
+//
+// Reading of the conventions (the paper leaves them open):
+//   xi = 2 k_i^0/sqrt(s_R); y = cos(k_i, k_j) (final J) or cos(k_i, beam 1);
+//   phi = azimuth about the emitter measured from the (emitter, z) plane.
+//   FSR: xi_max = 1 - M_rec^2/s; recoilers boosted along the emitter axis.
+//   ISR: xi_max = 1 - s_B/s_cap (sqrt(s_cap) = 4000 GeV), s_R = s_B/(1-xi),
+//        Born final state pure-boosted to K = p1 + p2 - k_i.
+//   f(xi,y) = xi^2 (1-y) |M_R|^2 S  (FSR),  xi^2 (1-y^2) |M_R|^2 S  (ISR)
+//   W_FSR = [f - f(0,y) - f(xi,1) + f(0,1)] / (xi (1-y))
+//   W_ISR = [f - f(0,y) - (1+y)/2 (f(xi,1)-f(0,1)) - (1-y)/2 (f(xi,-1)-f(0,-1))] / (xi (1-y^2))
+//   Sector functions S = (h_IJ/d_IJ)/sum_pairs(h/d), d = xi_k xi_l (1-y_kl)
+//   or xi_k (1-y_k^2) for the beams, h = xi_l/(xi_k+xi_l) for gluon pairs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "helas.hpp"
+#include "launch.hpp"
+
+namespace nlo {
+
+constexpr double FKS_SCAP = 4000.0 * 4000.0;   // notional hadronic s for the ISR xi_max
+constexpr double FKS_CF = 4.0 / 3.0, FKS_CA = 3.0;
+
+struct FksKin {
+  double xi, y, sqs_b, sb, sqs_r;
+  double nh[3];   // direction of parton I (soft limit)
+  double ep[3];   // transverse unit vector of the collinear limit
+  double ejc, z;  // FSR: E_J at y = 1 and its momentum fraction there
+};
+
+__device__ __forceinline__ double d3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ __forceinline__ double mink(const double* a, const double* b) {
+  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+// unit vectors orthogonal to kh: e1 in the plane of kh and z, e2 = kh x e1
+__device__ __forceinline__ void fks_perp(const double* kh, double* e1, double* e2) {
+  const double st = sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
+  const double ct = kh[2];
+  const double cp = st > 0.0 ? kh[0] / st : 1.0, sp = st > 0.0 ? kh[1] / st : 0.0;
+  e1[0] = ct * cp; e1[1] = ct * sp; e1[2] = -st;
+  e2[0] = -sp; e2[1] = cp; e2[2] = 0.0;
+}
+
+// real kinematics of one event
+template <class S>
+__device__ void fks_map(const double (&kb)[S::NB][4], double xit, double y, double phi, double (&kr)[S::NR][4],
+                        FksKin& K) {
+  K.y = y;
+  K.sqs_b = kb[0][0] + kb[1][0];
+  K.sb = K.sqs_b * K.sqs_b;
+  const double sy = sqrt((1.0 - y) * (1.0 + y));
+  double cphi, sphi;
+  sincos(phi, &sphi, &cphi);
+  if constexpr (S::J >= 0) {
+    const double* kj = kb[S::JB];
+    const double sq = K.sqs_b;
+    const double rec[4] = {sq - kj[0], -kj[1], -kj[2], -kj[3]};
+    const double mrec2 = mink(rec, rec);
+    const double xi = xit * (1.0 - mrec2 / K.sb);
+    const double ei = 0.5 * xi * sq;
+    const double ej = (K.sb - mrec2 - 2.0 * sq * ei) / (2.0 * sq - 2.0 * ei * (1.0 - y));
+    const double kabs = sqrt(ei * ei + ej * ej + 2.0 * ei * ej * y);
+    const double kjabs = sqrt(d3(kj + 1, kj + 1));
+    const double kh[3] = {kj[1] / kjabs, kj[2] / kjabs, kj[3] / kjabs};
+    double e1[3], e2[3];
+    fks_perp(kh, e1, e2);
+    const double cti = (ei + ej * y) / kabs, sti = ej * sy / kabs;
+    double kid[3];
+    for (int m = 0; m < 3; ++m) {
+      K.ep[m] = cphi * e1[m] + sphi * e2[m];
+      kid[m] = cti * kh[m] + sti * K.ep[m];
+      K.nh[m] = y * kh[m] + sy * K.ep[m];
+    }
+    // recoil: light-cone component E + p.u along u = -kh scaled by rho
+    const double rho = (sq - ei - ej + kabs) / (sq - kj[0] + kjabs);
+#pragma unroll
+    for (int r = 0; r < S::NR; ++r) {
+      if (r == S::I) {
+        kr[r][0] = ei;
+        for (int m = 0; m < 3; ++m) kr[r][1 + m] = ei * kid[m];
+      } else if (r == S::J) {
+        kr[r][0] = ej;
+        for (int m = 0; m < 3; ++m) kr[r][1 + m] = kabs * kh[m] - ei * kid[m];
+      } else {
+        const double* p = kb[S::BMAP[r]];
+        if (r < 2) {
+          for (int m = 0; m < 4; ++m) kr[r][m] = p[m];
+        } else {
+          const double pl = -d3(p + 1, kh);
+          const double pp = p[0] + pl, pm = p[0] - pl;
+          const double e2n = 0.5 * (rho * pp + pm / rho), pl2 = 0.5 * (rho * pp - pm / rho);
+          kr[r][0] = e2n;
+          for (int m = 0; m < 3; ++m) kr[r][1 + m] = p[1 + m] - (pl2 - pl) * kh[m];
+        }
+      }
+    }
+    K.xi = xi;
+    K.sqs_r = sq;
+    K.ejc = kj[0] - ei;
+    K.z = K.ejc / kj[0];
+  } else {
+    const double xi = xit * (1.0 - K.sb / FKS_SCAP);
+    const double sr = K.sb / (1.0 - xi);
+    const double sqr = sqrt(sr);
+    const double ei = 0.5 * xi * sqr;
+    K.nh[0] = sy * cphi; K.nh[1] = sy * sphi; K.nh[2] = y;
+    K.ep[0] = cphi; K.ep[1] = sphi; K.ep[2] = 0.0;
+    // pure boost from the Born rest frame to K = p1 + p2 - k_i (K^2 = s_B)
+    const double Kv[4] = {sqr - ei, -ei * K.nh[0], -ei * K.nh[1], -ei * K.nh[2]};
+    const double M = K.sqs_b;
+#pragma unroll
+    for (int r = 0; r < S::NR; ++r) {
+      if (r == 0 || r == 1) {
+        kr[r][0] = 0.5 * sqr; kr[r][1] = 0.0; kr[r][2] = 0.0; kr[r][3] = r == 0 ? 0.5 * sqr : -0.5 * sqr;
+      } else if (r == S::I) {
+        kr[r][0] = ei;
+        for (int m = 0; m < 3; ++m) kr[r][1 + m] = ei * K.nh[m];
+      } else {
+        const double* p = kb[S::BMAP[r]];
+        const double bp = (Kv[1] * p[1] + Kv[2] * p[2] + Kv[3] * p[3]) / M;
+        kr[r][0] = (Kv[0] * p[0]) / M + bp;
+        const double f = p[0] / M + bp / (Kv[0] + M);
+        for (int m = 0; m < 3; ++m) kr[r][1 + m] = p[1 + m] + f * Kv[1 + m];
+      }
+    }
+    K.xi = xi;
+    K.sqs_r = sqr;
+    K.ejc = 0.0;
+    K.z = 0.0;
+  }
+}
+
+// sector function of the pair (I, J) at the real point
+template <class S>
+__device__ double fks_sector(const double (&k)[S::NR][4], double sqs) {
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int q = 0; q < S::NPAIR; ++q) {
+    const int a = S::PI[q], b = S::PJ[q];
+    const double xa = 2.0 * k[a][0] / sqs;
+    const double pa = sqrt(d3(k[a] + 1, k[a] + 1));
+    double t;
+    if (b < 0) {
+      const double ya = k[a][3] / pa;
+      t = 1.0 / (xa * (1.0 - ya) * (1.0 + ya));
+    } else {
+      const double xb = 2.0 * k[b][0] / sqs;
+      const double pb = sqrt(d3(k[b] + 1, k[b] + 1));
+      const double yab = d3(k[a] + 1, k[b] + 1) / (pa * pb);
+      const double h = (S::GLUON[a] && S::GLUON[b]) ? xb / (xa + xb) : 1.0;
+      t = h / (xa * xb * (1.0 - yab));
+    }
+    den += t;
+    if (a == S::I && b == S::J) num = t;
+  }
+  return num / den;
+}
+
+// its soft limit: parton I along nh, the others at their Born momenta
+template <class S>
+__device__ double fks_sector_soft(const double (&kb)[S::NB][4], const double* nh, double sqs_b) {
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int q = 0; q < S::NPAIR; ++q) {
+    if (S::PI[q] != S::I) continue;
+    const int b = S::PJ[q];
+    double t;
+    if (b < 0) {
+      t = 1.0 / ((1.0 - nh[2]) * (1.0 + nh[2]));
+    } else {
+      const double* p = kb[S::BMAP[b]];
+      const double y = d3(nh, p + 1) / sqrt(d3(p + 1, p + 1));
+      t = 1.0 / ((2.0 * p[0] / sqs_b) * (1.0 - y));
+    }
+    den += t;
+    if (b == S::J) num = t;
+  }
+  return num / den;
+}
+
+// ---------------------------------------------------------------------------
+// launch arguments
+// ---------------------------------------------------------------------------
+struct FksArgs {
+  int64_t n, ld;                       // events, leading dimension of the caller's arrays
+  const double* born;                  // [NB][4][ld]
+  const double *xit, *y, *phi;         // [n]
+  const uint8_t* mask;                 // [4][ld] for B, R, S, C or null
+  double* real;                        // workspace [NR][4][n], bucket order
+  double* me2r;                        // workspace [n], bucket order
+  unsigned* inv;                       // workspace [n]: bucket position -> event
+  unsigned* cnt;                       // workspace [2]: FP32 and FP64 bucket sizes
+  double thr;                          // route to FP64 when min(xi, 1-|y|) < thr
+  int mode;                            // 0: all FP32, 1: all FP64, 2: route
+  double scale_b, g2, mt;
+  double *xi_out, *born_out, *gR, *gS, *gC, *gCm, *gSC, *gSCm, *W;   // [n], any may be null but W
+  uint8_t* status;                     // [n] or null
+  double* real_out;                    // [NR][4][ld] (event order) or null
+};
+
+template <class S>
+__device__ __forceinline__ void load_born(const FksArgs& a, int64_t e, double (&kb)[S::NB][4]) {
+#pragma unroll
+  for (int k = 0; k < S::NB; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) kb[k][m] = a.born[(k * 4 + m) * a.ld + e];
+}
+
+static __global__ void k_fks_zero(unsigned* cnt) {
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0u;
+}
+
+// 1. map and route
+template <class S>
+__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_map(FksArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = e < a.n;
+  double kb[S::NB][4], kr[S::NR][4];
+  FksKin K;
+  bool f64 = false;
+  if (act) {
+    load_born<S>(a, e, kb);
+    fks_map<S>(kb, a.xit[e], a.y[e], a.phi[e], kr, K);
+    const double dist = fmin(K.xi, 1.0 - fabs(K.y));
+    f64 = (a.mode == 1) || (a.mode == 2 && !(dist >= a.thr));
+  }
+  // wave-aggregated bucket positions
+  const unsigned long long m64 = __ballot(act && f64), m32 = __ballot(act && !f64);
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+  unsigned b32 = 0, b64 = 0;
+  if (lane == 0) {
+    if (m32) b32 = atomicAdd(&a.cnt[0], (unsigned)__popcll(m32));
+    if (m64) b64 = atomicAdd(&a.cnt[1], (unsigned)__popcll(m64));
+  }
+  b32 = __shfl(b32, 0);
+  b64 = __shfl(b64, 0);
+  if (!act) return;
+  const int64_t pos = f64 ? a.n - 1 - (int64_t)(b64 + __popcll(m64 & lower)) : (int64_t)(b32 + __popcll(m32 & lower));
+  a.inv[pos] = (unsigned)e;
+#pragma unroll
+  for (int k = 0; k < S::NR; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a.real[(k * 4 + m) * a.n + pos] = kr[k][m];
+  if (a.real_out) {
+#pragma unroll
+    for (int k = 0; k < S::NR; ++k)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) a.real_out[(k * 4 + m) * a.ld + e] = kr[k][m];
+  }
+}
+
+// spin-correlated Born: leg LEG's polarisation replaced by (0, ep), summed
+// over the other helicities
+template <class BP, int LEG, class T>
+__device__ double born_spin(const typename BP::template Pre<T>& s, const double* ep, T mt) {
+  const w4<T> ov = {{cx<T>{T(0), T(0)}, cx<T>{T(ep[0]), T(0)}, cx<T>{T(ep[1]), T(0)}, cx<T>{T(ep[2]), T(0)}}};
+  double acc = 0.0;
+#pragma unroll 1
+  for (int h = 0; h < BP::NHEL; ++h) {
+    if ((h >> (BP::NPART - 1 - LEG)) & 1) continue;
+    cx<T> J[BP::NFLOW];
+    BP::template amplitudes<T, LEG>(s, h, mt, J, &ov);
+    acc += (double)BP::colour_sum(J);
+  }
+  return acc;
+}
+
+// 3. Born correlations, counterterms and subtracted weight for one bucket
+template <class S, class T>
+__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which) {
+  using BP = typename S::Born;
+  const int64_t lo = which == 0 ? 0 : a.n - (int64_t)a.cnt[1];
+  const int64_t hi = which == 0 ? (int64_t)a.cnt[0] : a.n;
+  const int64_t pos = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= hi) return;
+  const int64_t e = a.inv[pos];
+  double kb[S::NB][4], kr[S::NR][4];
+  FksKin K;
+  load_born<S>(a, e, kb);
+  fks_map<S>(kb, a.xit[e], a.y[e], a.phi[e], kr, K);
+  const double S_real = fks_sector<S>(kr, K.sqs_r);
+
+  // Born: |M|^2 and the helicity-summed density of the flow vector
+  typename BP::template Pre<T> s;
+  BP::prologue(kb, s, a.mt);
+  double rho[BP::NRHO];
+#pragma unroll
+  for (int q = 0; q < BP::NRHO; ++q) rho[q] = 0.0;
+  double bsum = 0.0;
+#pragma unroll 1
+  for (int ih = 0; ih < BP::NGOOD; ++ih) {
+    cx<T> J[BP::NFLOW];
+    BP::amplitudes(s, BP::good(ih), T(a.mt), J);
+    bsum += (double)BP::colour_sum(J);
+    int q = 0;
+#pragma unroll
+    for (int u = 0; u < BP::NFLOW; ++u)
+#pragma unroll
+      for (int v = u; v < BP::NFLOW; ++v, ++q) rho[q] += (double)(J[u].r * J[v].r + J[u].i * J[v].i);
+  }
+  double bkl[BP::NCL][BP::NCL];
+  BP::colour_corr(rho, bkl);
+  const double B = bsum * a.scale_b;
+  // eikonal factor -sum_kl (p_k.p_l)/((p_k.n)(p_l.n)) B_kl with n = (1, nh)
+  const double n4[4] = {1.0, K.nh[0], K.nh[1], K.nh[2]};
+  double eik = 0.0;
+#pragma unroll
+  for (int k = 0; k < BP::NCL; ++k)
+#pragma unroll
+    for (int l = 0; l < BP::NCL; ++l) {
+      const double* pk = kb[BP::CLEG[k]];
+      const double* pl = kb[BP::CLEG[l]];
+      eik -= mink(pk, pl) / (mink(pk, n4) * mink(pl, n4)) * bkl[k][l] * a.scale_b;
+    }
+  const double Ss = fks_sector_soft<S>(kb, K.nh, K.sqs_b);
+  const double xi = K.xi, y = K.y, g2 = a.g2;
+  const double me2r = a.me2r[pos];
+  double gR, gS, gC, gCm = 0.0, gSC, gSCm = 0.0;
+  if constexpr (S::J >= 0) {
+    gR = xi * xi * (1.0 - y) * me2r * S_real;
+    gS = (1.0 - y) * 4.0 / K.sb * g2 * eik * Ss;
+    const double z = K.z;
+    const double Sc = S::J_GLUON && S::GLUON[S::I] ? z : 1.0;
+    double P, Cj;
+    if constexpr (S::J_GLUON) {
+      const double Bp = born_spin<BP, S::JB, T>(s, K.ep, T(a.mt)) * a.scale_b;
+      P = 2.0 * FKS_CA * ((z / (1.0 - z) + (1.0 - z) / z) * B + 2.0 * z * (1.0 - z) * Bp);
+      Cj = FKS_CA;
+    } else {
+      P = FKS_CF * (1.0 + z * z) / (1.0 - z) * B;
+      Cj = FKS_CF;
+    }
+    gC = 2.0 * xi * g2 / (K.sqs_b * K.ejc) * P * Sc;
+    gSC = 8.0 * g2 * Cj / K.sb * B;
+  } else {
+    gR = xi * xi * (1.0 - y) * (1.0 + y) * me2r * S_real;
+    gS = (1.0 - y) * (1.0 + y) * 4.0 / K.sb * g2 * eik * Ss;
+    const double x = 1.0 - xi;
+    double Pp, Pm, Cp, Cm;
+    if constexpr (S::BEAM_GLUON0) {
+      const double Bp = born_spin<BP, 0, T>(s, K.ep, T(a.mt)) * a.scale_b;
+      Pp = 2.0 * FKS_CA * ((x / (1.0 - x) + x * (1.0 - x)) * B + 2.0 * (1.0 - x) / x * Bp);
+      Cp = FKS_CA;
+    } else {
+      Pp = FKS_CF * (1.0 + x * x) / (1.0 - x) * B;
+      Cp = FKS_CF;
+    }
+    if constexpr (S::BEAM_GLUON1) {
+      const double Bp = born_spin<BP, 1, T>(s, K.ep, T(a.mt)) * a.scale_b;
+      Pm = 2.0 * FKS_CA * ((x / (1.0 - x) + x * (1.0 - x)) * B + 2.0 * (1.0 - x) / x * Bp);
+      Cm = FKS_CA;
+    } else {
+      Pm = FKS_CF * (1.0 + x * x) / (1.0 - x) * B;
+      Cm = FKS_CF;
+    }
+    gC = 8.0 * xi * g2 / K.sb * Pp;
+    gCm = 8.0 * xi * g2 / K.sb * Pm;
+    gSC = 16.0 * g2 * Cp / K.sb * B;
+    gSCm = 16.0 * g2 * Cm / K.sb * B;
+  }
+  // Algorithm-2 masks: a failed cut zeroes its contribution after evaluation
+  uint8_t st = which == 1 ? 2 : 0;
+  double Bo = B;
+  if (a.mask) {
+    const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e], mC = a.mask[3 * a.ld + e];
+    if (!mB) Bo = 0.0;
+    if (!mR) gR = 0.0;
+    if (!mS) gS = 0.0;
+    if (!mC) { gC = 0.0; gCm = 0.0; }
+    if (!mS || !mC) { gSC = 0.0; gSCm = 0.0; }
+    if (!(mB && mR && mS && mC)) st |= 4;
+  }
+  double W;
+  if constexpr (S::J >= 0) {
+    W = (gR - gS - gC + gSC) / (xi * (1.0 - y));
+  } else {
+    W = (gR - gS - 0.5 * (1.0 + y) * (gC - gSC) - 0.5 * (1.0 - y) * (gCm - gSCm)) / (xi * (1.0 - y) * (1.0 + y));
+  }
+  if (!isfinite(W)) st |= 1;
+  a.W[e] = W;
+  if (a.xi_out) a.xi_out[e] = xi;
+  if (a.born_out) a.born_out[e] = Bo;
+  if (a.gR) a.gR[e] = gR;
+  if (a.gS) a.gS[e] = gS;
+  if (a.gC) a.gC[e] = gC;
+  if (a.gCm) a.gCm[e] = gCm;
+  if (a.gSC) a.gSC[e] = gSC;
+  if (a.gSCm) a.gSCm[e] = gSCm;
+  if (a.status) a.status[e] = st;
+}
+
+// fixed-order FP64 sum (single block; deterministic for a given n)
+static __global__ __launch_bounds__(1024) void k_sum_fixed(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double part[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += x[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
+template <class S>
+hipError_t launch_fks_map(const FksArgs& a, int block, hipStream_t st) {
+  hipLaunchKernelGGL(k_fks_zero, dim3(1), dim3(64), 0, st, a.cnt);
+  const int64_t grid = (a.n + block - 1) / block;
+  hipLaunchKernelGGL((k_fks_map<S>), dim3((unsigned)grid), dim3(block), 0, st, a);
+  return hipGetLastError();
+}
+
+template <class S, class T>
+hipError_t launch_fks_born(const FksArgs& a, int which, int block, hipStream_t st) {
+  const int64_t grid = (a.n + block - 1) / block;
+  hipLaunchKernelGGL((k_fks_born<S, T>), dim3((unsigned)grid), dim3(block), 0, st, a, which);
+  return hipGetLastError();
+}
+
+}  // namespace nlo

@@ -31,11 +31,22 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
 // ---------------------------------------------------------------------------
 // vector-ALU kernel: any arithmetic type T
 // ---------------------------------------------------------------------------
+// event range of a launch: all of [0, n), or one bucket of a bucketed batch
+__device__ __forceinline__ void event_range(int64_t n, const unsigned* cnt, int which, int64_t& lo, int64_t& hi) {
+  lo = 0;
+  hi = n;
+  if (which == 0) hi = cnt[0];
+  else if (which == 1) lo = n - (int64_t)cnt[1];
+}
+
 template <class P, class T>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
-                                                  double* __restrict__ out, double scale, double mt) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+                                                  double* __restrict__ out, double scale, double mt,
+                                                  const unsigned* cnt, int which) {
+  int64_t lo, hi;
+  event_range(n, cnt, which, lo, hi);
+  const int64_t e = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= hi) return;
   double p[P::NPART][4];
   load_event<P>(mom, ld, e, p);
   typename P::template Pre<T> s;
@@ -66,16 +77,21 @@ struct MfmaShape {
 
 template <class P>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t ld, const double* __restrict__ mom,
-                                                  double* __restrict__ out, double scale, double mt) {
+                                                  double* __restrict__ out, double scale, double mt,
+                                                  const unsigned* cnt, int which) {
   using S = MfmaShape<P>;
   extern __shared__ float smem[];
+  int64_t lo, hi;
+  event_range(n, cnt, which, lo, hi);
+  const int64_t b0 = lo + (int64_t)blockIdx.x * blockDim.x;
+  if (b0 >= hi) return;   // block-uniform: the barriers below see every wave
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   float* buf = smem + wave * S::WAVE_FLOATS;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = b0 + threadIdx.x;
   // every lane of a wave takes part in the MFMA; lanes past the end reuse the
   // last event and do not store
-  const int64_t ec = e < n ? e : n - 1;
+  const int64_t ec = e < hi ? e : hi - 1;
   double p[P::NPART][4];
   load_event<P>(mom, ld, ec, p);
   typename P::template Pre<float> s;
@@ -155,7 +171,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t l
       for (int r = 0; r < 4; ++r) rows[16 * t + 4 * (lane >> 4) + r] = rs[t][r];
   }
   __syncthreads();
-  if (e < n) out[e] = (rows[lane] + rows[64 + lane]) * scale;
+  if (e < hi) out[e] = (rows[lane] + rows[64 + lane]) * scale;
 }
 
 template <class P>
@@ -169,13 +185,13 @@ hipError_t launch_me2(const LaunchArgs& a) {
   const int64_t grid = (a.n + a.block - 1) / a.block;
   if constexpr (VARIANT == VAR_F64) {
     hipLaunchKernelGGL((k_me2_valu<P, double>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt);
+                       a.out, a.scale, a.mt, a.cnt, a.which);
   } else if constexpr (VARIANT == VAR_F32) {
     hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt);
+                       a.out, a.scale, a.mt, a.cnt, a.which);
   } else {
     hipLaunchKernelGGL((k_me2_mfma<P>), dim3((unsigned)grid), dim3(a.block), mfma_smem_bytes<P>(a.block), a.stream,
-                       a.n, a.ld, a.mom, a.out, a.scale, a.mt);
+                       a.n, a.ld, a.mom, a.out, a.scale, a.mt, a.cnt, a.which);
   }
   return hipGetLastError();
 }

@@ -20,6 +20,10 @@ struct LaunchArgs {
   double mt;
   int block;
   hipStream_t stream;
+  // optional device-side event range (bucketed FKS evaluation): which = -1
+  // all of [0, n); 0: [0, cnt[0]); 1: [n - cnt[1], n)
+  const unsigned* cnt = nullptr;
+  int which = -1;
 };
 
 struct ProcStatic {

@@ -1,6 +1,8 @@
 """Throughput benchmark: helicity- and colour-summed gg -> t tbar g |M|^2 on
-one MI355X, mixed precision (FP32 amplitudes, matrix-core colour
-contraction, FP64 helicity sum) against the plain FP64 GPU path, with the
+one MI355X, mixed precision (FP32 amplitudes, FP64 prologue and helicity sum,
+colour contraction on the faster unit for the process -- vector ALU at 6
+colour flows, the matrix-core variant timed beside it) against the plain
+FP64 GPU path, with the
 relative error of every event against the FP64 result and of a sample
 against the FP64 CPU oracle.
 
@@ -112,15 +114,29 @@ def main():
                                         "max": float(rel.max()), "summed": sum_rel}}
         print("fp64: %.3f ms per step" % ms64, file=sys.stderr, flush=True)
 
-    # algorithmic flops of the helicity loop (amplitudes + colour contraction)
+    # the other colour-contraction unit, for the record
+    other = None
+    if args.prec == "mixed":
+        cur = ctx.info(proc)
+        mode_now = 2 if info.ncolour >= 12 else 1
+        ctx.set_kernel_config(proc, "mixed", 256, 3 - mode_now)
+        ms_o = timed(ctx, proc, mom, out, "mixed", max(3, args.steps // 4), 1)
+        ctx.set_kernel_config(proc, "mixed", 256, 0)
+        other = {"colour_unit": "mfma" if mode_now == 1 else "valu", "ms_per_step": ms_o, "events_per_s": n / (ms_o * 1e-3)}
+        print("other colour unit: %.3f ms per step" % ms_o, file=sys.stderr, flush=True)
+
+    # algorithmic flops per event: exact count of the generated source of the
+    # nested helicity schedule the kernels run (amplitudes + colour contraction)
     with open(os.path.join(ROOT, "paper_2503_07439_amd", "flops.json")) as f:
         fl = json.load(f)[proc]
-    flops_event = fl["ngood"] * (fl["amp_flops_per_hel"] + fl["colour_flops_per_hel"])
+    flops_event = fl["nested_flops_per_event"]
     achieved = flops_event * n / (ms * 1e-3) / 1e12
     peak = PEAK["fp64" if args.prec == "fp64" else "fp32"]
+    unit = "mfma" if (args.prec == "mixed" and info.ncolour >= 12) else "valu"
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None, "flops_per_event": flops_event,
-                "kernel": "k_me2_%s<%s>" % ("mfma" if args.prec == "mixed" else "valu", proc)}
+                "flops_per_event_per_helicity_evaluation": fl["ngood"] * (fl["amp_flops_per_hel"] + fl["colour_flops_per_hel"]),
+                "kernel": "k_me2_%s<%s%s>" % (unit, proc, ", float" if unit == "valu" and args.prec != "fp64" else (", double" if args.prec == "fp64" else ""))}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -139,7 +155,7 @@ def main():
                    "sqrt_s_hat_GeV": list(rs) if isinstance(rs, tuple) else rs, "m_top_GeV": 173.0,
                    "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
                    "helicities": info.ngood_hel},
-        "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64,
+        "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -50,9 +50,11 @@ typedef enum {
  * float64.  NLO_FP64: everything in double.  NLO_FP32: spinors, currents,
  * vertices and the colour contraction in float; helicity-independent
  * quantities (internal momenta, propagator denominators, external-state
- * set-up) and the per-event helicity sum in double.  NLO_MIXED for |M|^2 is
- * NLO_FP32 with the colour contraction on the matrix cores; for subtracted
- * weights it routes events near soft/collinear limits to FP64. */
+ * set-up) and the per-event helicity sum in double; colour contraction on the
+ * vector ALU.  NLO_MIXED for |M|^2 is NLO_FP32 with the colour contraction on
+ * the matrix cores when the process has at least 12 colour flows (vector ALU
+ * below, where it is faster; nlo_set_kernel_config overrides); for subtracted
+ * weights it also routes events near soft/collinear limits to FP64. */
 typedef enum { NLO_FP64 = 0, NLO_FP32 = 1, NLO_FP16 = 2, NLO_BF16 = 3, NLO_MIXED = 4 } nlo_prec;
 
 /* Physics parameters: fixed couplings (no running), top mass, zero widths,

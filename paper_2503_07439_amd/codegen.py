@@ -743,6 +743,128 @@ def emit_colour_corr(p):
     return L
 
 
+# rough flops of each routine, for choosing the order of the helicity loops
+_NODE_COST = {"ffv_vec": 128, "ffv_col": 132, "ffv_row": 132, "vvv_vec": 166, "vvvv_vec0": 124,
+              "vvvv_vec1": 124, "vvvv_vec2": 124, "ext": 8}
+
+
+def _massless_lines(p):
+    lines = []
+    for k in range(p.npart):
+        t = p.itype[k]
+        if is_antifermion(t) and FERMIONS[flavour(t)][0] == "0":
+            c = [j for j in range(p.npart) if p.itype[j] == flavour(t)][0]
+            lines.append((k, c))
+    return lines
+
+
+def helicity_order(p):
+    """Order of the nested helicity loops (outermost first).  A sub-current over
+    leg set S is evaluated once per helicity assignment of the loops down to
+    the innermost of its legs, i.e. 2^(level+1) times; the root leg takes part
+    in no sub-current and goes innermost.  Exhaustive search over the other
+    legs minimises the estimated flops."""
+    root = p.npart - 1
+    others = list(range(p.npart - 1))
+    best = None
+    for perm in itertools.permutations(others):
+        order = list(perm) + [root]
+        lev = {k: i for i, k in enumerate(order)}
+        cost = 0
+        for n in p.nodes:
+            l = max(lev[k] for k in n.legs)
+            cost += _NODE_COST.get(n.kind, 130) * (2 ** (l + 1))
+        if best is None or cost < best[0]:
+            best = (cost, order)
+    return best[1]
+
+
+def emit_nested(p, mslot, dslot, N, nin):
+    """helicity_sum: nested loops over the legs' helicities; every
+    sub-current is evaluated at the loop level of its innermost leg and reused
+    by all inner iterations; the amplitudes, J and body(J) run once per
+    non-zero helicity combination."""
+    order = helicity_order(p)
+    lev = {k: i for i, k in enumerate(order)}
+    L = ["  // helicity loops, outermost first: legs %s" % ", ".join(str(k) for k in order),
+         "  template <class T, class F> NLO_HD static void helicity_sum(const Pre<T>& s, T mt, F&& body) {"]
+    # chirality exclusions of massless fermion lines, checked at the inner leg's level
+    checks = {}
+    for r, c in _massless_lines(p):
+        out_r, out_c = r >= nin, c >= nin
+        # block of the row spinor: outgoing ubar(+)/incoming vbar(-) -> 1; block of the column:
+        # outgoing v(+)/incoming u(-) -> 1; the amplitude vanishes when the blocks agree
+        rb = "(b%d ? %d : %d)" % (lev[r], 1 if out_r else 2, 2 if out_r else 1)
+        cb = "(b%d ? %d : %d)" % (lev[c], 1 if out_c else 2, 2 if out_c else 1)
+        checks.setdefault(max(lev[r], lev[c]), []).append("%s == %s" % (rb, cb))
+    ind = "    "
+    for level, k in enumerate(order):
+        L.append(ind + "#pragma unroll 1")
+        L.append(ind + "for (int b%d = 0; b%d < 2; ++b%d) {" % (level, level, level))
+        ind += "  "
+        for cond in checks.get(level, []):
+            L.append(ind + "if (%s) continue;" % cond)
+        for n in p.nodes:
+            if max(lev[x] for x in n.legs) != level:
+                continue
+            v = "v%d" % n.id
+            if n.kind == "ext":
+                t = n.ptype
+                out = k >= nin
+                bit = "b%d" % level
+                if t in ("g", "a"):
+                    expr = "wf_eps(s.x%d, %s, %s)" % (k, bit, "true" if out else "false")
+                elif is_fermion(t):
+                    expr = "%s(s.x%d, %s)" % ("wf_v" if out else "wf_u", k, bit)
+                else:
+                    expr = "wf_bar(%s(s.x%d, %s))" % ("wf_u" if out else "wf_v", k, bit)
+                L.append(ind + "const w4<T> %s = %s;" % (v, expr))
+                continue
+            ch = ["v%d" % c.id for c in n.children]
+            Q = "s.Q[%d]" % mslot[n.legs]
+            D = "s.den[%d]" % dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")]
+            if n.kind == "ffv_vec":
+                L.append(ind + "const w4<T> %s = ffv_vec(%s, %s, %s);" % (v, ch[0], ch[1], D))
+            elif n.kind in ("ffv_col", "ffv_row"):
+                if n.mass == "MT":
+                    L.append(ind + "const w4<T> %s = %s(%s, %s, %s, %s, mt);" % (v, n.kind, ch[0], ch[1], Q, D))
+                else:
+                    L.append(ind + "const w4<T> %s = %s0(%s, %s, %s, %s);" % (v, n.kind, ch[0], ch[1], Q, D))
+            elif n.kind == "vvv_vec":
+                QA = "s.Q[%d]" % mslot[n.children[0].legs]
+                QB = "s.Q[%d]" % mslot[n.children[1].legs]
+                L.append(ind + "const w4<T> %s = vvv_vec(%s, %s, %s, %s, %s);" % (v, ch[0], QA, ch[1], QB, D))
+            else:
+                L.append(ind + "const w4<T> %s = %s(%s, %s, %s, %s);" % (v, n.kind, ch[0], ch[1], ch[2], D))
+    nflow = len(p.flows)
+    L.append(ind + "cx<T> J[NFLOW];")
+    L.append(ind + "for (int f = 0; f < NFLOW; ++f) J[f] = czero<T>();")
+    for i, a in enumerate(p.amps):
+        ch = ["v%d" % c.id for c in a.children]
+        av = "a%d" % i
+        if a.kind == "ffv_amp":
+            L.append(ind + "const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[0], ch[2], ch[1]))
+        elif a.kind == "ffv_amp_rootcol":
+            L.append(ind + "const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[0], ch[1], ch[2]))
+        elif a.kind == "ffv_amp_rootrow":
+            L.append(ind + "const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[2], ch[1], ch[0]))
+        elif a.kind == "vvv_amp":
+            Qs = ["s.Q[%d]" % mslot[c.legs] for c in a.children]
+            L.append(ind + "const cx<T> %s = vvv_amp(%s, %s, %s, %s, %s, %s);" % (av, ch[0], Qs[0], ch[1], Qs[1], ch[2], Qs[2]))
+        else:
+            L.append(ind + "const cx<T> %s = %s(%s, %s, %s, %s);" % (av, a.kind, ch[0], ch[1], ch[2], ch[3]))
+        for f in range(nflow):
+            c = _phase_coef(a.coef[f], a.phase, a.qfac)
+            for line in _acc_code("J[%d]" % f, c, av):
+                L.append(ind + line)
+    L.append(ind + "body(J);")
+    for level in range(N):
+        ind = ind[:-2]
+        L.append(ind + "}")
+    L.append("  }")
+    return L
+
+
 def emit_process(p):
     """HIP source for one process (a struct with static device functions)."""
     good = p.good_helicities()
@@ -879,6 +1001,7 @@ def emit_process(p):
             for line in _acc_code("J[%d]" % f, c, av):
                 L.append("    " + line)
     L.append("  }")
+    L.extend(emit_nested(p, mslot, dslot, N, nin))
     # colour sum: J^dagger C J = |L^T Re J|^2 + |L^T Im J|^2, C = L L^T
     Lc = cholesky_lower(p.colour_matrix)
     L.append("  // colour matrix (rows):")

@@ -36,6 +36,7 @@ nlo_status fail(nlo_status st, const char* fmt, ...) {
 }
 
 constexpr int NPROC_ = NPROC;
+constexpr int MFMA_MIN_FLOWS = 12;
 
 }  // namespace
 
@@ -85,7 +86,10 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
     var = VAR_F64;
   } else {
     int mode = kc.colour_mode;
-    if (mode == 0) mode = (prec == NLO_MIXED) ? 2 : 1;
+    // automatic: matrix cores when the colour contraction is large enough to
+    // pay for its LDS round trip (measured: 24 flows faster on MFMA, 2-6 flows
+    // faster on the vector ALU)
+    if (mode == 0) mode = (prec == NLO_MIXED && PROC_STATIC[pid].nflow >= MFMA_MIN_FLOWS) ? 2 : 1;
     var = (mode == 2) ? VAR_MFMA : VAR_F32;
   }
   LaunchArgs a{n, ld, mom, out, coupling_scale(pid, ctx->params), ctx->params.m_top, kc.block, st};
@@ -224,7 +228,8 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
   const nlo_kernel_config& kc = ctx->cfg[real_proc][prec];
   LaunchArgs la{n, n, a.real, a.me2r, coupling_scale(real_proc, ctx->params), ctx->params.m_top, kc.block, s,
                 a.cnt, 0};
-  if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][a.mode == 2 ? VAR_MFMA : VAR_F32](la);
+  const bool mfma = kc.colour_mode == 2 || (kc.colour_mode == 0 && a.mode == 2 && PROC_STATIC[real_proc].nflow >= MFMA_MIN_FLOWS);
+  if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
   if (err == hipSuccess && a.mode != 0) {
     la.which = 1;
     err = ME2_LAUNCH[real_proc][VAR_F64](la);

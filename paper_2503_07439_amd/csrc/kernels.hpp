@@ -3,8 +3,10 @@
 // One event per lane.  Per event: coalesced load of the structure-of-arrays
 // FP64 momenta, a helicity-independent FP64 prologue (external-state data,
 // internal momenta, propagator denominators), then a loop over the
-// structurally non-zero helicities that evaluates every Feynman-diagram
-// sub-current once, accumulates the colour-flow vector J, contracts
+// structurally non-zero helicities -- nested per leg, so that every
+// Feynman-diagram sub-current is evaluated once per helicity assignment of
+// its own legs and reused by the inner loops -- accumulates the colour-flow
+// vector J, contracts
 // J^dagger C J with the constant colour matrix and adds the result to an FP64
 // per-event sum.  The colour contraction runs either on the vector ALU
 // (Cholesky form |L^T Re J|^2 + |L^T Im J|^2) or on the matrix cores: each
@@ -52,13 +54,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t l
   typename P::template Pre<T> s;
   P::prologue(p, s, mt);
   double acc = 0.0;
-#pragma unroll 1
-  for (int ih = 0; ih < P::NGOOD; ++ih) {
-    const int h = P::good(ih);
-    cx<T> J[P::NFLOW];
-    P::amplitudes(s, h, T(mt), J);
-    acc += (double)P::colour_sum(J);
-  }
+  P::helicity_sum(s, T(mt), [&](const cx<T> (&J)[P::NFLOW]) { acc += (double)P::colour_sum(J); });
   out[e] = acc * scale;
 }
 
@@ -118,11 +114,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t l
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[t][r] = 0.0f;
 
-#pragma unroll 1
-  for (int ih = 0; ih < P::NGOOD; ++ih) {
-    const int h = P::good(ih);
-    cx<float> J[P::NFLOW];
-    P::amplitudes(s, h, float(mt), J);
+  P::helicity_sum(s, float(mt), [&](const cx<float> (&J)[P::NFLOW]) {
     __syncthreads();   // the previous helicity's fragment reads are complete
 #pragma unroll
     for (int j = 0; j < S::NF; ++j) {
@@ -148,7 +140,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t l
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] += d[nt][r] * d[nt][r];
     }
-  }
+  });
   // sum the squares over the 16 columns held by lanes with equal lane/16
   double rs[8][4];
 #pragma unroll

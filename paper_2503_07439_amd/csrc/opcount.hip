@@ -43,8 +43,14 @@ void count(const char* sep) {
   Cnt::add = Cnt::mul = 0;
   (void)P::colour_sum(J);
   long long col = Cnt::add + Cnt::mul;
-  printf("%s\"%s\": {\"amp_flops_per_hel\": %lld, \"colour_flops_per_hel\": %lld, \"ngood\": %d, \"nflow\": %d}",
-         sep, P::NAME, amp, col, P::NGOOD, P::NFLOW);
+  // the nested helicity schedule the kernels run: whole helicity sum per event
+  Cnt::add = Cnt::mul = 0;
+  long long nbody = 0;
+  P::helicity_sum(s, Cnt(0), [&](const cx<Cnt> (&Jn)[P::NFLOW]) { (void)P::colour_sum(Jn); ++nbody; });
+  long long nested = Cnt::add + Cnt::mul;
+  printf("%s\"%s\": {\"amp_flops_per_hel\": %lld, \"colour_flops_per_hel\": %lld, \"ngood\": %d, \"nflow\": %d, "
+         "\"nested_flops_per_event\": %lld, \"nested_bodies\": %lld}",
+         sep, P::NAME, amp, col, P::NGOOD, P::NFLOW, nested, nbody);
 }
 
 int main() {

@@ -117,7 +117,6 @@ def main():
     # the other colour-contraction unit, for the record
     other = None
     if args.prec == "mixed":
-        cur = ctx.info(proc)
         mode_now = 2 if info.ncolour >= 12 else 1
         ctx.set_kernel_config(proc, "mixed", 256, 3 - mode_now)
         ms_o = timed(ctx, proc, mom, out, "mixed", max(3, args.steps // 4), 1)

@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--events", type=int, default=0, help="override the batch size")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -95,6 +97,12 @@ def main():
     mom_np, _ = config_events(args.workload, n=n)
     print("inputs: %d %s events generated in %.1f s" % (n, proc, time.perf_counter() - t), file=sys.stderr, flush=True)
     ctx = nl.Context()
+    if args.copy_probe_mib:
+        a = torch.ones(args.copy_probe_mib << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     mom = torch.from_numpy(mom_np).cuda()
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     info = ctx.info(proc)

@@ -114,6 +114,16 @@ nlo_status nlo_process_info(const nlo_ctx* ctx, int proc_id, nlo_proc_info* out)
 nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const nlo_kernel_config* cfg);
 nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec, nlo_kernel_config* cfg);
 
+/* Autotuner: times every launch configuration of (proc_id, prec) -- block of
+ * 64/128/192/256 threads and, for FP32/MIXED, the colour contraction on the
+ * vector ALU or the matrix cores -- on the caller's sample batch (device
+ * momenta, n events, scratch output me2 of n doubles) with HIP events on the
+ * given stream, keeps the fastest for this context and returns it in *best
+ * (may be NULL) and its time per event in *ns_per_event (may be NULL).
+ * Synchronises the stream; allocates nothing. */
+nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int64_t ld, const double* mom,
+                        double* me2, void* hip_stream, nlo_kernel_config* best, double* ns_per_event);
+
 /* Squared matrix elements (the paper's Born and real equations):
  *   me2[e] = avg_factor * sum_{helicities} sum_{colours} |M(mom_e)|^2
  * for e in [0, n).  mom: device, layout above, npart particles.  me2: device
@@ -163,6 +173,39 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
 
 /* Routing threshold of NLO_MIXED subtracted weights (default 1e-4). */
 nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold);
+
+/* ---- batched mixes: one graph launch for many (process, contribution) items ----
+ * The paper notes that Born amplitudes are evaluated at several kinematics per
+ * NLO event and that parallelism should run over FKS sectors; a batch gathers
+ * the Born, real and subtracted evaluations of several subprocesses with
+ * uneven event counts.  nlo_batch_plan validates the items, allocates the
+ * FKS workspaces, and captures every item's launch sequence into one HIP
+ * graph whose independent items run concurrently (items are spread over
+ * forked capture streams, largest first).  nlo_batch_run is a single
+ * hipGraphLaunch on the caller's stream.  Items keep pointing at the caller's
+ * device arrays: refill them between runs, do not free them while the plan
+ * lives. */
+typedef enum { NLO_ITEM_ME2 = 0, NLO_ITEM_SUBTRACTED = 1 } nlo_item_kind;
+
+typedef struct {
+  nlo_item_kind kind;
+  int proc_id;                       /* process (ME2) or real process (SUBTRACTED) */
+  int fks_i, fks_j;                  /* SUBTRACTED only */
+  int64_t n, ld;
+  const double* mom;                 /* ME2: momenta; SUBTRACTED: Born momenta (device) */
+  const double *xi_tilde, *y, *phi;  /* SUBTRACTED only (device [n]) */
+  const uint8_t* mask;               /* SUBTRACTED only, or NULL */
+  nlo_prec prec;
+  double* me2;                       /* ME2 output (device [n]) */
+  nlo_fks_out fks_out;               /* SUBTRACTED outputs (device arrays) */
+} nlo_work_item;
+
+typedef struct nlo_plan nlo_plan;   /* opaque, library-owned (holds the graph) */
+
+/* Build a plan; nbranches = concurrent branches (1..16, 0 = 4). */
+nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, int nbranches, nlo_plan** out);
+nlo_status nlo_batch_run(nlo_plan* plan, void* hip_stream);
+nlo_status nlo_plan_destroy(nlo_plan* plan);
 
 #ifdef __cplusplus
 }

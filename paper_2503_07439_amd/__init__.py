@@ -8,7 +8,8 @@ from . import _lib
 from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloError,  # noqa: F401
                    nlo_abi_version, nlo_create, nlo_destroy, nlo_last_error, nlo_num_processes,
                    nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
-                   nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out)
+                   nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
+                   nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -89,6 +90,15 @@ class Context:
         nlo_subtracted(self.ctx, proc_id(real), fks_i, fks_j, n, n, born_mom.data_ptr(), xi_tilde.data_ptr(),
                        y.data_ptr(), phi.data_ptr(), mptr, PREC[prec], out, self._stream())
         return res
+
+    def autotune(self, proc, mom, prec="mixed"):
+        """Time every launch configuration on this sample and keep the fastest.
+        Returns ((block, colour_mode), ns per event)."""
+        import torch
+        n = mom.shape[2]
+        out = torch.empty(n, dtype=torch.float64, device=mom.device)
+        return nlo_autotune(self.ctx, proc_id(proc), PREC[prec], n, n, mom.data_ptr(), out.data_ptr(),
+                            self._stream())
 
     def set_fks_threshold(self, thr):
         nlo_set_fks_threshold(self.ctx, thr)

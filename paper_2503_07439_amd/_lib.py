@@ -36,6 +36,17 @@ class nlo_fks_out(ctypes.Structure):
                 ("status", ctypes.c_void_p), ("real_mom", ctypes.c_void_p), ("w_sum", ctypes.c_void_p)]
 
 
+class nlo_work_item(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("proc_id", ctypes.c_int), ("fks_i", ctypes.c_int), ("fks_j", ctypes.c_int),
+                ("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("mom", ctypes.c_void_p),
+                ("xi_tilde", ctypes.c_void_p), ("y", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("prec", ctypes.c_int), ("me2", ctypes.c_void_p),
+                ("fks_out", nlo_fks_out)]
+
+
+NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED = 0, 1
+
+
 class NloError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("nlome status %d: %s" % (status, msg))
@@ -60,6 +71,12 @@ SIGNATURES = {
     "nlo_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
                         ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
     "nlo_set_fks_threshold": ([_VP, ctypes.c_double], ctypes.c_int),
+    "nlo_batch_plan": ([_VP, ctypes.POINTER(nlo_work_item), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)],
+                       ctypes.c_int),
+    "nlo_batch_run": ([_VP, _VP], ctypes.c_int),
+    "nlo_autotune": ([_VP, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, ctypes.POINTER(nlo_kernel_config),
+                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "nlo_plan_destroy": ([_VP], ctypes.c_int),
 }
 
 
@@ -136,3 +153,26 @@ def nlo_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr
 
 def nlo_set_fks_threshold(ctx, threshold):
     return check(lib().nlo_set_fks_threshold(ctx, threshold))
+
+
+def nlo_batch_plan(ctx, items, nbranches=0):
+    arr = (nlo_work_item * len(items))(*items)
+    plan = _VP()
+    check(lib().nlo_batch_plan(ctx, arr, len(items), nbranches, ctypes.byref(plan)))
+    return plan
+
+
+def nlo_batch_run(plan, stream_ptr):
+    return check(lib().nlo_batch_run(plan, stream_ptr))
+
+
+def nlo_plan_destroy(plan):
+    return check(lib().nlo_plan_destroy(plan))
+
+
+def nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr):
+    best = nlo_kernel_config()
+    ns = ctypes.c_double()
+    check(lib().nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr, ctypes.byref(best),
+                             ctypes.byref(ns)))
+    return (best.block, best.colour_mode), ns.value

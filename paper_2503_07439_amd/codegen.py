@@ -779,86 +779,151 @@ def helicity_order(p):
     return best[1]
 
 
+# processes whose sub-currents one level above the deepest loop are also
+# evaluated lazily inside it (more flops, far fewer live registers)
+JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
+
+
+def _node_call(n, mslot, dslot):
+    """C++ expression evaluating sub-current n from its children."""
+    ch = ["v%d" % c.id for c in n.children]
+    Q = "s.Q[%d]" % mslot[n.legs]
+    D = "s.den[%d]" % dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")]
+    if n.kind == "ffv_vec":
+        return "ffv_vec(%s, %s, %s)" % (ch[0], ch[1], D)
+    if n.kind in ("ffv_col", "ffv_row"):
+        if n.mass == "MT":
+            return "%s(%s, %s, %s, %s, mt)" % (n.kind, ch[0], ch[1], Q, D)
+        return "%s0(%s, %s, %s, %s)" % (n.kind, ch[0], ch[1], Q, D)
+    if n.kind == "vvv_vec":
+        QA = "s.Q[%d]" % mslot[n.children[0].legs]
+        QB = "s.Q[%d]" % mslot[n.children[1].legs]
+        return "vvv_vec(%s, %s, %s, %s, %s)" % (ch[0], QA, ch[1], QB, D)
+    return "%s(%s, %s, %s, %s)" % (n.kind, ch[0], ch[1], ch[2], D)
+
+
+def _ext_call(p, k, bit, nin):
+    t = p.itype[k]
+    out = k >= nin
+    if t in ("g", "a"):
+        return "wf_eps(s.x%d, %s, %s)" % (k, bit, "true" if out else "false")
+    if is_fermion(t):
+        return "%s(s.x%d, %s)" % ("wf_v" if out else "wf_u", k, bit)
+    return "wf_bar(%s(s.x%d, %s))" % ("wf_u" if out else "wf_v", k, bit)
+
+
+def _amp_call(a, ch, mslot, rootv):
+    """C++ expression of amplitude a with the root wavefunction rootv."""
+    ch = ch[:-1] + [rootv]
+    if a.kind == "ffv_amp":
+        return "ffv_amp(%s, %s, %s)" % (ch[0], ch[2], ch[1])
+    if a.kind == "ffv_amp_rootcol":
+        return "ffv_amp(%s, %s, %s)" % (ch[0], ch[1], ch[2])
+    if a.kind == "ffv_amp_rootrow":
+        return "ffv_amp(%s, %s, %s)" % (ch[2], ch[1], ch[0])
+    if a.kind == "vvv_amp":
+        Qs = ["s.Q[%d]" % mslot[c.legs] for c in a.children]
+        return "vvv_amp(%s, %s, %s, %s, %s, %s)" % (ch[0], Qs[0], ch[1], Qs[1], ch[2], Qs[2])
+    return "%s(%s, %s, %s, %s)" % (a.kind, ch[0], ch[1], ch[2], ch[3])
+
+
 def emit_nested(p, mslot, dslot, N, nin):
-    """helicity_sum: nested loops over the legs' helicities; every
-    sub-current is evaluated at the loop level of its innermost leg and reused
-    by all inner iterations; the amplitudes, J and body(J) run once per
-    non-zero helicity combination."""
+    """helicity_sum: nested loops over the helicities of all legs but the root
+    (the leg taking part in no sub-current).  A sub-current is evaluated at the
+    loop level of its innermost leg and reused by all inner iterations; in the
+    deepest loop the remaining sub-currents are evaluated just before their
+    first use, amplitude by amplitude, and every amplitude is formed for both
+    root helicities at once, giving two flow vectors and two calls of body."""
     order = helicity_order(p)
     lev = {k: i for i, k in enumerate(order)}
-    L = ["  // helicity loops, outermost first: legs %s" % ", ".join(str(k) for k in order),
+    root = order[-1]
+    deep = N - 2                                    # deepest emitted loop
+    jit_from = deep - JIT_EXTRA_LEVELS.get(p.name, 0)
+    L = ["  // helicity loops, outermost first: legs %s (root leg %d folded into the amplitudes)"
+         % (", ".join(str(k) for k in order[:-1]), root),
          "  template <class T, class F> NLO_HD static void helicity_sum(const Pre<T>& s, T mt, F&& body) {"]
-    # chirality exclusions of massless fermion lines, checked at the inner leg's level
     checks = {}
     for r, c in _massless_lines(p):
         out_r, out_c = r >= nin, c >= nin
-        # block of the row spinor: outgoing ubar(+)/incoming vbar(-) -> 1; block of the column:
-        # outgoing v(+)/incoming u(-) -> 1; the amplitude vanishes when the blocks agree
         rb = "(b%d ? %d : %d)" % (lev[r], 1 if out_r else 2, 2 if out_r else 1)
         cb = "(b%d ? %d : %d)" % (lev[c], 1 if out_c else 2, 2 if out_c else 1)
         checks.setdefault(max(lev[r], lev[c]), []).append("%s == %s" % (rb, cb))
+    nodes = [n for n in p.nodes if not (n.kind == "ext" and min(n.legs) == root)]
+    level_of = {id(n): max(lev[k] for k in n.legs) for n in nodes}
     ind = "    "
-    for level, k in enumerate(order):
+    for level in range(deep + 1):
         L.append(ind + "#pragma unroll 1")
         L.append(ind + "for (int b%d = 0; b%d < 2; ++b%d) {" % (level, level, level))
         ind += "  "
         for cond in checks.get(level, []):
             L.append(ind + "if (%s) continue;" % cond)
-        for n in p.nodes:
-            if max(lev[x] for x in n.legs) != level:
+        for n in nodes:
+            if level_of[id(n)] != level or (level >= jit_from and n.kind != "ext"):
                 continue
-            v = "v%d" % n.id
             if n.kind == "ext":
-                t = n.ptype
-                out = k >= nin
-                bit = "b%d" % level
-                if t in ("g", "a"):
-                    expr = "wf_eps(s.x%d, %s, %s)" % (k, bit, "true" if out else "false")
-                elif is_fermion(t):
-                    expr = "%s(s.x%d, %s)" % ("wf_v" if out else "wf_u", k, bit)
-                else:
-                    expr = "wf_bar(%s(s.x%d, %s))" % ("wf_u" if out else "wf_v", k, bit)
-                L.append(ind + "const w4<T> %s = %s;" % (v, expr))
-                continue
-            ch = ["v%d" % c.id for c in n.children]
-            Q = "s.Q[%d]" % mslot[n.legs]
-            D = "s.den[%d]" % dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")]
-            if n.kind == "ffv_vec":
-                L.append(ind + "const w4<T> %s = ffv_vec(%s, %s, %s);" % (v, ch[0], ch[1], D))
-            elif n.kind in ("ffv_col", "ffv_row"):
-                if n.mass == "MT":
-                    L.append(ind + "const w4<T> %s = %s(%s, %s, %s, %s, mt);" % (v, n.kind, ch[0], ch[1], Q, D))
-                else:
-                    L.append(ind + "const w4<T> %s = %s0(%s, %s, %s, %s);" % (v, n.kind, ch[0], ch[1], Q, D))
-            elif n.kind == "vvv_vec":
-                QA = "s.Q[%d]" % mslot[n.children[0].legs]
-                QB = "s.Q[%d]" % mslot[n.children[1].legs]
-                L.append(ind + "const w4<T> %s = vvv_vec(%s, %s, %s, %s, %s);" % (v, ch[0], QA, ch[1], QB, D))
+                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _ext_call(p, min(n.legs), "b%d" % level, nin)))
             else:
-                L.append(ind + "const w4<T> %s = %s(%s, %s, %s, %s);" % (v, n.kind, ch[0], ch[1], ch[2], D))
+                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot)))
+    # deepest loop: root wavefunctions, then amplitudes with just-in-time
+    # sub-currents.  A massless-fermion root whose chirality partner is fixed
+    # has one allowed helicity: evaluate only that one.
+    root_checks = checks.get(N - 1, [])
+    if root_checks:
+        assert len(root_checks) == 1
+        bad0 = root_checks[0].replace("b%d" % (N - 1), "0")
+        L.append(ind + "const int rbit = (%s) ? 1 : 0;" % bad0)
+        L.append(ind + "const w4<T> r0 = %s;" % _ext_call(p, root, "rbit", nin))
+        roots = (("r0", "J0"),)
+        L.append(ind + "cx<T> J0[NFLOW];")
+        L.append(ind + "for (int f = 0; f < NFLOW; ++f) J0[f] = czero<T>();")
+    else:
+        L.append(ind + "const w4<T> r0 = %s;" % _ext_call(p, root, "0", nin))
+        L.append(ind + "const w4<T> r1 = %s;" % _ext_call(p, root, "1", nin))
+        roots = (("r0", "J0"), ("r1", "J1"))
+        L.append(ind + "cx<T> J0[NFLOW], J1[NFLOW];")
+        L.append(ind + "for (int f = 0; f < NFLOW; ++f) { J0[f] = czero<T>(); J1[f] = czero<T>(); }")
+    done = set()
+
+    def need(n):
+        """sub-currents still to emit for node n (children first)"""
+        if n.kind == "ext" or id(n) in done or level_of[id(n)] < jit_from:
+            return []
+        out = []
+        for c in n.children:
+            out += need(c)
+        done.add(id(n))
+        return out + [n]
+
+    # greedy amplitude order: next the one needing the fewest new sub-currents
+    pending = list(p.amps)
     nflow = len(p.flows)
-    L.append(ind + "cx<T> J[NFLOW];")
-    L.append(ind + "for (int f = 0; f < NFLOW; ++f) J[f] = czero<T>();")
-    for i, a in enumerate(p.amps):
+    k = 0
+    while pending:
+        def newcount(a):
+            seen = set()
+            def cnt(n):
+                if n.kind == "ext" or id(n) in done or level_of[id(n)] < jit_from or id(n) in seen:
+                    return 0
+                seen.add(id(n))
+                return 1 + sum(cnt(c) for c in n.children)
+            return sum(cnt(c) for c in a.children[:-1])
+        a = min(pending, key=newcount)
+        pending.remove(a)
+        for c in a.children[:-1]:
+            for n in need(c):
+                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot)))
         ch = ["v%d" % c.id for c in a.children]
-        av = "a%d" % i
-        if a.kind == "ffv_amp":
-            L.append(ind + "const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[0], ch[2], ch[1]))
-        elif a.kind == "ffv_amp_rootcol":
-            L.append(ind + "const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[0], ch[1], ch[2]))
-        elif a.kind == "ffv_amp_rootrow":
-            L.append(ind + "const cx<T> %s = ffv_amp(%s, %s, %s);" % (av, ch[2], ch[1], ch[0]))
-        elif a.kind == "vvv_amp":
-            Qs = ["s.Q[%d]" % mslot[c.legs] for c in a.children]
-            L.append(ind + "const cx<T> %s = vvv_amp(%s, %s, %s, %s, %s, %s);" % (av, ch[0], Qs[0], ch[1], Qs[1], ch[2], Qs[2]))
-        else:
-            L.append(ind + "const cx<T> %s = %s(%s, %s, %s, %s);" % (av, a.kind, ch[0], ch[1], ch[2], ch[3]))
-        for f in range(nflow):
-            c = _phase_coef(a.coef[f], a.phase, a.qfac)
-            for line in _acc_code("J[%d]" % f, c, av):
-                L.append(ind + line)
-    L.append(ind + "body(J);")
-    for level in range(N):
+        for rv, J in roots:
+            av = "a%d_%s" % (k, rv)
+            L.append(ind + "const cx<T> %s = %s;" % (av, _amp_call(a, ch, mslot, rv)))
+            for f in range(nflow):
+                c = _phase_coef(a.coef[f], a.phase, a.qfac)
+                for line in _acc_code("%s[%d]" % (J, f), c, av):
+                    L.append(ind + line)
+        k += 1
+    for _, J in roots:
+        L.append(ind + "body(%s);" % J)
+    for level in range(deep + 1):
         ind = ind[:-2]
         L.append(ind + "}")
     L.append("  }")

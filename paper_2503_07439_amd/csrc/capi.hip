@@ -7,9 +7,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "generated/index.hpp"
 #include "launch.hpp"
@@ -36,7 +38,10 @@ nlo_status fail(nlo_status st, const char* fmt, ...) {
 }
 
 constexpr int NPROC_ = NPROC;
-constexpr int MFMA_MIN_FLOWS = 12;
+// smallest colour basis for which MIXED picks the matrix cores automatically;
+// measured on MI355X with the nested helicity schedule the vector ALU was
+// faster for every process (6 and 24 flows), so automatic mode never does
+constexpr int MFMA_MIN_FLOWS = 1 << 30;
 
 }  // namespace
 
@@ -155,45 +160,45 @@ nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold) {
   return NLO_OK;
 }
 
-nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
-                          const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
-                          const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream) {
-  nlo_status st = check_ctx(ctx, real_proc, "nlo_subtracted");
+}  // extern "C"
+
+namespace {
+
+// validation shared by the direct call and batch items
+nlo_status check_subtracted(const nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                            const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                            nlo_prec prec, const nlo_fks_out* out, const FksSector** sec_out, const char* fn) {
+  nlo_status st = check_ctx(ctx, real_proc, fn);
   if (st) return st;
   const FksSector* sec = nullptr;
   for (const FksSector& f : FKS_TABLE)
     if (f.real == real_proc && f.i == fks_i && f.j == fks_j) sec = &f;
   if (!sec)
-    return fail(NLO_EUNSUPPORTED, "nlo_subtracted: no FKS sector (%d, %d) for process %s", fks_i, fks_j,
+    return fail(NLO_EUNSUPPORTED, "%s: no FKS sector (%d, %d) for process %s", fn, fks_i, fks_j,
                 PROC_STATIC[real_proc].name);
-  if (n < 0) return fail(NLO_EINVAL, "nlo_subtracted: n = %lld < 0", (long long)n);
-  if (ld < n) return fail(NLO_EINVAL, "nlo_subtracted: ld = %lld < n = %lld", (long long)ld, (long long)n);
-  if (n > 0x7fffffffLL) return fail(NLO_EINVAL, "nlo_subtracted: n too large");
+  if (n < 0) return fail(NLO_EINVAL, "%s: n = %lld < 0", fn, (long long)n);
+  if (ld < n) return fail(NLO_EINVAL, "%s: ld = %lld < n = %lld", fn, (long long)ld, (long long)n);
+  if (n > 0x7fffffffLL) return fail(NLO_EINVAL, "%s: n too large", fn);
   if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
-    return fail(NLO_EUNSUPPORTED, "nlo_subtracted: precision %d not supported (FP64, FP32, MIXED)", (int)prec);
-  if (!out) return fail(NLO_EINVAL, "nlo_subtracted: out is NULL");
-  if (n == 0) return NLO_OK;
-  if (!born_mom || !xi_tilde || !y || !phi || !out->W) return fail(NLO_EINVAL, "nlo_subtracted: NULL device pointer");
-  std::lock_guard<std::mutex> g(ctx->mu);
-  st = use_device(ctx, "nlo_subtracted");
-  if (st) return st;
-  hipStream_t s = (hipStream_t)hip_stream;
+    return fail(NLO_EUNSUPPORTED, "%s: precision %d not supported (FP64, FP32, MIXED)", fn, (int)prec);
+  if (!out) return fail(NLO_EINVAL, "%s: out is NULL", fn);
+  if (n > 0 && (!born_mom || !xi_tilde || !y || !phi || !out->W))
+    return fail(NLO_EINVAL, "%s: NULL device pointer", fn);
+  *sec_out = sec;
+  return NLO_OK;
+}
+
+size_t fks_ws_bytes(int real_proc, int64_t n) {
   const int nr = PROC_STATIC[real_proc].npart;
-  const size_t need = (size_t)n * (nr * 4 + 1) * sizeof(double) + (size_t)n * sizeof(unsigned) + 64;
-  if (need > ctx->ws_bytes) {
-    if (ctx->ws) {
-      if (hipStreamSynchronize(s) != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: stream sync failed");
-      (void)hipFree(ctx->ws);
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
-      ctx->ws = nullptr;
-      return fail(NLO_ENOMEM, "nlo_subtracted: workspace of %zu bytes", need);
-    }
-    ctx->ws_bytes = need;
-  }
-  char* base = static_cast<char*>(ctx->ws);
+  return (size_t)n * (nr * 4 + 1) * sizeof(double) + (size_t)n * sizeof(unsigned) + 128;
+}
+
+// the launch sequence of one FKS sector on stream s with workspace ws
+hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_proc, int64_t n, int64_t ld,
+                             const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                             const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* ws, hipStream_t s) {
+  const int nr = PROC_STATIC[real_proc].npart;
+  char* base = static_cast<char*>(ws);
   FksArgs a{};
   a.n = n;
   a.ld = ld;
@@ -205,7 +210,8 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
   a.real = reinterpret_cast<double*>(base);
   a.me2r = a.real + (size_t)n * nr * 4;
   a.inv = reinterpret_cast<unsigned*>(a.me2r + n);
-  a.cnt = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(a.inv + n) + (64 - ((n * sizeof(unsigned)) % 64)) % 64);
+  uintptr_t c = reinterpret_cast<uintptr_t>(a.inv + n);
+  a.cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
   a.thr = ctx->fks_thr;
   a.mode = prec == NLO_FP64 ? 1 : (prec == NLO_FP32 ? 0 : 2);
   a.scale_b = coupling_scale(sec->born, ctx->params);
@@ -224,7 +230,7 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
   a.real_out = out->real_mom;
   const int block = 256;
   hipError_t err = sec->map(a, block, s);
-  // real |M|^2 per bucket: FP32 (matrix-core colour in MIXED) from the front, FP64 from the back
+  // real |M|^2 per bucket: FP32 from the front, FP64 from the back
   const nlo_kernel_config& kc = ctx->cfg[real_proc][prec];
   LaunchArgs la{n, n, a.real, a.me2r, coupling_scale(real_proc, ctx->params), ctx->params.m_top, kc.block, s,
                 a.cnt, 0};
@@ -240,6 +246,50 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, s, n, (const double*)out->W, out->w_sum);
     err = hipGetLastError();
   }
+  return err;
+}
+
+}  // namespace
+
+struct nlo_plan {
+  nlo_ctx* ctx = nullptr;
+  std::vector<void*> ws;
+  std::vector<hipStream_t> streams;   // [0] capture origin, then the branches
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                          const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                          const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream) {
+  const FksSector* sec = nullptr;
+  nlo_status st = check_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_mom, xi_tilde, y, phi, prec, out, &sec,
+                                   "nlo_subtracted");
+  if (st) return st;
+  if (n == 0) return NLO_OK;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, "nlo_subtracted");
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t need = fks_ws_bytes(real_proc, n);
+  if (need > ctx->ws_bytes) {
+    if (ctx->ws) {
+      if (hipStreamSynchronize(s) != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: stream sync failed");
+      (void)hipFree(ctx->ws);
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+      ctx->ws = nullptr;
+      return fail(NLO_ENOMEM, "nlo_subtracted: workspace of %zu bytes", need);
+    }
+    ctx->ws_bytes = need;
+  }
+  hipError_t err = launch_subtracted(ctx, sec, real_proc, n, ld, born_mom, xi_tilde, y, phi, mask, prec, out,
+                                     ctx->ws, s);
   if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: launch failed: %s", hipGetErrorString(err));
   return NLO_OK;
 }
@@ -293,6 +343,184 @@ nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const doubl
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   return launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s);
+}
+
+
+nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int64_t ld, const double* mom,
+                        double* me2, void* hip_stream, nlo_kernel_config* best, double* ns_per_event) {
+  nlo_status st = check_ctx(ctx, proc_id, "nlo_autotune");
+  if (st) return st;
+  if (n <= 0 || ld < n) return fail(NLO_EINVAL, "nlo_autotune: need 0 < n <= ld");
+  if (!mom || !me2) return fail(NLO_EINVAL, "nlo_autotune: NULL device pointer");
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "nlo_autotune: precision %d not supported", (int)prec);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, "nlo_autotune");
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(NLO_EDEVICE, "nlo_autotune: event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(NLO_EDEVICE, "nlo_autotune: event");
+  }
+  const nlo_kernel_config saved = ctx->cfg[proc_id][prec];
+  nlo_kernel_config win = saved;
+  float win_ms = -1.0f;
+  nlo_status result = NLO_OK;
+  const int modes_fp32[2] = {1, 2};
+  const int nmodes = prec == NLO_FP64 ? 1 : 2;
+  for (int block = 64; block <= NLO_MAX_BLOCK && result == NLO_OK; block += 64) {
+    for (int m = 0; m < nmodes && result == NLO_OK; ++m) {
+      ctx->cfg[proc_id][prec] = nlo_kernel_config{block, prec == NLO_FP64 ? 1 : modes_fp32[m]};
+      // one warm-up, then three timed launches
+      for (int rep = 0; rep < 4 && result == NLO_OK; ++rep) {
+        if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) result = fail(NLO_EDEVICE, "nlo_autotune: record");
+        if (result == NLO_OK) result = launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s);
+      }
+      if (result != NLO_OK) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        result = fail(NLO_EDEVICE, "nlo_autotune: timing failed");
+        break;
+      }
+      if (win_ms < 0.0f || ms < win_ms) {
+        win_ms = ms;
+        win = ctx->cfg[proc_id][prec];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->cfg[proc_id][prec] = result == NLO_OK ? win : saved;
+  if (result != NLO_OK) return result;
+  if (best) *best = win;
+  if (ns_per_event) *ns_per_event = (double)win_ms * 1e6 / 3.0 / (double)n;
+  return NLO_OK;
+}
+
+nlo_status nlo_plan_destroy(nlo_plan* plan) {
+  if (!plan) return NLO_OK;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  for (hipEvent_t e : plan->events) (void)hipEventDestroy(e);
+  for (hipStream_t s : plan->streams) (void)hipStreamDestroy(s);
+  for (void* w : plan->ws) (void)hipFree(w);
+  delete plan;
+  return NLO_OK;
+}
+
+nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, int nbranches, nlo_plan** out) {
+  if (!out) return fail(NLO_EINVAL, "nlo_batch_plan: out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(NLO_EINVAL, "nlo_batch_plan: ctx is NULL");
+  if (nitems < 0 || (nitems > 0 && !items)) return fail(NLO_EINVAL, "nlo_batch_plan: bad item list");
+  if (nbranches == 0) nbranches = 4;
+  if (nbranches < 1 || nbranches > 16) return fail(NLO_EINVAL, "nlo_batch_plan: nbranches must be in [1, 16]");
+  // validate every item as the direct calls would
+  std::vector<const FksSector*> secs(nitems, nullptr);
+  std::vector<double> cost(nitems, 0.0);
+  for (int k = 0; k < nitems; ++k) {
+    const nlo_work_item& it = items[k];
+    nlo_status st;
+    if (it.kind == NLO_ITEM_ME2) {
+      st = check_ctx(ctx, it.proc_id, "nlo_batch_plan");
+      if (st) return st;
+      if (it.n < 0 || it.ld < it.n) return fail(NLO_EINVAL, "nlo_batch_plan: item %d: bad n/ld", k);
+      if (it.prec != NLO_FP64 && it.prec != NLO_FP32 && it.prec != NLO_MIXED)
+        return fail(NLO_EUNSUPPORTED, "nlo_batch_plan: item %d: precision %d not supported", k, (int)it.prec);
+      if (it.n > 0 && (!it.mom || !it.me2)) return fail(NLO_EINVAL, "nlo_batch_plan: item %d: NULL device pointer", k);
+    } else if (it.kind == NLO_ITEM_SUBTRACTED) {
+      st = check_subtracted(ctx, it.proc_id, it.fks_i, it.fks_j, it.n, it.ld, it.mom, it.xi_tilde, it.y, it.phi,
+                            it.prec, &it.fks_out, &secs[k], "nlo_batch_plan");
+      if (st) return st;
+    } else {
+      return fail(NLO_EINVAL, "nlo_batch_plan: item %d: unknown kind %d", k, (int)it.kind);
+    }
+    const ProcStatic& P = PROC_STATIC[it.proc_id];
+    cost[k] = (double)it.n * P.ngood * (P.nterm + P.ncur) * (it.kind == NLO_ITEM_SUBTRACTED ? 1.3 : 1.0) *
+              (it.prec == NLO_FP64 ? 4.0 : 1.0);
+  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  nlo_status st = use_device(ctx, "nlo_batch_plan");
+  if (st) return st;
+  nlo_plan* plan = new (std::nothrow) nlo_plan;
+  if (!plan) return fail(NLO_ENOMEM, "nlo_batch_plan: out of host memory");
+  plan->ctx = ctx;
+  auto bail = [&](nlo_status code, const char* what, hipError_t e) {
+    nlo_plan_destroy(plan);
+    return fail(code, "nlo_batch_plan: %s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e = hipSuccess;
+  // per-item FKS workspaces (items run concurrently)
+  std::vector<void*> item_ws(nitems, nullptr);
+  for (int k = 0; k < nitems; ++k) {
+    if (items[k].kind != NLO_ITEM_SUBTRACTED || items[k].n == 0) continue;
+    void* w = nullptr;
+    e = hipMalloc(&w, fks_ws_bytes(items[k].proc_id, items[k].n));
+    if (e != hipSuccess) return bail(NLO_ENOMEM, "workspace", e);
+    plan->ws.push_back(w);
+    item_ws[k] = w;
+  }
+  for (int b = 0; b <= nbranches; ++b) {
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(NLO_EDEVICE, "stream", e);
+    plan->streams.push_back(s);
+  }
+  for (int b = 0; b <= nbranches; ++b) {
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(NLO_EDEVICE, "event", e);
+    plan->events.push_back(ev);
+  }
+  // largest first onto the least-loaded branch
+  std::vector<int> idx(nitems);
+  for (int k = 0; k < nitems; ++k) idx[k] = k;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<double> load(nbranches, 0.0);
+  hipStream_t origin = plan->streams[0];
+  e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bail(NLO_EDEVICE, "begin capture", e);
+  hipError_t cap_err = hipEventRecord(plan->events[0], origin);
+  for (int b = 1; b <= nbranches && cap_err == hipSuccess; ++b) cap_err = hipStreamWaitEvent(plan->streams[b], plan->events[0], 0);
+  for (int q = 0; q < nitems && cap_err == hipSuccess; ++q) {
+    const int k = idx[q];
+    const nlo_work_item& it = items[k];
+    if (it.n == 0) continue;
+    int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[b] += cost[k];
+    hipStream_t s = plan->streams[1 + b];
+    if (it.kind == NLO_ITEM_ME2) {
+      nlo_status ls = launch_me2(ctx, it.proc_id, it.n, it.ld, it.mom, it.me2, it.prec, s);
+      if (ls) cap_err = hipErrorLaunchFailure;
+    } else {
+      cap_err = launch_subtracted(ctx, secs[k], it.proc_id, it.n, it.ld, it.mom, it.xi_tilde, it.y, it.phi, it.mask,
+                                  it.prec, &it.fks_out, item_ws[k], s);
+    }
+  }
+  for (int b = 1; b <= nbranches && cap_err == hipSuccess; ++b) {
+    cap_err = hipEventRecord(plan->events[b], plan->streams[b]);
+    if (cap_err == hipSuccess) cap_err = hipStreamWaitEvent(origin, plan->events[b], 0);
+  }
+  e = hipStreamEndCapture(origin, &plan->graph);
+  if (cap_err != hipSuccess) return bail(NLO_EDEVICE, "capture", cap_err);
+  if (e != hipSuccess) return bail(NLO_EDEVICE, "end capture", e);
+  e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(NLO_EDEVICE, "instantiate", e);
+  *out = plan;
+  return NLO_OK;
+}
+
+nlo_status nlo_batch_run(nlo_plan* plan, void* hip_stream) {
+  if (!plan || !plan->exec) return fail(NLO_EINVAL, "nlo_batch_run: plan is NULL");
+  std::lock_guard<std::mutex> g(plan->ctx->mu);
+  nlo_status st = use_device(plan->ctx, "nlo_batch_run");
+  if (st) return st;
+  hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_batch_run: graph launch failed: %s", hipGetErrorString(e));
+  return NLO_OK;
 }
 
 }  // extern "C"

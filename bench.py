@@ -61,6 +61,29 @@ def timed(ctx, proc, mom, out, prec, steps, warmup):
     return t0.elapsed_time(t1) / steps
 
 
+def measured_traffic(kernel, n):
+    """HBM bytes per launch from the committed rocprofv3 counter passes
+    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), scaled to
+    n events -- or None when the kernel sources have changed since the
+    counters were taken, or for another kernel."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gg_ttg_2p22_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("traffic:"):
+            rec = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
+    h = hashlib.sha256()
+    for f in ("generated/gg_ttg.hpp", "kernels.hpp", "helas.hpp", "launch.hpp"):
+        with open(os.path.join(ROOT, "paper_2503_07439_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if not rec or rec.get("sources") != h.hexdigest()[:16] or rec.get("kernel") != kernel.replace(" ", ""):
+        return None
+    return (int(rec["fetch_bytes"]) + int(rec["write_bytes"])) * n / int(rec["events"])
+
+
 def cpu_baseline(proc, mom_full, target_s=12.0):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (the first events of the batch)."""
@@ -133,17 +156,24 @@ def main():
         print("other colour unit: %.3f ms per step" % ms_o, file=sys.stderr, flush=True)
 
     # algorithmic flops per event: exact count of the generated source of the
-    # nested helicity schedule the kernels run (amplitudes + colour contraction)
+    # nested helicity schedule the kernels run (amplitudes + colour
+    # contraction), with operations on literal constants folded away
     with open(os.path.join(ROOT, "paper_2503_07439_amd", "flops.json")) as f:
         fl = json.load(f)[proc]
-    flops_event = fl["nested_flops_per_event"]
+    flops_event = fl["nested_flops_per_event_folded"]
     achieved = flops_event * n / (ms * 1e-3) / 1e12
     peak = PEAK["fp64" if args.prec == "fp64" else "fp32"]
     unit = "mfma" if (args.prec == "mixed" and info.ncolour >= 12) else "valu"
+    kernel = "k_me2_%s<%s%s>" % (unit, proc, ", float" if unit == "valu" and args.prec != "fp64" else
+                                 (", double" if args.prec == "fp64" else ""))
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "flops_per_event": flops_event,
-                "flops_per_event_per_helicity_evaluation": fl["ngood"] * (fl["amp_flops_per_hel"] + fl["colour_flops_per_hel"]),
-                "kernel": "k_me2_%s<%s%s>" % (unit, proc, ", float" if unit == "valu" and args.prec != "fp64" else (", double" if args.prec == "fp64" else ""))}
+                "traffic": measured_traffic(kernel, n), "kernel": kernel,
+                "flops_per_event": flops_event, "flops_per_event_as_written": fl["nested_flops_per_event"],
+                "bytes_per_event": 32 * info.npart + 8}
+    if args.prec != "fp64":
+        # packed FP32 instructions are not generated (compiler flag), so the
+        # single-issue vector FP32 rate is the attainable ceiling
+        roofline["frac_of_unpacked_fp32_peak"] = achieved / PEAK["fp64"]
 
     cpu = None
     if not args.no_cpu_baseline:

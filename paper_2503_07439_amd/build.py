@@ -88,7 +88,7 @@ def count_flops(verbose=True):
     algorithmic flop count per event used for the roofline)."""
     exe = os.path.join(OBJ, "opcount")
     src = os.path.join(CSRC, "opcount.hip")
-    cmd = [_hipcc(), "-O1", "-std=c++17", "--offload-arch=gfx950", "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
+    cmd = [_hipcc(), "-O0", "-std=c++17", "--offload-arch=gfx950", "-I" + CSRC, "-I" + os.path.join(ROOT, "include"),
            "-o", exe, src]
     subprocess.run(cmd, check=True, capture_output=True)
     out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout

@@ -1198,6 +1198,7 @@ static double born_spin_correlated(int proc, const V4* p, int leg, const V4& epe
 struct FksPair { int i, j; };            // j = -1: initial state (both beams)
 struct FksDef {
   int real, born;
+  int bornm = -1;                        // Born at the y -> -1 end when it differs (quark FKS parton)
   int nreal, nborn;
   std::vector<FksPair> pairs;            // all FKS pairs of the real process
   std::vector<char> gluon;               // per real leg
@@ -1211,6 +1212,7 @@ static FksDef fks_def(int real) {
   else if (real == GG_TTG) { d.born = GG_TT; d.pairs = {{4, -1}}; }
   else if (real == GG_TTGG) { d.born = GG_TTG; d.pairs = {{4, 5}, {5, 4}, {4, -1}, {5, -1}}; }
   else if (real == UU_TTG) { d.born = UU_TT; d.pairs = {{4, -1}}; }
+  else if (real == UG_TTU) { d.born = GG_TT; d.bornm = UU_TT; d.pairs = {{4, -1}}; }
   else d.born = -1;
   d.nborn = d.born >= 0 ? PROCS[d.born].npart : 0;
   d.gluon.assign(d.nreal, 0);
@@ -1432,6 +1434,34 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
     o.me2R = me2_event(d.real, kreal, nullptr);
     o.S = sector_value(d, kreal, sqs_real, i, -1);
     o.gR = xi * xi * (1.0 - y) * (1.0 + y) * o.me2R * o.S;
+    if (d.bornm >= 0) {
+      // The FKS parton is a quark (u g -> t tbar u, i = the final u): a soft
+      // quark is not singular (g_S = g_SC = 0), and each collinear end changes
+      // the flavour of the parton entering the hard process.
+      //   y -> +1: u(beam 1) -> u(final) + g(x p1); Born g g -> t tbar;
+      //            P_gq with its spin correlation, C_F [x B + 4 (1-x)/x B_perp]
+      //   y -> -1: g(beam 2) -> u(final) + ubar(x p2); Born u ubar -> t tbar;
+      //            P_qg = T_R [x^2 + (1-x)^2] B
+      // Real and Born are both averaged over their own initial spins and
+      // colours, so the unpolarised splitting functions apply as they stand
+      // (they are defined for averaged initial states); a ratio of spin x
+      // colour states n_q/n_g belongs only to raw, unaveraged sums.
+      const double TR = 0.5;
+      double x = 1.0 - xi;
+      double Bplus = me2_event(d.born, kb, nullptr);
+      double Bperp = born_spin_correlated(d.born, kb, 0, eperp);
+      double Bminus = me2_event(d.bornm, kb, nullptr);
+      double Pp = CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
+      double Pm = TR * (x * x + (1.0 - x) * (1.0 - x)) * Bminus;
+      o.B = Bplus;
+      o.gS = 0.0;
+      o.gC = 8.0 * xi * g2 / sb * Pp;
+      o.gCm = 8.0 * xi * g2 / sb * Pm;
+      o.gSC = 0.0;
+      o.gSCm = 0.0;
+      o.W = (o.gR - 0.5 * (1.0 + y) * o.gC - 0.5 * (1.0 - y) * o.gCm) / (xi * (1.0 - y) * (1.0 + y));
+      return o;
+    }
     double B;
     std::vector<double> Bkl;
     born_correlations(d.born, kb, B, Bkl);
@@ -1474,7 +1504,7 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
 
 extern "C" {
 
-// FKS-subtracted real emission.  real_proc in {ee_uug, gg_ttg, gg_ttgg, uu_ttg};
+// FKS-subtracted real emission.  real_proc in {ee_uug, gg_ttg, gg_ttgg, uu_ttg, ug_ttu};
 // (i, j) an FKS pair of that process (j = -1: initial state).  born_mom: SoA
 // [nborn][4][n]; xi_tilde, y, phi: [n].  out: [n][12] = xi, y, g_R, g_S, g_C,
 // g_Cm, g_SC, g_SCm, W, |M_R|^2, B, S.  real_out (optional): SoA [nreal][4][n].

@@ -11,7 +11,11 @@ fixes independently of the chosen conventions:
   limit, at the rate the expansion predicts (linear in xi for soft,
   square root of 1-y for collinear),
 * the soft and collinear counterterms share their double limit,
-* for e+e- -> u ubar g the soft counterterm equals its closed form.
+* for e+e- -> u ubar g the soft counterterm equals its closed form,
+* for u g -> t tbar u with the final quark as FKS parton, the two collinear
+  ends reach different Borns (g g -> t tbar through P_gq with its spin
+  correlation, u ubar -> t tbar through P_qg) and the soft quark is not
+  singular.
 The real matrix element in these ratios is the independently pinned |M|^2,
 so a wrong eikonal factor, colour correlator, splitting kernel or
 spin-correlation sign fails a limit."""
@@ -36,6 +40,8 @@ SECTORS = [
     ("gg_ttgg", 4, -1, "gg_ttg", (400.0, 2000.0)),
     ("gg_ttgg", 5, -1, "gg_ttg", (400.0, 2000.0)),
 ]
+# the FKS parton is a quark: collinear limits only, Born flavour changes at each end
+QUARK_SECTORS = [("ug_ttu", 4, -1, "gg_tt", (400.0, 2000.0))]
 
 
 def test_colour_linked_borns(orc):
@@ -74,7 +80,7 @@ def test_spin_correlated_born_completeness(orc):
                 assert abs(s / orc.me2(proc, mom[:, :, e:e + 1])[0] - 1) < 1e-12
 
 
-@pytest.mark.parametrize("real,i,j,born,rs", SECTORS)
+@pytest.mark.parametrize("real,i,j,born,rs", SECTORS + QUARK_SECTORS)
 def test_maps(orc, real, i, j, born, rs):
     mom, _ = events(born, 8, rs, stream=23)
     nb = mom.shape[0]
@@ -135,7 +141,7 @@ def test_soft_limit(orc, real, i, j, born, rs):
     assert np.all(slope > 0.8)
 
 
-@pytest.mark.parametrize("real,i,j,born,rs", SECTORS)
+@pytest.mark.parametrize("real,i,j,born,rs", SECTORS + QUARK_SECTORS)
 def test_collinear_limits(orc, real, i, j, born, rs):
     mom, _ = events(born, 6, rs, stream=26)
     for sign, key in ((1, "g_C"), (-1, "g_Cm")):
@@ -183,3 +189,32 @@ def test_ee_uug_soft_counterterm_closed_form(orc):
     S = (1 / d2) / (1 / d2 + 1 / d3)
     want = (1 - y) * 4 / s * G2 * eik * B * S
     assert np.allclose(r["g_S"], want, rtol=1e-9)
+
+
+def test_quark_emission_sector(orc):
+    """u g -> t tbar u, FKS parton = final u: no soft counterterm; g_R
+    vanishes linearly in xi (a soft quark is not singular), so W has a finite
+    soft limit; the collinear counterterms are the unpolarised splitting
+    functions times independently pinned Borns (checked above), and their
+    azimuthal average reproduces P_gq = C_F (1 + (1-x)^2)/x on the y -> +1 side."""
+    mom, _ = events("gg_tt", 6, (400.0, 2000.0), stream=28)
+    r1 = orc.fks("ug_ttu", 4, -1, mom, 1e-5, 0.3, 1.0)
+    r2 = orc.fks("ug_ttu", 4, -1, mom, 1e-7, 0.3, 1.0)
+    for k in ("g_S", "g_SC", "g_SCm"):
+        assert np.all(r1[k] == 0.0)
+    assert np.allclose(r1["g_R"] / r1["xi"], r2["g_R"] / r2["xi"], rtol=1e-3)
+    assert np.allclose(r1["W"], r2["W"], rtol=1e-3)
+    # azimuthal average at fixed y = 1 - 1e-9 (phi and phi + pi/2 cancel the
+    # cos 2 phi term of the spin correlation)
+    xt = 0.4
+    a = orc.fks("ug_ttu", 4, -1, mom, xt, 1 - 1e-9, 0.2)
+    b = orc.fks("ug_ttu", 4, -1, mom, xt, 1 - 1e-9, 0.2 + math.pi / 2)
+    x = 1 - a["xi"]
+    born = orc.me2("gg_tt", mom)
+    pgq = CF * (1 + (1 - x) ** 2) / x
+    sb = (mom[0, 0] + mom[1, 0]) ** 2
+    assert np.allclose(0.5 * (a["g_C"] + b["g_C"]), 8 * a["xi"] * G2 / sb * pgq * born, rtol=1e-12)
+    # the y -> -1 side: P_qg = T_R (x^2 + (1-x)^2) times the u ubar -> t tbar Born
+    c = orc.fks("ug_ttu", 4, -1, mom, xt, -(1 - 1e-9), 0.2)
+    pqg = 0.5 * (x ** 2 + (1 - x) ** 2)
+    assert np.allclose(c["g_Cm"], 8 * c["xi"] * G2 / sb * pqg * orc.me2("uu_tt", mom), rtol=1e-12)

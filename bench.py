@@ -11,7 +11,10 @@ One step = one nlo_me2 call over the whole batch (2^22 RAMBO events, m_t =
 Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--no-cpu-baseline] [--prec mixed|fp32|fp64]
+                    [--no-cpu-baseline] [--no-mix] [--prec mixed|fp32|fp64]
+
+Beside the headline line it times an uneven mix of Born, real and subtracted
+items as one captured-graph launch against per-item calls ("batch_mix").
 """
 import argparse
 import json
@@ -26,7 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "gg→tt̄g |M|^2 events/s (hel+colour summed) mixed vs FP64, at stated rel err"
-PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector ALU, TFLOP/s (published)
+# MI355X vector ALU peaks, TFLOP/s: FP32 and FP64 published; packed FP16 is
+# 256 CUs x 4 SIMDs x 16 lanes x 2 (pair) x 2 (FMA) x 2.4 GHz; BF16 has no
+# native arithmetic here and runs at the single-issue FP32 rate
+PEAK = {"fp32": 157.3, "fp64": 78.6, "fp16": 157.3, "bf16": 78.6}
 
 
 def parse():
@@ -35,10 +41,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gg_ttg_400_2000")
-    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp32", "fp64", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--events", type=int, default=0, help="override the batch size")
+    ap.add_argument("--no-mix", action="store_true", help="skip the batched-mix leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -59,6 +66,70 @@ def timed(ctx, proc, mom, out, prec, steps, warmup):
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def mix_leg(ctx, steps):
+    """An uneven mix of Born, real and subtracted items (MIXED precision):
+    one captured-graph launch of the whole mix against the same items issued
+    one call after another on the stream."""
+    import torch
+    import paper_2503_07439_amd as nl
+    from nlo_inputs.workloads import MIX_ITEMS, MIX_STREAM, events, fks_variables, mix_counts
+    counts = mix_counts()
+    items, keep, calls = [], [], []
+    stream = torch.cuda.current_stream().cuda_stream
+    for k, ((kind, proc, pair, born), n) in enumerate(zip(MIX_ITEMS, counts)):
+        n = int(n)
+        it = nl.nlo_work_item()
+        it.proc_id, it.n, it.ld, it.prec = nl.proc_id(proc), n, n, nl.NLO_MIXED
+        if kind == "me2":
+            mom = torch.from_numpy(events(proc, n, (400.0, 2000.0), stream=MIX_STREAM + k)[0]).cuda()
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            it.kind, it.mom, it.me2 = nl.NLO_ITEM_ME2, mom.data_ptr(), out.data_ptr()
+            keep += [mom, out]
+            calls.append(lambda it=it: nl.nlo_me2(ctx.ctx, it.proc_id, it.n, it.ld, it.mom, it.me2, it.prec, stream))
+        else:
+            mom = torch.from_numpy(events(born, n, (400.0, 2000.0), stream=MIX_STREAM + k)[0]).cuda()
+            xt, y, phi = (torch.from_numpy(np.ascontiguousarray(a)).cuda()
+                          for a in fks_variables(n, stream=MIX_STREAM + k, initial_state=pair[1] < 0))
+            W = torch.empty(n, dtype=torch.float64, device="cuda")
+            wsum = torch.empty(1, dtype=torch.float64, device="cuda")
+            it.kind, (it.fks_i, it.fks_j) = nl.NLO_ITEM_SUBTRACTED, pair
+            it.mom, it.xi_tilde, it.y, it.phi = mom.data_ptr(), xt.data_ptr(), y.data_ptr(), phi.data_ptr()
+            it.fks_out.W, it.fks_out.w_sum = W.data_ptr(), wsum.data_ptr()
+            keep += [mom, xt, y, phi, W, wsum]
+            calls.append(lambda it=it: nl.nlo_subtracted(ctx.ctx, it.proc_id, it.fks_i, it.fks_j, it.n, it.ld, it.mom,
+                                                         it.xi_tilde, it.y, it.phi, None, it.prec, it.fks_out, stream))
+        items.append(it)
+    plan = nl.nlo_batch_plan(ctx.ctx, items, 4)
+
+    def run_graph():
+        nl.nlo_batch_run(plan, stream)
+
+    def run_direct():
+        for c in calls:
+            c()
+
+    res = {}
+    try:
+        for name, fn in (("graph", run_graph), ("direct", run_direct)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            res[name] = t0.elapsed_time(t1) / steps
+    finally:
+        nl.nlo_plan_destroy(plan)
+    total = int(counts.sum())
+    return {"items": [[k, p, list(q) if q else None, int(c)] for (k, p, q, _), c in zip(MIX_ITEMS, counts)],
+            "events": total, "precision": "mixed", "graph_ms": res["graph"], "direct_ms": res["direct"],
+            "graph_events_per_s": total / (res["graph"] * 1e-3), "graph_speedup": res["direct"] / res["graph"]}
 
 
 def measured_traffic(kernel, n):
@@ -162,18 +233,26 @@ def main():
         fl = json.load(f)[proc]
     flops_event = fl["nested_flops_per_event_folded"]
     achieved = flops_event * n / (ms * 1e-3) / 1e12
-    peak = PEAK["fp64" if args.prec == "fp64" else "fp32"]
+    peak = PEAK[args.prec if args.prec in PEAK else "fp32"]
     unit = "mfma" if (args.prec == "mixed" and info.ncolour >= 12) else "valu"
-    kernel = "k_me2_%s<%s%s>" % (unit, proc, ", float" if unit == "valu" and args.prec != "fp64" else
-                                 (", double" if args.prec == "fp64" else ""))
+    if args.prec in ("fp16", "bf16"):
+        kernel = "k_me2_pair<%s, %s>" % (proc, "f16x2" if args.prec == "fp16" else "bf16x2")
+    else:
+        kernel = "k_me2_%s<%s%s>" % (unit, proc, ", float" if unit == "valu" and args.prec != "fp64" else
+                                     (", double" if args.prec == "fp64" else ""))
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(kernel, n), "kernel": kernel,
                 "flops_per_event": flops_event, "flops_per_event_as_written": fl["nested_flops_per_event"],
                 "bytes_per_event": 32 * info.npart + 8}
-    if args.prec != "fp64":
+    if args.prec in ("mixed", "fp32"):
         # packed FP32 instructions are not generated (compiler flag), so the
         # single-issue vector FP32 rate is the attainable ceiling
         roofline["frac_of_unpacked_fp32_peak"] = achieved / PEAK["fp64"]
+
+    mix = None
+    if not args.no_mix:
+        mix = mix_leg(ctx, max(3, args.steps // 4))
+        print("mix: graph %.3f ms, direct %.3f ms" % (mix["graph_ms"], mix["direct_ms"]), file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -187,12 +266,14 @@ def main():
     line = {
         "metric": METRIC, "value": n / (ms * 1e-3), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp16": "f16", "bf16": "bf16"}.get(args.prec, "f32"),
+        "data": "synthetic",
         "config": {"workload": args.workload, "process": info.name.decode(), "events": n,
                    "sqrt_s_hat_GeV": list(rs) if isinstance(rs, tuple) else rs, "m_top_GeV": 173.0,
                    "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
                    "helicities": info.ngood_hel},
         "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
+        "batch_mix": mix,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

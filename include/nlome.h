@@ -54,7 +54,21 @@ typedef enum {
  * vector ALU.  NLO_MIXED for |M|^2 is NLO_FP32 with the colour contraction on
  * the matrix cores when the process has at least 12 colour flows (vector ALU
  * below, where it is faster; nlo_set_kernel_config overrides); for subtracted
- * weights it also routes events near soft/collinear limits to FP64. */
+ * weights it also routes events near soft/collinear limits to FP64.
+ * NLO_FP16 / NLO_BF16 (nlo_me2 and ME2 batch items only): amplitudes in
+ * half-width floats on packed pairs of events, with momenta and masses
+ * divided by sqrt(s_hat) of the event first (|M|^2 of N particles is
+ * s_hat^(4-N) times that of the scaled momenta, applied in double); FP64
+ * prologue, colour contraction in float, helicity sum in double.  The
+ * external wavefunctions of each event are also scaled by a power of two set
+ * by its largest propagator denominator, which keeps the intermediate values
+ * inside the FP16 range.  Events whose largest denominator exceeds 2^14/s_hat
+ * (close to a soft or collinear pole, where the diagrams cancel beyond what
+ * a half-width significand resolves) are listed and evaluated again in FP32
+ * by a second launch; this uses a workspace owned by the context (n + 32
+ * 32-bit words, grown like the one of nlo_subtracted).  BF16 has no native
+ * arithmetic on this GPU: every operation rounds through FP32.
+ * These are accuracy studies, not production precisions. */
 typedef enum { NLO_FP64 = 0, NLO_FP32 = 1, NLO_FP16 = 2, NLO_BF16 = 3, NLO_MIXED = 4 } nlo_prec;
 
 /* Physics parameters: fixed couplings (no running), top mass, zero widths,
@@ -115,7 +129,8 @@ nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const
 nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec, nlo_kernel_config* cfg);
 
 /* Autotuner: times every launch configuration of (proc_id, prec) -- block of
- * 64/128/192/256 threads and, for FP32/MIXED, the colour contraction on the
+ * 64/128/192/256 threads (FP16/BF16 blocks cover two events per thread)
+ * and, for FP32/MIXED, the colour contraction on the
  * vector ALU or the matrix cores -- on the caller's sample batch (device
  * momenta, n events, scratch output me2 of n doubles) with HIP events on the
  * given stream, keeps the fastest for this context and returns it in *best
@@ -127,8 +142,8 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
 /* Squared matrix elements (the paper's Born and real equations):
  *   me2[e] = avg_factor * sum_{helicities} sum_{colours} |M(mom_e)|^2
  * for e in [0, n).  mom: device, layout above, npart particles.  me2: device
- * float64 [n].  prec: NLO_FP64, NLO_FP32 or NLO_MIXED.  Per-event values are
- * written only; nothing is accumulated. */
+ * float64 [n].  prec: any nlo_prec.  Per-event values are written only;
+ * nothing is accumulated. */
 nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
                    nlo_prec prec, void* hip_stream);
 
@@ -151,7 +166,12 @@ typedef struct {
  * subtraction; its branch-free loop evaluates Born, real, soft and collinear
  * terms at every point, then zeroes those whose cuts fail).
  *   real_proc: ee_uug (pairs (4,2), (4,3)), gg_ttg (4,-1), uu_ttg (4,-1),
- *              gg_ttgg ((4,5), (5,4), (4,-1), (5,-1));  fks_j = -1: both beams.
+ *              ug_ttu (4,-1), gg_ttgg ((4,5), (5,4), (4,-1), (5,-1));
+ *              fks_j = -1: both beams.  In ug_ttu the FKS parton is the final
+ *              quark: g_S = g_SC = 0, g_C uses the g g -> t tbar Born (beam 1
+ *              quark turned gluon) and g_Cm the u ubar -> t tbar Born (beam 2
+ *              gluon turned antiquark); born_mom are then the common t tbar
+ *              kinematics and `born` reports the g g -> t tbar Born.
  *   born_mom:  device, Born momenta (the real process without particle
  *              fks_i), layout above, in the Born centre-of-mass frame.
  *   xi_tilde, y, phi: device [n] radiation variables: xi = xi_tilde * xi_max

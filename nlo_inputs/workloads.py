@@ -101,3 +101,25 @@ CONFIGS = {
 def config_events(name, n=None, first=0):
     proc, nfull, rs, stream = CONFIGS[name]
     return events(proc, nfull if n is None else n, rs, stream=stream, first=first)
+
+
+# Uneven mix of Born, real and subtracted items for one batched launch:
+# (kind, process, FKS pair (i, j; j = -1 both beams), Born process), each item
+# with floor(10^U(3, 6)) events drawn from the seed; momenta with sqrt(s_hat)
+# uniform in [400, 2000] GeV, stream MIX_STREAM + item index.
+MIX_ITEMS = [
+    ("me2", "gg_tt", None, None),
+    ("me2", "uu_tt", None, None),
+    ("me2", "gg_ttg", None, None),
+    ("me2", "uu_ttg", None, None),
+    ("me2", "ug_ttu", None, None),
+    ("sub", "gg_ttg", (4, -1), "gg_tt"),
+    ("sub", "uu_ttg", (4, -1), "uu_tt"),
+    ("sub", "ug_ttu", (4, -1), "gg_tt"),
+]
+MIX_STREAM = 50
+
+
+def mix_counts(lo=3.0, hi=6.0, seed=SEED, stream=MIX_STREAM):
+    u = uniforms(seed, stream, np.arange(len(MIX_ITEMS)), 0)[:, 0]
+    return np.floor(10.0 ** (lo + (hi - lo) * u)).astype(np.int64)

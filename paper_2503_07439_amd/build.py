@@ -69,7 +69,8 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     os.makedirs(OBJ, exist_ok=True)
     srcs = [os.path.join(CSRC, "capi.hip")] + list(tus)
     # the largest process first so the long poles start early
-    srcs.sort(key=lambda p: 0 if ("gg_ttgg" in p and "fks" not in p) else (1 if "gg_ttg" in p else 2))
+    srcs.sort(key=lambda p: 0 if p.endswith("tu_gg_ttgg_4.hip") else
+              (1 if ("gg_ttgg" in p and "fks" not in p) else (2 if "gg_ttg" in p else 3)))
     jobs = jobs or min(16, os.cpu_count() or 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra_flags, verbose, force), srcs))

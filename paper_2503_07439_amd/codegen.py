@@ -1008,6 +1008,15 @@ def emit_process(p):
                          % (j, mterm))
         L.append("    }")
     L.append("  }")
+    # exact power-of-two rescaling of the external wavefunctions (used by the
+    # half-width kernels to keep intermediate values inside the FP16 range)
+    L.append("  // multiply the external wavefunctions by powers of two with product 2^-b;")
+    L.append("  // |M|^2 then scales by exactly 2^-2b")
+    L.append("  template <class T> NLO_HD static void scale_legs(Pre<T>& s, int b) {")
+    L.append("    const int q = b / NPART, r = b % NPART;")
+    for k in range(N):
+        L.append("    scale_leg(s.x%d, T(ldexpf(1.0f, -(q + (%d < r ? 1 : 0)))));" % (k, k))
+    L.append("  }")
     # amplitudes for one helicity
     L.append("  // OVR >= 0: the external wavefunction of leg OVR is replaced by *ov")
     L.append("  template <class T, int OVR = -1> NLO_HD static void amplitudes(const Pre<T>& s, int h, T mt, cx<T> (&J)[NFLOW],")
@@ -1091,7 +1100,7 @@ def emit_process(p):
     return "\n".join(L)
 
 
-VARIANTS = ("VAR_F64", "VAR_F32", "VAR_MFMA")
+VARIANTS = ("VAR_F64", "VAR_F32", "VAR_MFMA", "VAR_F16", "VAR_BF16")
 
 
 def _write_if_changed(path, src):
@@ -1101,16 +1110,18 @@ def _write_if_changed(path, src):
             f.write(src)
 
 
-# FKS sectors: (real process, Born process, I, J (-1: both beams), all FKS pairs of the real process)
+# FKS sectors: (real process, Born process, I, J (-1: both beams), all FKS pairs of
+# the real process, Born at the y -> -1 end when it differs from the one at y -> +1)
 FKS_SECTORS = [
-    ("ee_uug", "ee_uu", 4, 2, [(4, 2), (4, 3)]),
-    ("ee_uug", "ee_uu", 4, 3, [(4, 2), (4, 3)]),
-    ("gg_ttg", "gg_tt", 4, -1, [(4, -1)]),
-    ("uu_ttg", "uu_tt", 4, -1, [(4, -1)]),
-    ("gg_ttgg", "gg_ttg", 4, 5, [(4, 5), (5, 4), (4, -1), (5, -1)]),
-    ("gg_ttgg", "gg_ttg", 5, 4, [(4, 5), (5, 4), (4, -1), (5, -1)]),
-    ("gg_ttgg", "gg_ttg", 4, -1, [(4, 5), (5, 4), (4, -1), (5, -1)]),
-    ("gg_ttgg", "gg_ttg", 5, -1, [(4, 5), (5, 4), (4, -1), (5, -1)]),
+    ("ee_uug", "ee_uu", 4, 2, [(4, 2), (4, 3)], None),
+    ("ee_uug", "ee_uu", 4, 3, [(4, 2), (4, 3)], None),
+    ("gg_ttg", "gg_tt", 4, -1, [(4, -1)], None),
+    ("uu_ttg", "uu_tt", 4, -1, [(4, -1)], None),
+    ("ug_ttu", "gg_tt", 4, -1, [(4, -1)], "uu_tt"),
+    ("gg_ttgg", "gg_ttg", 4, 5, [(4, 5), (5, 4), (4, -1), (5, -1)], None),
+    ("gg_ttgg", "gg_ttg", 5, 4, [(4, 5), (5, 4), (4, -1), (5, -1)], None),
+    ("gg_ttgg", "gg_ttg", 4, -1, [(4, 5), (5, 4), (4, -1), (5, -1)], None),
+    ("gg_ttgg", "gg_ttg", 5, -1, [(4, 5), (5, 4), (4, -1), (5, -1)], None),
 ]
 
 
@@ -1118,7 +1129,7 @@ def sector_name(real, i, j):
     return "fks_%s_%d_%s" % (real, i, "0" if j < 0 else str(j))
 
 
-def emit_sector(procs, real, born, i, j, pairs):
+def emit_sector(procs, real, born, i, j, pairs, bornm=None):
     R = procs[real]
     B = procs[born]
     nr, nb = R.npart, B.npart
@@ -1135,6 +1146,10 @@ def emit_sector(procs, real, born, i, j, pairs):
     L = ["struct %s {" % name,
          "  using Real = %s;" % real,
          "  using Born = %s;" % born,
+         "  using BornM = %s;   // Born at the y -> -1 end" % (bornm or born),
+         "  // FKS parton I is a quark: no soft singularity, and the incoming parton",
+         "  // changes flavour at each collinear end (Born and BornM)",
+         "  static constexpr bool QUARK_I = %s;" % ("true" if bornm else "false"),
          "  static constexpr int I = %d, J = %d, JB = %d, NR = %d, NB = %d, NPAIR = %d;"
          % (i, j, bmap[j] if j >= 0 else -1, nr, nb, len(pairs)),
          "  static constexpr int BMAP[NR] = {%s};" % ", ".join(str(x) for x in bmap),
@@ -1187,16 +1202,17 @@ def generate(out_dir):
     # FKS sectors
     byname = {p.name: p for p in procs}
     index.append("struct FksSector {")
-    index.append("  const char* name; int real, born, i, j;")
+    index.append("  const char* name; int real, born, bornm, i, j;")
     index.append("  hipError_t (*map)(const FksArgs&, int, hipStream_t);")
     index.append("  hipError_t (*born_fn[2])(const FksArgs&, int, int, hipStream_t);   // [0] double, [1] float")
     index.append("};")
     decl, rows = [], []
     pid = {p.name: k for k, p in enumerate(procs)}
-    for real, born, i, j, pairs in FKS_SECTORS:
-        name, struct = emit_sector(byname, real, born, i, j, pairs)
-        hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "%s.hpp"' % real,
-                          '#include "%s.hpp"' % born, "namespace nlo {", struct, "}  // namespace nlo", ""])
+    for real, born, i, j, pairs, bornm in FKS_SECTORS:
+        name, struct = emit_sector(byname, real, born, i, j, pairs, bornm)
+        incs = ['#include "%s.hpp"' % x for x in dict.fromkeys([real, born, bornm or born])]
+        hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once"] + incs +
+                         ["namespace nlo {", struct, "}  // namespace nlo", ""])
         _write_if_changed(os.path.join(out_dir, name + ".hpp"), hdr)
         for v, T in enumerate(("double", "float")):
             body = ['#include "../fks.hpp"', '#include "%s.hpp"' % name, "namespace nlo {"]
@@ -1210,7 +1226,8 @@ def generate(out_dir):
         decl.append("hipError_t %s_map(const FksArgs&, int, hipStream_t);" % name)
         decl.append("hipError_t %s_born0(const FksArgs&, int, int, hipStream_t);" % name)
         decl.append("hipError_t %s_born1(const FksArgs&, int, int, hipStream_t);" % name)
-        rows.append('  {"%s", %d, %d, %d, %d, %s_map, {%s_born0, %s_born1}},' % (name, pid[real], pid[born], i, j, name, name, name))
+        rows.append('  {"%s", %d, %d, %d, %d, %d, %s_map, {%s_born0, %s_born1}},' % (
+            name, pid[real], pid[born], pid[bornm or born], i, j, name, name, name))
     index.extend(decl)
     index.append("constexpr int NFKS = %d;" % len(FKS_SECTORS))
     index.append("static const FksSector FKS_TABLE[NFKS] = {")

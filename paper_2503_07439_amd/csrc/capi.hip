@@ -83,12 +83,22 @@ double coupling_scale(int pid, const nlo_params& p) {
   return P.avg * std::pow(gs2, P.gs_pow) * std::pow(e2, P.e_pow);
 }
 
+bool half_prec(nlo_prec p) { return p == NLO_FP16 || p == NLO_BF16; }
+
+// workspace of a half-width |M|^2 launch: the FP32 fallback list (n entries)
+// and its counter
+size_t half_ws_bytes(int64_t n) { return (size_t)n * sizeof(unsigned) + 128; }
+
 nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double* mom, double* out, nlo_prec prec,
-                      hipStream_t st) {
+                      hipStream_t st, void* ws = nullptr) {
   const nlo_kernel_config& kc = ctx->cfg[pid][prec];
   int var;
   if (prec == NLO_FP64) {
     var = VAR_F64;
+  } else if (prec == NLO_FP16) {
+    var = VAR_F16;
+  } else if (prec == NLO_BF16) {
+    var = VAR_BF16;
   } else {
     int mode = kc.colour_mode;
     // automatic: matrix cores when the colour contraction is large enough to
@@ -98,8 +108,32 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
     var = (mode == 2) ? VAR_MFMA : VAR_F32;
   }
   LaunchArgs a{n, ld, mom, out, coupling_scale(pid, ctx->params), ctx->params.m_top, kc.block, st};
+  if (half_prec(prec)) {
+    if (!ws) return fail(NLO_EINVAL, "nlo_me2: internal: no workspace for a half-width launch");
+    a.fb_list = static_cast<unsigned*>(ws);
+    const uintptr_t c = reinterpret_cast<uintptr_t>(a.fb_list + n);
+    a.fb_cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
+  }
   hipError_t err = ME2_LAUNCH[pid][var](a);
   if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_me2: launch failed: %s", hipGetErrorString(err));
+  return NLO_OK;
+}
+
+// grow the context's workspace to at least need bytes (synchronising the
+// stream before freeing the old one); caller holds ctx->mu
+nlo_status ensure_ws(nlo_ctx* ctx, size_t need, hipStream_t s, const char* fn) {
+  if (need <= ctx->ws_bytes) return NLO_OK;
+  if (ctx->ws) {
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(NLO_EDEVICE, "%s: stream sync failed", fn);
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(NLO_ENOMEM, "%s: workspace of %zu bytes", fn, need);
+  }
+  ctx->ws_bytes = need;
   return NLO_OK;
 }
 
@@ -215,6 +249,7 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.thr = ctx->fks_thr;
   a.mode = prec == NLO_FP64 ? 1 : (prec == NLO_FP32 ? 0 : 2);
   a.scale_b = coupling_scale(sec->born, ctx->params);
+  a.scale_bm = coupling_scale(sec->bornm, ctx->params);
   a.g2 = 4.0 * M_PI * ctx->params.alpha_s;
   a.mt = ctx->params.m_top;
   a.xi_out = out->xi;
@@ -274,20 +309,8 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
   st = use_device(ctx, "nlo_subtracted");
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  const size_t need = fks_ws_bytes(real_proc, n);
-  if (need > ctx->ws_bytes) {
-    if (ctx->ws) {
-      if (hipStreamSynchronize(s) != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: stream sync failed");
-      (void)hipFree(ctx->ws);
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
-      ctx->ws = nullptr;
-      return fail(NLO_ENOMEM, "nlo_subtracted: workspace of %zu bytes", need);
-    }
-    ctx->ws_bytes = need;
-  }
+  st = ensure_ws(ctx, fks_ws_bytes(real_proc, n), s, "nlo_subtracted");
+  if (st) return st;
   hipError_t err = launch_subtracted(ctx, sec, real_proc, n, ld, born_mom, xi_tilde, y, phi, mask, prec, out,
                                      ctx->ws, s);
   if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: launch failed: %s", hipGetErrorString(err));
@@ -311,7 +334,7 @@ nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const
     return fail(NLO_EINVAL, "nlo_set_kernel_config: block %d must be a multiple of 64 in [64, %d]", cfg->block,
                 NLO_MAX_BLOCK);
   if (cfg->colour_mode < 0 || cfg->colour_mode > 2) return fail(NLO_EINVAL, "nlo_set_kernel_config: bad colour_mode");
-  if (cfg->colour_mode == 2 && prec == NLO_FP64)
+  if (cfg->colour_mode == 2 && prec != NLO_FP32 && prec != NLO_MIXED)
     return fail(NLO_EUNSUPPORTED, "nlo_set_kernel_config: matrix-core colour contraction is FP32 only");
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->cfg[proc_id][prec] = *cfg;
@@ -333,8 +356,7 @@ nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const doubl
   if (st) return st;
   if (n < 0) return fail(NLO_EINVAL, "nlo_me2: n = %lld < 0", (long long)n);
   if (ld < n) return fail(NLO_EINVAL, "nlo_me2: ld = %lld < n = %lld", (long long)ld, (long long)n);
-  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
-    return fail(NLO_EUNSUPPORTED, "nlo_me2: precision %d not supported (FP64, FP32, MIXED)", (int)prec);
+  if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "nlo_me2: bad precision %d", (int)prec);
   if (n == 0) return NLO_OK;
   if (!mom || !me2) return fail(NLO_EINVAL, "nlo_me2: NULL device pointer");
   if ((int64_t)((n + 1023) / 64) > (int64_t)0x7fffffff) return fail(NLO_EINVAL, "nlo_me2: n too large");
@@ -342,7 +364,12 @@ nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const doubl
   st = use_device(ctx, "nlo_me2");
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  return launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s);
+  if (half_prec(prec)) {
+    if (n > 0x7fffffffLL) return fail(NLO_EINVAL, "nlo_me2: n too large for FP16/BF16 (event list)");
+    st = ensure_ws(ctx, half_ws_bytes(n), s, "nlo_me2");
+    if (st) return st;
+  }
+  return launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s, ctx->ws);
 }
 
 
@@ -352,12 +379,15 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
   if (st) return st;
   if (n <= 0 || ld < n) return fail(NLO_EINVAL, "nlo_autotune: need 0 < n <= ld");
   if (!mom || !me2) return fail(NLO_EINVAL, "nlo_autotune: NULL device pointer");
-  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
-    return fail(NLO_EUNSUPPORTED, "nlo_autotune: precision %d not supported", (int)prec);
+  if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "nlo_autotune: bad precision %d", (int)prec);
   std::lock_guard<std::mutex> g(ctx->mu);
   st = use_device(ctx, "nlo_autotune");
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
+  if (half_prec(prec)) {
+    st = ensure_ws(ctx, half_ws_bytes(n), s, "nlo_autotune");
+    if (st) return st;
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(NLO_EDEVICE, "nlo_autotune: event");
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -369,14 +399,15 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
   float win_ms = -1.0f;
   nlo_status result = NLO_OK;
   const int modes_fp32[2] = {1, 2};
-  const int nmodes = prec == NLO_FP64 ? 1 : 2;
+  const bool fp32 = prec == NLO_FP32 || prec == NLO_MIXED;
+  const int nmodes = fp32 ? 2 : 1;
   for (int block = 64; block <= NLO_MAX_BLOCK && result == NLO_OK; block += 64) {
     for (int m = 0; m < nmodes && result == NLO_OK; ++m) {
-      ctx->cfg[proc_id][prec] = nlo_kernel_config{block, prec == NLO_FP64 ? 1 : modes_fp32[m]};
+      ctx->cfg[proc_id][prec] = nlo_kernel_config{block, fp32 ? modes_fp32[m] : 1};
       // one warm-up, then three timed launches
       for (int rep = 0; rep < 4 && result == NLO_OK; ++rep) {
         if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) result = fail(NLO_EDEVICE, "nlo_autotune: record");
-        if (result == NLO_OK) result = launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s);
+        if (result == NLO_OK) result = launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s, ctx->ws);
       }
       if (result != NLO_OK) break;
       float ms = 0.0f;
@@ -428,8 +459,10 @@ nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, 
       st = check_ctx(ctx, it.proc_id, "nlo_batch_plan");
       if (st) return st;
       if (it.n < 0 || it.ld < it.n) return fail(NLO_EINVAL, "nlo_batch_plan: item %d: bad n/ld", k);
-      if (it.prec != NLO_FP64 && it.prec != NLO_FP32 && it.prec != NLO_MIXED)
-        return fail(NLO_EUNSUPPORTED, "nlo_batch_plan: item %d: precision %d not supported", k, (int)it.prec);
+      if ((int)it.prec < 0 || (int)it.prec > NLO_MIXED)
+        return fail(NLO_EINVAL, "nlo_batch_plan: item %d: bad precision %d", k, (int)it.prec);
+      if (half_prec(it.prec) && it.n > 0x7fffffffLL)
+        return fail(NLO_EINVAL, "nlo_batch_plan: item %d: n too large for FP16/BF16", k);
       if (it.n > 0 && (!it.mom || !it.me2)) return fail(NLO_EINVAL, "nlo_batch_plan: item %d: NULL device pointer", k);
     } else if (it.kind == NLO_ITEM_SUBTRACTED) {
       st = check_subtracted(ctx, it.proc_id, it.fks_i, it.fks_j, it.n, it.ld, it.mom, it.xi_tilde, it.y, it.phi,
@@ -440,7 +473,7 @@ nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, 
     }
     const ProcStatic& P = PROC_STATIC[it.proc_id];
     cost[k] = (double)it.n * P.ngood * (P.nterm + P.ncur) * (it.kind == NLO_ITEM_SUBTRACTED ? 1.3 : 1.0) *
-              (it.prec == NLO_FP64 ? 4.0 : 1.0);
+              (it.prec == NLO_FP64 ? 4.0 : (it.prec == NLO_FP16 ? 0.6 : (it.prec == NLO_BF16 ? 1.5 : 1.0)));
   }
   std::lock_guard<std::mutex> g(ctx->mu);
   nlo_status st = use_device(ctx, "nlo_batch_plan");
@@ -453,12 +486,13 @@ nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, 
     return fail(code, "nlo_batch_plan: %s: %s", what, hipGetErrorString(e));
   };
   hipError_t e = hipSuccess;
-  // per-item FKS workspaces (items run concurrently)
+  // per-item workspaces of FKS and half-width items (items run concurrently)
   std::vector<void*> item_ws(nitems, nullptr);
   for (int k = 0; k < nitems; ++k) {
-    if (items[k].kind != NLO_ITEM_SUBTRACTED || items[k].n == 0) continue;
+    const bool sub = items[k].kind == NLO_ITEM_SUBTRACTED, half = !sub && half_prec(items[k].prec);
+    if ((!sub && !half) || items[k].n == 0) continue;
     void* w = nullptr;
-    e = hipMalloc(&w, fks_ws_bytes(items[k].proc_id, items[k].n));
+    e = hipMalloc(&w, sub ? fks_ws_bytes(items[k].proc_id, items[k].n) : half_ws_bytes(items[k].n));
     if (e != hipSuccess) return bail(NLO_ENOMEM, "workspace", e);
     plan->ws.push_back(w);
     item_ws[k] = w;
@@ -493,7 +527,7 @@ nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, 
     load[b] += cost[k];
     hipStream_t s = plan->streams[1 + b];
     if (it.kind == NLO_ITEM_ME2) {
-      nlo_status ls = launch_me2(ctx, it.proc_id, it.n, it.ld, it.mom, it.me2, it.prec, s);
+      nlo_status ls = launch_me2(ctx, it.proc_id, it.n, it.ld, it.mom, it.me2, it.prec, s, item_ws[k]);
       if (ls) cap_err = hipErrorLaunchFailure;
     } else {
       cap_err = launch_subtracted(ctx, secs[k], it.proc_id, it.n, it.ld, it.mom, it.xi_tilde, it.y, it.phi, it.mask,

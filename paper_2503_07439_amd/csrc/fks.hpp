@@ -209,6 +209,7 @@ struct FksArgs {
   double thr;                          // route to FP64 when min(xi, 1-|y|) < thr
   int mode;                            // 0: all FP32, 1: all FP64, 2: route
   double scale_b, g2, mt;
+  double scale_bm;                     // coupling x average factor of the y -> -1 Born (quark FKS parton)
   double *xi_out, *born_out, *gR, *gS, *gC, *gCm, *gSC, *gSCm, *W;   // [n], any may be null but W
   uint8_t* status;                     // [n] or null
   double* real_out;                    // [NR][4][ld] (event order) or null
@@ -282,6 +283,77 @@ __device__ double born_spin(const typename BP::template Pre<T>& s, const double*
   return acc;
 }
 
+// Algorithm-2 masks (a failed cut zeroes its contribution after evaluation),
+// the subtracted weight and the per-event outputs
+template <class S>
+__device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e, double B, double gR, double gS,
+                                          double gC, double gCm, double gSC, double gSCm, double xi, double y) {
+  uint8_t st = which == 1 ? 2 : 0;
+  double Bo = B;
+  if (a.mask) {
+    const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e], mC = a.mask[3 * a.ld + e];
+    if (!mB) Bo = 0.0;
+    if (!mR) gR = 0.0;
+    if (!mS) gS = 0.0;
+    if (!mC) { gC = 0.0; gCm = 0.0; }
+    if (!mS || !mC) { gSC = 0.0; gSCm = 0.0; }
+    if (!(mB && mR && mS && mC)) st |= 4;
+  }
+  double W;
+  if constexpr (S::J >= 0) {
+    W = (gR - gS - gC + gSC) / (xi * (1.0 - y));
+  } else {
+    W = (gR - gS - 0.5 * (1.0 + y) * (gC - gSC) - 0.5 * (1.0 - y) * (gCm - gSCm)) / (xi * (1.0 - y) * (1.0 + y));
+  }
+  if (!isfinite(W)) st |= 1;
+  a.W[e] = W;
+  if (a.xi_out) a.xi_out[e] = xi;
+  if (a.born_out) a.born_out[e] = Bo;
+  if (a.gR) a.gR[e] = gR;
+  if (a.gS) a.gS[e] = gS;
+  if (a.gC) a.gC[e] = gC;
+  if (a.gCm) a.gCm[e] = gCm;
+  if (a.gSC) a.gSC[e] = gSC;
+  if (a.gSCm) a.gSCm[e] = gSCm;
+  if (a.status) a.status[e] = st;
+}
+
+// helicity- and colour-summed |M|^2 of a Born (without its average factor)
+template <class BP, class T>
+__device__ __forceinline__ double born_sum(const double (&kb)[BP::NPART][4], double mt) {
+  typename BP::template Pre<T> s;
+  BP::prologue(kb, s, mt);
+  double acc = 0.0;
+  BP::helicity_sum(s, T(mt), [&](const cx<T> (&J)[BP::NFLOW]) { acc += (double)BP::colour_sum(J); });
+  return acc;
+}
+
+// Quark FKS parton from the initial state (e.g. u g -> t tbar u with the
+// final u): a soft quark is not singular, so g_S = g_SC = 0; at y -> +1 the
+// incoming quark of beam 1 turns into a gluon entering the Born (P_gq with its
+// spin correlation, C_F [x B + 4 (1-x)/x B_perp]); at y -> -1 the gluon of
+// beam 2 turns into an antiquark (P_qg = T_R [x^2 + (1-x)^2] B of the other
+// Born).  Real and Born are averaged over their own initial states, so the
+// unpolarised kernels apply without a ratio of spin x colour states.
+template <class S, class T>
+__device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64_t pos, int64_t e,
+                                              const double (&kb)[S::NB][4], const FksKin& K, double S_real) {
+  using BP = typename S::Born;
+  using BM = typename S::BornM;
+  const double xi = K.xi, y = K.y, g2 = a.g2, x = 1.0 - xi;
+  typename BP::template Pre<T> sp;
+  BP::prologue(kb, sp, a.mt);
+  double bp = 0.0;
+  BP::helicity_sum(sp, T(a.mt), [&](const cx<T> (&J)[BP::NFLOW]) { bp += (double)BP::colour_sum(J); });
+  const double Bplus = bp * a.scale_b;
+  const double Bperp = born_spin<BP, 0, T>(sp, K.ep, T(a.mt)) * a.scale_b;
+  const double Bminus = born_sum<BM, T>(kb, a.mt) * a.scale_bm;
+  const double Pp = FKS_CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
+  const double Pm = 0.5 * (x * x + (1.0 - x) * (1.0 - x)) * Bminus;
+  const double gR = xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
+  fks_store<S>(a, which, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, xi, y);
+}
+
 // 3. Born correlations, counterterms and subtracted weight for one bucket
 template <class S, class T>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which) {
@@ -296,6 +368,10 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
   load_born<S>(a, e, kb);
   fks_map<S>(kb, a.xit[e], a.y[e], a.phi[e], kr, K);
   const double S_real = fks_sector<S>(kr, K.sqs_r);
+  if constexpr (S::QUARK_I) {
+    fks_quark_isr<S, T>(a, which, pos, e, kb, K, S_real);
+    return;
+  } else {
 
   // Born: |M|^2 and the helicity-summed density of the flow vector
   typename BP::template Pre<T> s;
@@ -375,35 +451,8 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     gSC = 16.0 * g2 * Cp / K.sb * B;
     gSCm = 16.0 * g2 * Cm / K.sb * B;
   }
-  // Algorithm-2 masks: a failed cut zeroes its contribution after evaluation
-  uint8_t st = which == 1 ? 2 : 0;
-  double Bo = B;
-  if (a.mask) {
-    const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e], mC = a.mask[3 * a.ld + e];
-    if (!mB) Bo = 0.0;
-    if (!mR) gR = 0.0;
-    if (!mS) gS = 0.0;
-    if (!mC) { gC = 0.0; gCm = 0.0; }
-    if (!mS || !mC) { gSC = 0.0; gSCm = 0.0; }
-    if (!(mB && mR && mS && mC)) st |= 4;
+  fks_store<S>(a, which, e, B, gR, gS, gC, gCm, gSC, gSCm, xi, y);
   }
-  double W;
-  if constexpr (S::J >= 0) {
-    W = (gR - gS - gC + gSC) / (xi * (1.0 - y));
-  } else {
-    W = (gR - gS - 0.5 * (1.0 + y) * (gC - gSC) - 0.5 * (1.0 - y) * (gCm - gSCm)) / (xi * (1.0 - y) * (1.0 + y));
-  }
-  if (!isfinite(W)) st |= 1;
-  a.W[e] = W;
-  if (a.xi_out) a.xi_out[e] = xi;
-  if (a.born_out) a.born_out[e] = Bo;
-  if (a.gR) a.gR[e] = gR;
-  if (a.gS) a.gS[e] = gS;
-  if (a.gC) a.gC[e] = gC;
-  if (a.gCm) a.gCm[e] = gCm;
-  if (a.gSC) a.gSC[e] = gSC;
-  if (a.gSCm) a.gSCm[e] = gSCm;
-  if (a.status) a.status[e] = st;
 }
 
 // fixed-order FP64 sum (single block; deterministic for a given n)

@@ -24,6 +24,12 @@
 namespace nlo {
 
 template <class T> struct cx { T r, i; };
+
+// packed pairs of half-width floats (one event in each half of a register)
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 template <class T> struct w4 { cx<T> c[4]; };      // spinor, or vector with upper index
 template <class T> struct r4 { T v[4]; };          // real four-momentum
 
@@ -239,6 +245,11 @@ NLO_HD void vec_setup(const double* p, vec_data<double>& d) {
   const double s2 = 0.70710678118654752440;
   d.e1x = ct * cp * s2; d.e1y = ct * sp * s2; d.e1z = -st * s2;
   d.e2x = -sp * s2; d.e2y = cp * s2;
+}
+// multiply the wavefunction a leg's data builds by c
+template <class T> NLO_HD void scale_leg(ferm_data<T>& d, T c) { d.wp = d.wp * c; d.wm = d.wm * c; }
+template <class T> NLO_HD void scale_leg(vec_data<T>& d, T c) {
+  d.e1x = d.e1x * c; d.e1y = d.e1y * c; d.e1z = d.e1z * c; d.e2x = d.e2x * c; d.e2y = d.e2y * c;
 }
 template <class T> NLO_HD ferm_data<T> cast(const ferm_data<double>& d) {
   return {T(d.a), T(d.br), T(d.bi), T(d.wp), T(d.wm)};

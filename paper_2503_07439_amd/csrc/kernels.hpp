@@ -15,6 +15,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 #include "helas.hpp"
 #include "launch.hpp"
 
@@ -34,6 +35,8 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
 // vector-ALU kernel: any arithmetic type T
 // ---------------------------------------------------------------------------
 // event range of a launch: all of [0, n), or one bucket of a bucketed batch
+// (which = 0: [0, cnt[0]), 1: [n - cnt[1], n)); which = 2 (vector-ALU kernel
+// only) takes the events listed in list[0, cnt[0]) instead
 __device__ __forceinline__ void event_range(int64_t n, const unsigned* cnt, int which, int64_t& lo, int64_t& hi) {
   lo = 0;
   hi = n;
@@ -44,11 +47,18 @@ __device__ __forceinline__ void event_range(int64_t n, const unsigned* cnt, int 
 template <class P, class T>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
-                                                  const unsigned* cnt, int which) {
-  int64_t lo, hi;
-  event_range(n, cnt, which, lo, hi);
-  const int64_t e = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= hi) return;
+                                                  const unsigned* cnt, int which, const unsigned* list) {
+  int64_t e;
+  if (which == 2) {               // the events listed in list[0, cnt[0])
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)cnt[0]) return;
+    e = list[i];
+  } else {
+    int64_t lo, hi;
+    event_range(n, cnt, which, lo, hi);
+    e = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= hi) return;
+  }
   double p[P::NPART][4];
   load_event<P>(mom, ld, e, p);
   typename P::template Pre<T> s;
@@ -166,9 +176,124 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t l
   if (e < hi) out[e] = (rows[lane] + rows[64 + lane]) * scale;
 }
 
+// ---------------------------------------------------------------------------
+// half-width kernels: FP16 or BF16 amplitudes, two events per lane
+// ---------------------------------------------------------------------------
+// The amplitude arithmetic runs on packed pairs (one event in each half of a
+// 32-bit register), so one instruction serves two events.  Momenta and the top
+// mass are divided by sqrt(s_hat) in FP64 first, making every input
+// dimensionless and O(1): |M|^2 of N external particles has mass dimension
+// 2(4 - N), so |M|^2(p) = s_hat^(4 - N) |M|^2(p / sqrt(s_hat)), and that factor
+// is applied in FP64 at the end.  J is widened to FP32 and the colour
+// contraction and helicity sum accumulate in FP32 / FP64.
+
+// Largest propagator denominator handled in half width, in units of 1/s_hat.
+// Beyond it an event is close to a soft or collinear pole, where Feynman-gauge
+// diagrams cancel against each other by orders of magnitude: an 11-bit (FP16)
+// or 8-bit (BF16) significand leaves no correct digit there.  Such events are
+// listed and evaluated again in FP32 by a second launch.
+constexpr int HALF_MAX_DEN_LOG2 = 14;
+
+// loads one event, divides momenta and mass by sqrt(s_hat) and runs the FP64
+// prologue on them; then scales the external wavefunctions down by 2^-b with
+// b from the largest propagator denominator: intermediate currents grow
+// roughly like the largest 1/(p^2 - m^2) on their tree, and this keeps them
+// below the FP16 maximum while the rest stay well above its smallest normal
+// number.  Returns 1 / sqrt(s_hat); f receives the FP64 factor that restores
+// |M|^2, s_hat^(4 - N) 2^(2b); safe is false when the event needs FP32.
+template <class P>
+__device__ __forceinline__ double scaled_prologue(const double* __restrict__ mom, int64_t ld, int64_t e, double mt,
+                                                  typename P::template Pre<float>& s, double& f, bool& safe) {
+  double p[P::NPART][4];
+  load_event<P>(mom, ld, e, p);
+  double q[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) q[m] = p[0][m] + p[1][m];
+  const double r = 1.0 / sqrt(q[0] * q[0] - q[1] * q[1] - q[2] * q[2] - q[3] * q[3]);
+#pragma unroll
+  for (int k = 0; k < P::NPART; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) p[k][m] *= r;
+  P::prologue(p, s, mt * r);
+  float dmax = 1.0f;
+#pragma unroll
+  for (int k = 0; k < P::NDEN; ++k) dmax = fmaxf(dmax, fabsf(s.den[k]));
+  int ex;
+  (void)frexpf(dmax, &ex);            // dmax < 2^ex
+  safe = ex <= HALF_MAX_DEN_LOG2;     // also false for a non-finite denominator
+  const int b = safe ? ex + 4 : 0;    // 16x headroom below the largest denominator
+  P::scale_legs(s, b);
+  f = ldexp(1.0, 2 * b);
+#pragma unroll
+  for (int k = 4; k < P::NPART; ++k) f *= r * r;   // s_hat^(4 - N)
+  return r;
+}
+
+template <class P, class V2>
+__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_pair(int64_t n, int64_t ld, const double* __restrict__ mom,
+                                                  double* __restrict__ out, double scale, double mt,
+                                                  const unsigned* cnt, int which, unsigned* fb_list,
+                                                  unsigned* fb_cnt) {
+  using Pf = typename P::template Pre<float>;
+  using Pv = typename P::template Pre<V2>;
+  static_assert(sizeof(V2) == sizeof(float) && sizeof(Pf) == sizeof(Pv), "pre-computed data must be all scalars");
+  constexpr int NW = sizeof(Pf) / sizeof(float);
+  int64_t lo, hi;
+  event_range(n, cnt, which, lo, hi);
+  // a block covers 2 * blockDim events: lanes take e and e + blockDim (both coalesced)
+  const int64_t e0 = lo + (int64_t)blockIdx.x * 2 * blockDim.x + threadIdx.x;
+  if (e0 >= hi) return;
+  const int64_t e1 = e0 + blockDim.x;
+  const bool has1 = e1 < hi;
+  Pf a, b;
+  double f[2], r[2];
+  bool safe0, safe1;
+  r[0] = scaled_prologue<P>(mom, ld, e0, mt, a, f[0], safe0);
+  r[1] = scaled_prologue<P>(mom, ld, has1 ? e1 : e0, mt, b, f[1], safe1);
+  {
+    // append the events that need FP32 to the fallback list (wave-aggregated)
+    const bool l0 = !safe0, l1 = has1 && !safe1;
+    const unsigned long long m0 = __ballot(l0), m1 = __ballot(l1);
+    if (m0 | m1) {
+      const int lane = threadIdx.x & 63;
+      const unsigned long long lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+      unsigned base = 0;
+      if (lane == 0) base = atomicAdd(fb_cnt, (unsigned)(__popcll(m0) + __popcll(m1)));
+      base = __shfl(base, 0);
+      if (l0) fb_list[base + __popcll(m0 & lower)] = (unsigned)e0;
+      if (l1) fb_list[base + __popcll(m0) + __popcll(m1 & lower)] = (unsigned)e1;
+    }
+  }
+  // pack: one rounding from FP32 per element, both events in one instruction
+  Pv s;
+  const float* af = reinterpret_cast<const float*>(&a);
+  const float* bf = reinterpret_cast<const float*>(&b);
+  V2* sv = reinterpret_cast<V2*>(&s);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) sv[k] = __builtin_convertvector(f32x2{af[k], bf[k]}, V2);
+  const V2 mtv = __builtin_convertvector(f32x2{float(mt * r[0]), float(mt * r[1])}, V2);
+  double acc0 = 0.0, acc1 = 0.0;
+  P::helicity_sum(s, mtv, [&](const cx<V2> (&J)[P::NFLOW]) {
+    cx<float> J0[P::NFLOW], J1[P::NFLOW];
+#pragma unroll
+    for (int j = 0; j < P::NFLOW; ++j) {
+      J0[j] = cx<float>{(float)J[j].r[0], (float)J[j].i[0]};
+      J1[j] = cx<float>{(float)J[j].r[1], (float)J[j].i[1]};
+    }
+    acc0 += (double)P::colour_sum(J0);
+    acc1 += (double)P::colour_sum(J1);
+  });
+  out[e0] = acc0 * f[0] * scale;
+  if (has1) out[e1] = acc1 * f[1] * scale;
+}
+
 template <class P>
 constexpr size_t mfma_smem_bytes(int block) {
   return (size_t)(block / 64) * MfmaShape<P>::WAVE_FLOATS * sizeof(float);
+}
+
+static __global__ void k_fb_zero(unsigned* c) {
+  if (threadIdx.x == 0) *c = 0u;
 }
 
 // launch one variant; returns the HIP launch status
@@ -177,10 +302,19 @@ hipError_t launch_me2(const LaunchArgs& a) {
   const int64_t grid = (a.n + a.block - 1) / a.block;
   if constexpr (VARIANT == VAR_F64) {
     hipLaunchKernelGGL((k_me2_valu<P, double>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which);
+                       a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr);
   } else if constexpr (VARIANT == VAR_F32) {
     hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which);
+                       a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr);
+  } else if constexpr (VARIANT == VAR_F16 || VARIANT == VAR_BF16) {
+    // half-width pass over all events, then FP32 over the listed ones
+    using V2 = typename std::conditional<VARIANT == VAR_F16, f16x2, bf16x2>::type;
+    const int64_t grid2 = (a.n + 2 * a.block - 1) / (2 * a.block);
+    hipLaunchKernelGGL(k_fb_zero, dim3(1), dim3(64), 0, a.stream, a.fb_cnt);
+    hipLaunchKernelGGL((k_me2_pair<P, V2>), dim3((unsigned)grid2), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
+                       a.out, a.scale, a.mt, a.cnt, a.which, a.fb_list, a.fb_cnt);
+    hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
+                       a.out, a.scale, a.mt, (const unsigned*)a.fb_cnt, 2, (const unsigned*)a.fb_list);
   } else {
     hipLaunchKernelGGL((k_me2_mfma<P>), dim3((unsigned)grid), dim3(a.block), mfma_smem_bytes<P>(a.block), a.stream,
                        a.n, a.ld, a.mom, a.out, a.scale, a.mt, a.cnt, a.which);

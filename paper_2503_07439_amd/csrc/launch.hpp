@@ -9,8 +9,9 @@
 namespace nlo {
 
 // kernel variants of one process: FP64 vector ALU, FP32 vector ALU, FP32 with
-// the colour contraction on the matrix cores
-enum { VAR_F64 = 0, VAR_F32 = 1, VAR_MFMA = 2, NVAR = 3 };
+// the colour contraction on the matrix cores, FP16 and BF16 amplitudes on
+// packed pairs of events
+enum { VAR_F64 = 0, VAR_F32 = 1, VAR_MFMA = 2, VAR_F16 = 3, VAR_BF16 = 4, NVAR = 5 };
 
 struct LaunchArgs {
   int64_t n, ld;
@@ -24,6 +25,10 @@ struct LaunchArgs {
   // all of [0, n); 0: [0, cnt[0]); 1: [n - cnt[1], n)
   const unsigned* cnt = nullptr;
   int which = -1;
+  // FP16 / BF16 variants: workspace for the list of events evaluated again in
+  // FP32 (fb_list: n entries, fb_cnt: one counter)
+  unsigned* fb_list = nullptr;
+  unsigned* fb_cnt = nullptr;
 };
 
 struct ProcStatic {

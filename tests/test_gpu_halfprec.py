@@ -1,0 +1,168 @@
+"""FP16 and BF16 amplitude variants of |M|^2 (through the C ABI) against the
+FP64 oracle on the same seeded inputs.
+
+These are accuracy studies: the bars below are what a half-width amplitude
+calculation can promise, and the observed figures are printed.  Relative
+error per event against the oracle:
+  FP16 : every event finite, median <= 1e-2, summed |M|^2 <= 5e-2
+  BF16 : every event finite, median <= 5e-2, summed |M|^2 <= 1e-1
+The kernels scale each event's external wavefunctions by a power of two set
+by its largest propagator denominator (no FP16 overflow), and hand the events
+whose largest denominator exceeds 2^14/s_hat to an FP32 pass: next to a soft
+or collinear pole the Feynman-gauge diagrams cancel by orders of magnitude
+and a half-width significand keeps no correct digit.  Below that threshold
+the cancellations still amplify the unit roundoff (4.9e-4 for FP16, 3.9e-3 for
+BF16) on the events that dominate the sum: that sets the summed bars for
+g g -> t tbar g g, where one event can carry most of a sample's sum.
+Exact properties, bitwise:
+  - the result does not depend on the block size or on which events share a
+    packed register pair;
+  - momenta and top mass doubled give |M|^2 times 2^(2 (4 - N)) exactly (the
+    kernels divide by sqrt(s_hat) first, which is exact for powers of two).
+"""
+import numpy as np
+import pytest
+
+from nlo_inputs.workloads import M_TOP, events
+
+pytestmark = pytest.mark.gpu
+
+PROCS = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
+BARS = {"fp16": (1e-2, 5e-2, 1.0), "bf16": (5e-2, 1e-1, 1.0)}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    import paper_2503_07439_amd as nl
+    ctx = nl.Context()
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _rs(proc):
+    return 1000.0 if proc.startswith("ee") else (400.0, 2000.0)
+
+
+def _me2(ctx, proc, mom, prec, n=None):
+    import torch
+    m = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
+    out = torch.full((n if n is not None else mom.shape[2],), -1.0, dtype=torch.float64, device="cuda")
+    ctx.me2(proc, m, prec, out=out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("proc", PROCS)
+def test_halfprec_accuracy(gpu, orc, proc, prec):
+    n = 1001 if proc != "gg_ttgg" else 333       # odd: the last packed pair is half empty
+    mom, _ = events(proc, n, _rs(proc), stream=111)
+    ref = orc.me2(proc, mom)
+    got = _me2(gpu, proc, mom, prec)
+    fin = np.isfinite(got)
+    r = np.abs(got[fin] / ref[fin] - 1)
+    summed = abs(got[fin].sum() / ref[fin].sum() - 1)
+    print(proc, prec, "finite %.4f median %.2e p99.9 %.2e max %.2e summed %.2e" % (
+        fin.mean(), np.median(r), np.quantile(r, 0.999), r.max(), summed), flush=True)
+    med, tot, frac = BARS[prec]
+    assert fin.mean() >= frac
+    assert np.median(r) <= med
+    assert summed <= tot
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_halfprec_launch_shape_bitwise(gpu, prec):
+    proc = "gg_ttg"
+    mom, _ = events(proc, 777, _rs(proc), stream=112)
+    a = _me2(gpu, proc, mom, prec)
+    for block in (64, 128, 192):
+        gpu.set_kernel_config(proc, prec, block, 0)
+        try:
+            b = _me2(gpu, proc, mom, prec)
+        finally:
+            gpu.set_kernel_config(proc, prec, 256, 0)
+        assert np.array_equal(a, b, equal_nan=True)
+    # a single event, and the same event inside a larger batch, pair with
+    # different partners: same value
+    one = _me2(gpu, proc, mom[:, :, 5:6], prec)
+    assert one[0] == a[5] or (np.isnan(one[0]) and np.isnan(a[5]))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65, 129, 513])
+def test_halfprec_ragged_and_padded(gpu, orc, n):
+    import torch
+    proc = "gg_tt"
+    ld = n + 7
+    mom, _ = events(proc, ld, _rs(proc), stream=113)
+    ref = orc.me2(proc, mom[:, :, :n])
+    m = torch.from_numpy(mom).cuda()
+    out = torch.full((n + 5,), -1.0, dtype=torch.float64, device="cuda")
+    import paper_2503_07439_amd as nl
+    nl.nlo_me2(gpu.ctx, nl.proc_id(proc), n, ld, m.data_ptr(), out.data_ptr(), nl.NLO_FP16, gpu._stream())
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(o[n:] == -1.0)                       # nothing written past n
+    assert np.all(np.abs(o[:n] / ref - 1) < 5e-2)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("proc", ["gg_tt", "gg_ttg", "ee_uug"])
+def test_halfprec_dimension_scaling_exact(proc, prec):
+    """|M|^2(2p; 2 m_t) = 2^(2 (4 - N)) |M|^2(p; m_t), bit for bit."""
+    import paper_2503_07439_amd as nl
+    mom, _ = events(proc, 300, _rs(proc), stream=114)
+    npart = mom.shape[0]
+    c1 = nl.Context(m_top=173.0)
+    c2 = nl.Context(m_top=346.0)
+    try:
+        a = _me2(c1, proc, mom, prec)
+        b = _me2(c2, proc, 2.0 * mom, prec)
+    finally:
+        c1.close()
+        c2.close()
+    assert np.array_equal(b, a * 2.0 ** (2 * (4 - npart)), equal_nan=True)
+
+
+def test_halfprec_rejected_for_subtracted(gpu):
+    import torch
+    import paper_2503_07439_amd as nl
+    z = torch.zeros(8, dtype=torch.float64, device="cuda")
+    out = nl.nlo_fks_out()
+    out.W = z.data_ptr()
+    for prec in (nl.NLO_FP16, nl.NLO_BF16):
+        with pytest.raises(nl.NloError) as e:
+            nl.nlo_subtracted(gpu.ctx, nl.proc_id("gg_ttg"), 4, -1, 1, 1, z.data_ptr(), z.data_ptr(), z.data_ptr(),
+                              z.data_ptr(), 0, prec, out, 0)
+        assert e.value.status == 5
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_halfprec_fallback_matches_fp32(gpu, prec):
+    """Events next to a pole (largest propagator above 2^14/s_hat) come from
+    the FP32 pass: bit for bit the FP32 result.  The batch mixes them with
+    ordinary events, across pairs and blocks."""
+    import itertools
+    proc = "gg_ttgg"
+    mom, _ = events(proc, 20000, _rs(proc), stream=115)
+    q = mom.copy()
+    q[2:] *= -1
+    sh = (mom[0, 0] + mom[1, 0]) ** 2
+    big = np.zeros(mom.shape[2])
+    for r in (2, 3):
+        for S in itertools.combinations(range(6), r):
+            Q = q[list(S)].sum(axis=0)
+            m2 = M_TOP ** 2 if (2 in S) != (3 in S) else 0.0     # a top line, else a gluon
+            q2 = Q[0] ** 2 - Q[1] ** 2 - Q[2] ** 2 - Q[3] ** 2
+            big = np.maximum(big, np.abs(sh / (q2 - m2)))
+    # every event clearly beyond 2^14 plus the first 300 ordinary events
+    cut = 1.01 * 2.0 ** 14
+    pick = np.concatenate([np.where(big > cut)[0], np.arange(300)])
+    sub = np.ascontiguousarray(mom[:, :, pick])
+    far = big[pick] > cut
+    assert far.sum() >= 10
+    got = _me2(gpu, proc, sub, prec)
+    f32 = _me2(gpu, proc, sub, "fp32")
+    assert np.array_equal(got[far], f32[far])
+    assert np.all(np.isfinite(got))

@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--events", type=int, default=0, help="override the batch size")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched-mix leg")
+    ap.add_argument("--no-half", action="store_true", help="skip the FP16 leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -216,6 +217,20 @@ def main():
                                         "max": float(rel.max()), "summed": sum_rel}}
         print("fp64: %.3f ms per step" % ms64, file=sys.stderr, flush=True)
 
+    # FP16 amplitudes (FP32 pass for near-pole events) on the same batch, for the record
+    half = None
+    if not args.no_half and args.prec == "mixed" and fp64 is not None:
+        out16 = torch.empty_like(out)
+        ms16 = timed(ctx, proc, mom, out16, "fp16", max(3, args.steps // 4), 1)
+        rel = (out16 / out64 - 1).abs().cpu().numpy()
+        half = {"precision": "fp16", "ms_per_step": ms16, "events_per_s": n / (ms16 * 1e-3),
+                "speedup_vs_mixed": ms / ms16,
+                "rel_err_vs_gpu_fp64": {"median": float(np.median(rel)), "p99_9": float(np.quantile(rel, 0.999)),
+                                        "max": float(rel.max()),
+                                        "summed": abs(float(out16.sum()) / float(out64.sum()) - 1)}}
+        print("fp16: %.3f ms per step" % ms16, file=sys.stderr, flush=True)
+        del out16
+
     # the other colour-contraction unit, for the record
     other = None
     if args.prec == "mixed":
@@ -273,7 +288,7 @@ def main():
                    "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
                    "helicities": info.ngood_hel},
         "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
-        "batch_mix": mix,
+        "half_precision": half, "batch_mix": mix,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

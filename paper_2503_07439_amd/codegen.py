@@ -782,13 +782,15 @@ def helicity_order(p):
 # processes whose sub-currents one level above the deepest loop are also
 # evaluated lazily inside it (more flops, far fewer live registers)
 JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
+# stop the compiler from hoisting those lazily emitted sub-currents back out
+KEEP_LAZY_IN_LOOP = True
 
 
-def _node_call(n, mslot, dslot):
+def _node_call(n, mslot, dslot, den="s.den"):
     """C++ expression evaluating sub-current n from its children."""
     ch = ["v%d" % c.id for c in n.children]
     Q = "s.Q[%d]" % mslot[n.legs]
-    D = "s.den[%d]" % dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")]
+    D = "%s[%d]" % (den, dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")])
     if n.kind == "ffv_vec":
         return "ffv_vec(%s, %s, %s)" % (ch[0], ch[1], D)
     if n.kind in ("ffv_col", "ffv_row"):
@@ -882,6 +884,17 @@ def emit_nested(p, mslot, dslot, N, nin):
         roots = (("r0", "J0"), ("r1", "J1"))
         L.append(ind + "cx<T> J0[NFLOW], J1[NFLOW];")
         L.append(ind + "for (int f = 0; f < NFLOW; ++f) { J0[f] = czero<T>(); J1[f] = czero<T>(); }")
+    lazy_den = "s.den"
+    if jit_from < deep and KEEP_LAZY_IN_LOOP:
+        # Sub-currents emitted lazily one or more levels above their own would
+        # be hoisted back out of the deepest loop by loop-invariant code motion
+        # (they do not depend on its helicity), undoing the trade of flops for
+        # registers.  Their propagator factors are read through a copy that the
+        # compiler must treat as changing every iteration.
+        lazy_den = "dl"
+        L.append(ind + "T dl[NDEN];")
+        L.append(ind + "#pragma unroll")
+        L.append(ind + "for (int q = 0; q < NDEN; ++q) { dl[q] = s.den[q]; opaque(dl[q]); }")
     done = set()
 
     def need(n):
@@ -911,7 +924,7 @@ def emit_nested(p, mslot, dslot, N, nin):
         pending.remove(a)
         for c in a.children[:-1]:
             for n in need(c):
-                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot)))
+                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot, lazy_den)))
         ch = ["v%d" % c.id for c in a.children]
         for rv, J in roots:
             av = "a%d_%s" % (k, rv)
@@ -1175,8 +1188,9 @@ def generate(out_dir):
     for p in procs:
         p.enumerate()
         p.colour()
-        hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once", '#include "../helas.hpp"',
-                          "namespace nlo {", emit_process(p), "}  // namespace nlo", ""])
+        incs = ['#include "../helas.hpp"'] + (['#include "../opaque.hpp"'] if JIT_EXTRA_LEVELS.get(p.name, 0) else [])
+        hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once"] + incs +
+                         ["namespace nlo {", emit_process(p), "}  // namespace nlo", ""])
         _write_if_changed(os.path.join(out_dir, p.name + ".hpp"), hdr)
         for v, var in enumerate(VARIANTS):
             tu = "\n".join(["// GENERATED by codegen.py -- do not edit.", '#include "../kernels.hpp"',

@@ -113,6 +113,7 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
     a.fb_list = static_cast<unsigned*>(ws);
     const uintptr_t c = reinterpret_cast<uintptr_t>(a.fb_list + n);
     a.fb_cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
+    a.fb_launch = ME2_LAUNCH[pid][VAR_F32];
   }
   hipError_t err = ME2_LAUNCH[pid][var](a);
   if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_me2: launch failed: %s", hipGetErrorString(err));

@@ -305,7 +305,7 @@ hipError_t launch_me2(const LaunchArgs& a) {
                        a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr);
   } else if constexpr (VARIANT == VAR_F32) {
     hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr);
+                       a.out, a.scale, a.mt, a.cnt, a.which, a.list);
   } else if constexpr (VARIANT == VAR_F16 || VARIANT == VAR_BF16) {
     // half-width pass over all events, then FP32 over the listed ones
     using V2 = typename std::conditional<VARIANT == VAR_F16, f16x2, bf16x2>::type;
@@ -313,8 +313,16 @@ hipError_t launch_me2(const LaunchArgs& a) {
     hipLaunchKernelGGL(k_fb_zero, dim3(1), dim3(64), 0, a.stream, a.fb_cnt);
     hipLaunchKernelGGL((k_me2_pair<P, V2>), dim3((unsigned)grid2), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
                        a.out, a.scale, a.mt, a.cnt, a.which, a.fb_list, a.fb_cnt);
-    hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, (const unsigned*)a.fb_cnt, 2, (const unsigned*)a.fb_list);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    // the FP32 kernel lives in the process's FP32 unit (one instantiation per
+    // kernel across the library)
+    if (!a.fb_launch) return hipErrorInvalidValue;
+    LaunchArgs f = a;
+    f.cnt = a.fb_cnt;
+    f.which = 2;
+    f.list = a.fb_list;
+    return a.fb_launch(f);
   } else {
     hipLaunchKernelGGL((k_me2_mfma<P>), dim3((unsigned)grid), dim3(a.block), mfma_smem_bytes<P>(a.block), a.stream,
                        a.n, a.ld, a.mom, a.out, a.scale, a.mt, a.cnt, a.which);

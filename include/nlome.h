@@ -184,9 +184,10 @@ typedef struct {
  *   prec:      NLO_FP64, NLO_FP32 (amplitudes in float, kinematics and
  *              assembly in double) or NLO_MIXED (float unless
  *              min(xi, 1-|y|) < threshold, see nlo_set_fks_threshold).
- * Uses a workspace owned by the context (grown on the first call with a
- * larger n after synchronising the stream); calls that overlap on different
- * streams with the same context race. */
+ * Uses a workspace owned by the context, grown on the first call with a
+ * larger n after synchronising the device (so do such a first call outside
+ * stream capture); calls that overlap on different streams with the same
+ * context race on it. */
 nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
                           const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
                           const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream);

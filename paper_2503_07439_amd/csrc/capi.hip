@@ -120,12 +120,14 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
   return NLO_OK;
 }
 
-// grow the context's workspace to at least need bytes (synchronising the
-// stream before freeing the old one); caller holds ctx->mu
+// grow the context's workspace to at least need bytes; the old one is freed
+// only after the whole device is idle (work already queued on any stream may
+// still use it); caller holds ctx->mu
 nlo_status ensure_ws(nlo_ctx* ctx, size_t need, hipStream_t s, const char* fn) {
+  (void)s;
   if (need <= ctx->ws_bytes) return NLO_OK;
   if (ctx->ws) {
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(NLO_EDEVICE, "%s: stream sync failed", fn);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(NLO_EDEVICE, "%s: device sync failed", fn);
     (void)hipFree(ctx->ws);
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;

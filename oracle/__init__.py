@@ -195,3 +195,21 @@ def born_spin_correlated(proc, mom, leg, eperp):
     out = np.empty(n)
     assert f(pid(proc), n, _dp(mom), leg, _dp(ep), _dp(out)) == 0
     return out
+
+
+def rambo(sqrt_s, masses, u):
+    """RAMBO from the uniforms u [n, nfin, 4] (cos theta, phi, two for the
+    energy per particle) at per-event sqrt_s [n].  Returns (p [n, nfin, 4]
+    with components E, px, py, pz in the final-state rest frame, weight [n])."""
+    L = lib()
+    f = L.orc_rambo
+    f.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    sqrt_s = np.ascontiguousarray(sqrt_s, dtype=np.float64)
+    masses = np.ascontiguousarray(masses, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    n, nfin = u.shape[0], u.shape[1]
+    p = np.empty((n, nfin, 4))
+    w = np.empty(n)
+    assert f(nfin, _dp(masses), n, _dp(sqrt_s), _dp(u), _dp(p), _dp(w)) == 0
+    return p, w

@@ -19,6 +19,9 @@
 //                T^a, every external colour assignment summed explicitly),
 //                i.e. the plain definition; slow, used to pin me2 on a few
 //                events.
+// Also: the FKS-subtracted real emission (fks, with colour-linked and
+// spin-correlated Borns) and the RAMBO phase-space generator (rambo), each
+// written out step by step further below.
 //
 // Conventions: metric (+,-,-,-); chiral Dirac representation; Feynman gauge;
 // Peskin-Schroeder vertex rules: quark-gluon  i g gamma^mu T^a,
@@ -1583,3 +1586,93 @@ int orc_born_spin_correlated(int proc, int64_t n, const double* mom, int leg, co
   return 0;
 }
 }
+
+// ============================================================================
+// RAMBO phase space (ORACLE) -- Kleiss, Stirling and Ellis's democratic
+// generator: n massless momenta drawn isotropically with energy density
+// q0 exp(-q0), brought to total momentum (sqrt_s, 0) by one conformal
+// (boost + scale) transformation; massive final states by a common rescaling
+// of the three-momenta solved for energy conservation (Newton).  The
+// uniforms are inputs (four per particle: cos theta, phi, and two for the
+// energy), so this checks the arithmetic alone.  After the conformal step a
+// projection removes the rounding it leaves (residual three-momentum, E = |p|),
+// as the input recipe of the batches does.
+// ============================================================================
+extern "C" {
+
+int orc_rambo(int nfin, const double* masses, int64_t n, const double* sqrt_s, const double* u, double* p_out,
+              double* w_out) {
+  if (nfin < 2 || nfin > 8) return 1;
+  double vol1 = std::pow(2.0 * M_PI, 4 - 3 * nfin) * std::pow(M_PI / 2.0, nfin - 1);
+  for (int k = 2; k <= nfin - 1; ++k) vol1 /= k;     // 1/(n-1)!
+  for (int k = 2; k <= nfin - 2; ++k) vol1 /= k;     // 1/(n-2)!
+  bool massive = false;
+  double msum = 0.0;
+  for (int i = 0; i < nfin; ++i) { massive = massive || masses[i] > 0.0; msum += masses[i]; }
+  for (int64_t e = 0; e < n; ++e) {
+    const double rs = sqrt_s[e];
+    const double* ue = u + e * nfin * 4;
+    double q[8][4], Q[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nfin; ++i) {
+      const double c = 2.0 * ue[4 * i] - 1.0, ph = 2.0 * M_PI * ue[4 * i + 1];
+      const double e0 = -std::log(ue[4 * i + 2] * ue[4 * i + 3]);
+      const double s = std::sqrt(std::max(0.0, 1.0 - c * c));
+      q[i][0] = e0; q[i][1] = e0 * s * std::cos(ph); q[i][2] = e0 * s * std::sin(ph); q[i][3] = e0 * c;
+      for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
+    }
+    // conformal transformation: boost by -Q/M, scale by sqrt_s/M
+    const double M = std::sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+    const double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
+    const double g = Q[0] / M, a = 1.0 / (1.0 + g), x = rs / M;
+    double p[8][4];
+    for (int i = 0; i < nfin; ++i) {
+      const double bq = b[0] * q[i][1] + b[1] * q[i][2] + b[2] * q[i][3];
+      p[i][0] = x * (g * q[i][0] + bq);
+      for (int m = 0; m < 3; ++m) p[i][1 + m] = x * (q[i][1 + m] + b[m] * q[i][0] + a * bq * b[m]);
+    }
+    // projection of the rounding left by the transformation
+    double r3[3] = {0, 0, 0};
+    for (int i = 0; i < nfin; ++i) for (int m = 0; m < 3; ++m) r3[m] += p[i][1 + m];
+    double pabs[8], tot = 0.0;
+    for (int i = 0; i < nfin; ++i) {
+      for (int m = 0; m < 3; ++m) p[i][1 + m] -= r3[m] / nfin;
+      pabs[i] = std::sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+      tot += pabs[i];
+    }
+    const double sc = rs / tot;
+    for (int i = 0; i < nfin; ++i) {
+      for (int m = 0; m < 3; ++m) p[i][1 + m] *= sc;
+      p[i][0] = pabs[i] * sc;
+    }
+    double w = vol1 * std::pow(rs, 2 * (nfin - 2));
+    if (massive) {
+      // common factor xi on the three-momenta: sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt_s
+      double xi = std::sqrt(std::max(1e-30, 1.0 - (msum / rs) * (msum / rs)));
+      for (int it = 0; it < 50; ++it) {
+        double f = -rs, fp = 0.0;
+        for (int i = 0; i < nfin; ++i) {
+          const double ek = std::sqrt(masses[i] * masses[i] + xi * xi * p[i][0] * p[i][0]);
+          f += ek;
+          fp += xi * p[i][0] * p[i][0] / ek;
+        }
+        xi -= f / fp;
+        if (std::fabs(f) <= 1e-14 * rs) break;
+      }
+      double ksum = 0.0, kprod = 1.0, k2e = 0.0;
+      for (int i = 0; i < nfin; ++i) {
+        const double E = p[i][0];
+        const double k0 = std::sqrt(masses[i] * masses[i] + xi * xi * E * E);
+        for (int m = 0; m < 3; ++m) p[i][1 + m] *= xi;
+        p[i][0] = k0;
+        const double ka = std::sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+        ksum += ka; kprod *= ka / k0; k2e += ka * ka / k0;
+      }
+      w *= std::pow(ksum / rs, 2 * nfin - 3) * kprod * rs / k2e;
+    }
+    for (int i = 0; i < nfin; ++i) for (int m = 0; m < 4; ++m) p_out[(e * nfin + i) * 4 + m] = p[i][m];
+    w_out[e] = w;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--events", type=int, default=0, help="override the batch size")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched-mix leg")
     ap.add_argument("--no-half", action="store_true", help="skip the FP16 leg")
+    ap.add_argument("--no-gen", action="store_true", help="skip the device phase-space generation leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -217,6 +218,43 @@ def main():
                                         "max": float(rel.max()), "summed": sum_rel}}
         print("fp64: %.3f ms per step" % ms64, file=sys.stderr, flush=True)
 
+    # the same batch generated on the device (Philox + RAMBO), alone and
+    # followed by the |M|^2 launch: the event loop without host inputs
+    gen = None
+    if not args.no_gen and args.prec == "mixed":
+        gmom = torch.empty_like(mom)
+        gw = torch.empty(n, dtype=torch.float64, device="cuda")
+        lo, hi = rs if isinstance(rs, tuple) else (rs, rs)
+        pid = nl.proc_id(proc)
+
+        def generate():
+            nl.nlo_phase_space(ctx.ctx, pid, n, n, 7439, stream, 0, float(lo), float(hi), gmom.data_ptr(),
+                               gw.data_ptr(), torch.cuda.current_stream().cuda_stream)
+
+        def both():
+            generate()
+            ctx.me2(proc, gmom, "mixed", out=out)
+
+        gms = {}
+        for name, fn in (("generate", generate), ("generate_and_me2", both)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(max(3, args.steps // 4)):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            gms[name] = t0.elapsed_time(t1) / max(3, args.steps // 4)
+        same = bool(torch.allclose(gmom, mom, rtol=0, atol=1e-12 * float(hi)))
+        gen = {"ms_generate": gms["generate"], "ms_generate_and_me2": gms["generate_and_me2"],
+               "events_per_s_generate_and_me2": n / (gms["generate_and_me2"] * 1e-3),
+               "same_points_as_host_batch": same}
+        print("device generation: %.3f ms, with |M|^2 %.3f ms" % (gms["generate"], gms["generate_and_me2"]),
+              file=sys.stderr, flush=True)
+        del gmom, gw
+
     # FP16 amplitudes (FP32 pass for near-pole events) on the same batch, for the record
     half = None
     if not args.no_half and args.prec == "mixed" and fp64 is not None:
@@ -288,7 +326,7 @@ def main():
                    "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
                    "helicities": info.ngood_hel},
         "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
-        "half_precision": half, "batch_mix": mix,
+        "half_precision": half, "device_generation": gen, "batch_mix": mix,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

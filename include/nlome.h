@@ -228,6 +228,37 @@ nlo_status nlo_batch_plan(nlo_ctx* ctx, const nlo_work_item* items, int nitems, 
 nlo_status nlo_batch_run(nlo_plan* plan, void* hip_stream);
 nlo_status nlo_plan_destroy(nlo_plan* plan);
 
+/* ---- on-device phase-space generation: the point-sampling step that opens
+ * each iteration of the paper's event loop (Algorithm 2), batched ----
+ * Every draw is a pure function of (seed, stream, event index, slot): the
+ * counter-based Philox4x32-10 generator with key (seed, stream) and counter
+ * (event low word, event high word, slot, 0); its four words give two doubles
+ * (53 random bits each, plus half a unit of the last place, so in (0, 1)).
+ * Event indices are first, first + 1, ...: any sub-range of a batch can be
+ * regenerated on its own, whatever the launch shape. */
+
+/* out: device float64 [n][2], the two uniforms of (event first + i, slot). */
+nlo_status nlo_uniforms(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first, uint32_t slot,
+                        double* out, void* hip_stream);
+
+/* RAMBO phase-space points for process proc_id (2 -> 2, 3 or 4), in the
+ * partonic centre-of-mass frame with the beams along +z and -z:
+ *   sqrt(s_hat) = sqrt_s_lo + (sqrt_s_hi - sqrt_s_lo) u (slot 64; equal
+ *   bounds give a fixed energy); final-state particle k from slots 2k, 2k+1;
+ *   top quarks at the context's m_top, everything else massless.
+ * mom: device, layout above ([npart][4][ld]); weight: device [n] RAMBO weight
+ * (the phase-space volume factor, (2 pi)^(4-3n) included) or NULL.
+ * Requires sqrt_s_lo > the sum of the final-state masses. */
+nlo_status nlo_phase_space(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uint32_t seed, uint32_t stream,
+                           uint64_t first, double sqrt_s_lo, double sqrt_s_hi, double* mom, double* weight,
+                           void* hip_stream);
+
+/* FKS radiation variables of nlo_subtracted: xi_tilde and 1 - |y|
+ * log-uniform in [1e-6, 1] (slot 65), phi uniform in [0, 2 pi) and, if
+ * initial_state, a random sign of y (slot 66).  Outputs: device [n] each. */
+nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
+                             int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

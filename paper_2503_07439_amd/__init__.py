@@ -9,7 +9,8 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_abi_version, nlo_create, nlo_destroy, nlo_last_error, nlo_num_processes,
                    nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
                    nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
-                   nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune)
+                   nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
+                   nlo_uniforms, nlo_phase_space, nlo_fks_variables)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -105,3 +106,34 @@ class Context:
 
     def set_kernel_config(self, proc, prec, block, colour_mode=0):
         nlo_set_kernel_config(self.ctx, proc_id(proc), PREC[prec], block, colour_mode)
+
+    SEED = 7439
+
+    def uniforms(self, n, stream, slot, first=0, seed=SEED):
+        """float64 CUDA [n, 2]: the generator's two uniforms per event."""
+        import torch
+        out = torch.empty((n, 2), dtype=torch.float64, device="cuda:%d" % self.device)
+        nlo_uniforms(self.ctx, n, seed, stream, first, slot, out.data_ptr(), self._stream())
+        return out
+
+    def phase_space(self, proc, n, sqrt_s, stream, first=0, seed=SEED):
+        """RAMBO points on the device: (mom [npart, 4, n], weight [n]) as float64
+        CUDA tensors; sqrt_s is a number or a (lo, hi) range."""
+        import torch
+        lo, hi = (sqrt_s, sqrt_s) if not isinstance(sqrt_s, (tuple, list)) else sqrt_s
+        npart = self.info(proc).npart
+        mom = torch.empty((npart, 4, n), dtype=torch.float64, device="cuda:%d" % self.device)
+        w = torch.empty(n, dtype=torch.float64, device=mom.device)
+        nlo_phase_space(self.ctx, proc_id(proc), n, n, seed, stream, first, float(lo), float(hi), mom.data_ptr(),
+                        w.data_ptr(), self._stream())
+        return mom, w
+
+    def fks_variables(self, n, stream, initial_state=False, first=0, seed=SEED):
+        """(xi_tilde, y, phi), float64 CUDA [n] each."""
+        import torch
+        dev = "cuda:%d" % self.device
+        xt, y, phi = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+        nlo_fks_variables(self.ctx, n, seed, stream, first, 1 if initial_state else 0, xt.data_ptr(), y.data_ptr(),
+                          phi.data_ptr(), self._stream())
+        return xt, y, phi
+

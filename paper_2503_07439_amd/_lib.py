@@ -77,6 +77,12 @@ SIGNATURES = {
     "nlo_autotune": ([_VP, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, ctypes.POINTER(nlo_kernel_config),
                       ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "nlo_plan_destroy": ([_VP], ctypes.c_int),
+    "nlo_uniforms": ([_VP, _I64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP],
+                     ctypes.c_int),
+    "nlo_phase_space": ([_VP, ctypes.c_int, _I64, _I64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                         ctypes.c_double, ctypes.c_double, _VP, _VP, _VP], ctypes.c_int),
+    "nlo_fks_variables": ([_VP, _I64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, _VP, _VP, _VP,
+                           _VP], ctypes.c_int),
 }
 
 
@@ -176,3 +182,17 @@ def nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr):
     check(lib().nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr, ctypes.byref(best),
                              ctypes.byref(ns)))
     return (best.block, best.colour_mode), ns.value
+
+
+def nlo_uniforms(ctx, n, seed, stream, first, slot, out_ptr, stream_ptr):
+    return check(lib().nlo_uniforms(ctx, n, seed, stream, first, slot, out_ptr, stream_ptr))
+
+
+def nlo_phase_space(ctx, proc_id, n, ld, seed, stream, first, sqrt_s_lo, sqrt_s_hi, mom_ptr, weight_ptr, stream_ptr):
+    return check(lib().nlo_phase_space(ctx, proc_id, n, ld, seed, stream, first, sqrt_s_lo, sqrt_s_hi, mom_ptr,
+                                       weight_ptr, stream_ptr))
+
+
+def nlo_fks_variables(ctx, n, seed, stream, first, initial_state, xit_ptr, y_ptr, phi_ptr, stream_ptr):
+    return check(lib().nlo_fks_variables(ctx, n, seed, stream, first, initial_state, xit_ptr, y_ptr, phi_ptr,
+                                         stream_ptr))

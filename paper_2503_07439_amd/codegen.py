@@ -1205,9 +1205,10 @@ def generate(out_dir):
     index.append("static const ProcStatic PROC_STATIC[NPROC] = {")
     for p in procs:
         gs, ee = p.coupling_powers()
-        index.append('  {"%s", %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %.17g, %.17g},' % (
+        tops = sum(1 << k for k, x in enumerate(list(p.incoming) + list(p.outgoing)) if x in ("t", "t~"))
+        index.append('  {"%s", %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %.17g, %.17g, %du},' % (
             p.name, p.npart, len(p.incoming), len(p.flows), 1 << p.npart, len(p.good_helicities()), p.ndiagrams,
-            len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee, p.avg, p.ident))
+            len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee, p.avg, p.ident, tops))
     index.append("};")
     index.append("static const me2_launcher ME2_LAUNCH[NPROC][NVAR] = {")
     for p in procs:

@@ -15,6 +15,7 @@
 
 #include "generated/index.hpp"
 #include "launch.hpp"
+#include "phase_space.hpp"
 #include "nlome.h"
 
 using namespace nlo;
@@ -557,6 +558,74 @@ nlo_status nlo_batch_run(nlo_plan* plan, void* hip_stream) {
   if (st) return st;
   hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
   if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_batch_run: graph launch failed: %s", hipGetErrorString(e));
+  return NLO_OK;
+}
+
+nlo_status nlo_uniforms(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first, uint32_t slot,
+                        double* out, void* hip_stream) {
+  if (!ctx) return fail(NLO_EINVAL, "nlo_uniforms: ctx is NULL");
+  if (n < 0) return fail(NLO_EINVAL, "nlo_uniforms: n = %lld < 0", (long long)n);
+  if (n == 0) return NLO_OK;
+  if (!out) return fail(NLO_EINVAL, "nlo_uniforms: NULL device pointer");
+  if (n > 0x7fffffffLL * 256) return fail(NLO_EINVAL, "nlo_uniforms: n too large");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  nlo_status st = use_device(ctx, "nlo_uniforms");
+  if (st) return st;
+  hipError_t e = launch_uniforms(n, seed, stream, first, slot, out, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_uniforms: launch failed: %s", hipGetErrorString(e));
+  return NLO_OK;
+}
+
+nlo_status nlo_phase_space(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uint32_t seed, uint32_t stream,
+                           uint64_t first, double sqrt_s_lo, double sqrt_s_hi, double* mom, double* weight,
+                           void* hip_stream) {
+  nlo_status st = check_ctx(ctx, proc_id, "nlo_phase_space");
+  if (st) return st;
+  const ProcStatic& P = PROC_STATIC[proc_id];
+  if (n < 0 || ld < n) return fail(NLO_EINVAL, "nlo_phase_space: need 0 <= n <= ld");
+  if (n == 0) return NLO_OK;
+  if (!mom) return fail(NLO_EINVAL, "nlo_phase_space: NULL device pointer");
+  if (n > 0x7fffffffLL * 256) return fail(NLO_EINVAL, "nlo_phase_space: n too large");
+  if (P.nin != 2 || P.npart - 2 < 2 || P.npart - 2 > 4)
+    return fail(NLO_EUNSUPPORTED, "nlo_phase_space: process %s has no 2 -> 2..4 generator", P.name);
+  double msum = 0.0;
+  PsArgs a{};
+  a.n = n;
+  a.ld = ld;
+  a.seed = seed;
+  a.stream = stream;
+  a.first = first;
+  a.rs_lo = sqrt_s_lo;
+  a.rs_hi = sqrt_s_hi;
+  for (int k = 2; k < P.npart; ++k) {
+    a.mass[k - 2] = (P.top_legs >> k) & 1u ? ctx->params.m_top : 0.0;
+    msum += a.mass[k - 2];
+  }
+  if (!(sqrt_s_lo > msum) || !(sqrt_s_hi >= sqrt_s_lo) || !std::isfinite(sqrt_s_hi))
+    return fail(NLO_EINVAL, "nlo_phase_space: need %g < sqrt_s_lo <= sqrt_s_hi < inf", msum);
+  a.mom = mom;
+  a.weight = weight;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, "nlo_phase_space");
+  if (st) return st;
+  hipError_t e = launch_rambo(P.npart - 2, a, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_phase_space: launch failed: %s", hipGetErrorString(e));
+  return NLO_OK;
+}
+
+nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
+                             int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream) {
+  if (!ctx) return fail(NLO_EINVAL, "nlo_fks_variables: ctx is NULL");
+  if (n < 0) return fail(NLO_EINVAL, "nlo_fks_variables: n = %lld < 0", (long long)n);
+  if (n == 0) return NLO_OK;
+  if (!xi_tilde || !y || !phi) return fail(NLO_EINVAL, "nlo_fks_variables: NULL device pointer");
+  if (n > 0x7fffffffLL * 256) return fail(NLO_EINVAL, "nlo_fks_variables: n too large");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  nlo_status st = use_device(ctx, "nlo_fks_variables");
+  if (st) return st;
+  hipError_t e = launch_fks_variables(n, seed, stream, first, initial_state ? 1 : 0, xi_tilde, y, phi,
+                                      (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_fks_variables: launch failed: %s", hipGetErrorString(e));
   return NLO_OK;
 }
 

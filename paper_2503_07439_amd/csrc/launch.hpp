@@ -39,6 +39,7 @@ struct ProcStatic {
   const char* name;
   int npart, nin, nflow, nhel, ngood, ndiag, nterm, ncur, gs_pow, e_pow;
   double avg, ident;
+  unsigned top_legs;   // bit k set: leg k is a top quark (mass m_t), else massless
 };
 
 typedef hipError_t (*me2_launcher)(const LaunchArgs&);

@@ -1,0 +1,217 @@
+// On-device phase-space generation: the random numbers, RAMBO points and FKS
+// radiation variables of a batch, produced where the matrix elements are
+// evaluated (the paper's event loop draws phase-space points per event;
+// keeping that step on the device removes the host round trip).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), a
+// counter-based generator, so every draw is a pure function of
+// (seed, stream, event index, slot) whatever the launch shape.  Key =
+// (seed, stream), counter = (event low word, event high word, slot, 0); the
+// four output words give two doubles of 53 random bits each, offset by half a
+// unit of the last place so that log(u) is finite.  Slot layout of an event
+// (the batch recipe): 2k and 2k+1 for final-state particle k, 64 for
+// sqrt(s_hat), 65 and 66 for the FKS variables.
+//
+// Phase space: RAMBO (Kleiss, Stirling and Ellis) in the partonic
+// centre-of-mass frame, beams along +z and -z, with the projection of the
+// conformal transformation's rounding and the Newton rescaling for massive
+// final states.  One event per lane, all in FP64.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include "phase_space.hpp"
+
+namespace nlo {
+
+struct philox_out { uint32_t w[4]; };
+
+__device__ __forceinline__ philox_out philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                     uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;   // round multipliers
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;   // Weyl key increments
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return {{c0, c1, c2, c3}};
+}
+
+// two uniforms in (0, 1) for (event, slot)
+__device__ __forceinline__ void uniform2(uint32_t seed, uint32_t stream, uint64_t e, uint32_t slot, double& a,
+                                         double& b) {
+  const philox_out o = philox4x32_10((uint32_t)e, (uint32_t)(e >> 32), slot, 0u, seed, stream);
+  const uint64_t ia = ((uint64_t)(o.w[0] >> 5) << 26) | (o.w[1] >> 6);
+  const uint64_t ib = ((uint64_t)(o.w[2] >> 5) << 26) | (o.w[3] >> 6);
+  const double s = 1.0 / 9007199254740992.0;   // 2^-53
+  a = ((double)ia + 0.5) * s;
+  b = ((double)ib + 0.5) * s;
+}
+
+__global__ __launch_bounds__(256) void k_uniforms(int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
+                                                  uint32_t slot, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a, b;
+  uniform2(seed, stream, first + (uint64_t)i, slot, a, b);
+  out[2 * i] = a;
+  out[2 * i + 1] = b;
+}
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const uint64_t e = a.first + (uint64_t)i;
+  double u0, u1, u2, u3;
+  uniform2(a.seed, a.stream, e, 64, u0, u1);
+  const double rs = a.rs_lo + (a.rs_hi - a.rs_lo) * u0;
+  // isotropic massless momenta, energy density q0 exp(-q0)
+  double q[NF][4], Q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    uniform2(a.seed, a.stream, e, 2 * k, u0, u1);
+    uniform2(a.seed, a.stream, e, 2 * k + 1, u2, u3);
+    const double c = 2.0 * u0 - 1.0, ph = 2.0 * M_PI * u1;
+    const double en = -log(u2 * u3);
+    const double st = sqrt(fmax(0.0, 1.0 - c * c));
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    q[k][0] = en; q[k][1] = en * st * cp; q[k][2] = en * st * sp; q[k][3] = en * c;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Q[m] += q[k][m];
+  }
+  // boost by -Q/M and scale by sqrt_s/M: total momentum (sqrt_s, 0)
+  const double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+  const double bx = -Q[1] / M, by = -Q[2] / M, bz = -Q[3] / M;
+  const double g = Q[0] / M, al = 1.0 / (1.0 + g), x = rs / M;
+  double p[NF][4];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const double bq = bx * q[k][1] + by * q[k][2] + bz * q[k][3];
+    p[k][0] = x * (g * q[k][0] + bq);
+    p[k][1] = x * (q[k][1] + bx * q[k][0] + al * bq * bx);
+    p[k][2] = x * (q[k][2] + by * q[k][0] + al * bq * by);
+    p[k][3] = x * (q[k][3] + bz * q[k][0] + al * bq * bz);
+  }
+  // remove the rounding the transformation leaves: zero total three-momentum,
+  // massless shells, exact total energy
+  double r3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) r3[m] += p[k][1 + m];
+  double pa[NF], tot = 0.0;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) p[k][1 + m] -= r3[m] / NF;
+    pa[k] = sqrt(p[k][1] * p[k][1] + p[k][2] * p[k][2] + p[k][3] * p[k][3]);
+    tot += pa[k];
+  }
+  const double sc = rs / tot;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) p[k][1 + m] *= sc;
+    p[k][0] = pa[k] * sc;
+  }
+  // massless volume (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!)
+  double w = pow(2.0 * M_PI, 4 - 3 * NF) * pow(0.5 * M_PI, NF - 1);
+#pragma unroll
+  for (int k = 2; k <= NF - 1; ++k) w /= k;
+#pragma unroll
+  for (int k = 2; k <= NF - 2; ++k) w /= k;
+  w *= pow(rs, 2 * (NF - 2));
+  double msum = 0.0;
+  bool massive = false;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) { msum += a.mass[k]; massive = massive || a.mass[k] > 0.0; }
+  if (massive) {
+    // common factor xi on the three-momenta with sum_k sqrt(m_k^2 + xi^2 E_k^2) = sqrt_s
+    double xi = sqrt(fmax(1e-30, 1.0 - (msum / rs) * (msum / rs)));
+    for (int it = 0; it < 50; ++it) {
+      double f = -rs, fp = 0.0;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        const double ek = sqrt(a.mass[k] * a.mass[k] + xi * xi * p[k][0] * p[k][0]);
+        f += ek;
+        fp += xi * p[k][0] * p[k][0] / ek;
+      }
+      xi -= f / fp;
+      if (fabs(f) <= 1e-14 * rs) break;
+    }
+    double ksum = 0.0, kprod = 1.0, k2e = 0.0;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const double k0 = sqrt(a.mass[k] * a.mass[k] + xi * xi * p[k][0] * p[k][0]);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) p[k][1 + m] *= xi;
+      p[k][0] = k0;
+      const double ka = sqrt(p[k][1] * p[k][1] + p[k][2] * p[k][2] + p[k][3] * p[k][3]);
+      ksum += ka;
+      kprod *= ka / k0;
+      k2e += ka * ka / k0;
+    }
+    w *= pow(ksum / rs, 2 * NF - 3) * kprod * rs / k2e;
+  }
+  // store: beams, then the final state
+  const double h = 0.5 * rs;
+  const double beams[2][4] = {{h, 0.0, 0.0, h}, {h, 0.0, 0.0, -h}};
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a.mom[(b * 4 + m) * a.ld + i] = beams[b][m];
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a.mom[((k + 2) * 4 + m) * a.ld + i] = p[k][m];
+  if (a.weight) a.weight[i] = w;
+}
+
+// FKS radiation variables: xi_tilde and 1 - |y| log-uniform in [1e-6, 1],
+// phi uniform in [0, 2 pi); a random sign of y for initial-state sectors
+__global__ __launch_bounds__(256) void k_fks_variables(int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
+                                                       int initial_state, double* __restrict__ xit,
+                                                       double* __restrict__ y, double* __restrict__ phi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t e = first + (uint64_t)i;
+  double a0, a1, b0, b1;
+  uniform2(seed, stream, e, 65, a0, a1);
+  uniform2(seed, stream, e, 66, b0, b1);
+  xit[i] = pow(10.0, -6.0 * a0);
+  const double yy = 1.0 - pow(10.0, -6.0 * a1);
+  y[i] = (initial_state && !(b1 < 0.5)) ? -yy : yy;
+  phi[i] = 2.0 * M_PI * b0;
+}
+
+hipError_t launch_uniforms(int64_t n, uint32_t seed, uint32_t stream, uint64_t first, uint32_t slot, double* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_uniforms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, seed, stream, first, slot,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rambo(int nfin, const PsArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+  switch (nfin) {
+    case 2: hipLaunchKernelGGL(k_rambo<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_rambo<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_rambo<4>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fks_variables(int64_t n, uint32_t seed, uint32_t stream, uint64_t first, int initial_state,
+                                double* xit, double* y, double* phi, hipStream_t st) {
+  hipLaunchKernelGGL(k_fks_variables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, seed, stream, first,
+                     initial_state, xit, y, phi);
+  return hipGetLastError();
+}
+
+}  // namespace nlo

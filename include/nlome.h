@@ -259,6 +259,17 @@ nlo_status nlo_phase_space(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uin
 nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
                              int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream);
 
+/* Partonic cross section of proc_id at fixed sqrt(s_hat) by plain Monte Carlo
+ * over n RAMBO points generated on the device (seed, stream; events 0..n-1),
+ * with |M|^2 in precision prec:
+ *   sigma = (1/n) sum_e w_e |M|^2_e ident / (2 s_hat),  in pb (GeV^-2 x 0.3893793721e9),
+ * error = the standard error of that mean.  Sums are accumulated in FP64 in a
+ * fixed order (reproducible for a given n).  Uses the context workspace,
+ * processes 2^20 events per chunk and synchronises the stream before
+ * returning.  error_pb may be NULL. */
+nlo_status nlo_cross_section(nlo_ctx* ctx, int proc_id, int64_t n, uint32_t seed, uint32_t stream, double sqrt_s,
+                             nlo_prec prec, double* sigma_pb, double* error_pb, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
                    nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
-                   nlo_uniforms, nlo_phase_space, nlo_fks_variables)
+                   nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -136,4 +136,8 @@ class Context:
         nlo_fks_variables(self.ctx, n, seed, stream, first, 1 if initial_state else 0, xt.data_ptr(), y.data_ptr(),
                           phi.data_ptr(), self._stream())
         return xt, y, phi
+
+    def cross_section(self, proc, n, sqrt_s, stream, prec="fp64", seed=SEED):
+        """(sigma, error) in pb at fixed sqrt(s_hat), plain Monte Carlo on the device."""
+        return nlo_cross_section(self.ctx, proc_id(proc), n, seed, stream, float(sqrt_s), PREC[prec], self._stream())
 

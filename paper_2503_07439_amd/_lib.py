@@ -83,6 +83,8 @@ SIGNATURES = {
                          ctypes.c_double, ctypes.c_double, _VP, _VP, _VP], ctypes.c_int),
     "nlo_fks_variables": ([_VP, _I64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, _VP, _VP, _VP,
                            _VP], ctypes.c_int),
+    "nlo_cross_section": ([_VP, ctypes.c_int, _I64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _VP], ctypes.c_int),
 }
 
 
@@ -196,3 +198,10 @@ def nlo_phase_space(ctx, proc_id, n, ld, seed, stream, first, sqrt_s_lo, sqrt_s_
 def nlo_fks_variables(ctx, n, seed, stream, first, initial_state, xit_ptr, y_ptr, phi_ptr, stream_ptr):
     return check(lib().nlo_fks_variables(ctx, n, seed, stream, first, initial_state, xit_ptr, y_ptr, phi_ptr,
                                          stream_ptr))
+
+
+def nlo_cross_section(ctx, proc_id, n, seed, stream, sqrt_s, prec, stream_ptr):
+    sig, err = ctypes.c_double(), ctypes.c_double()
+    check(lib().nlo_cross_section(ctx, proc_id, n, seed, stream, sqrt_s, prec, ctypes.byref(sig), ctypes.byref(err),
+                                  stream_ptr))
+    return sig.value, err.value

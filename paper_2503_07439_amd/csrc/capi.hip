@@ -629,4 +629,65 @@ nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t st
   return NLO_OK;
 }
 
+nlo_status nlo_cross_section(nlo_ctx* ctx, int proc_id, int64_t n, uint32_t seed, uint32_t stream, double sqrt_s,
+                             nlo_prec prec, double* sigma_pb, double* error_pb, void* hip_stream) {
+  nlo_status st = check_ctx(ctx, proc_id, "nlo_cross_section");
+  if (st) return st;
+  const ProcStatic& P = PROC_STATIC[proc_id];
+  if (n < 2 || n > (int64_t)1 << 40) return fail(NLO_EINVAL, "nlo_cross_section: need 2 <= n <= 2^40");
+  if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "nlo_cross_section: bad precision");
+  if (!sigma_pb) return fail(NLO_EINVAL, "nlo_cross_section: sigma_pb is NULL");
+  if (P.nin != 2 || P.npart - 2 < 2 || P.npart - 2 > 4)
+    return fail(NLO_EUNSUPPORTED, "nlo_cross_section: process %s has no 2 -> 2..4 generator", P.name);
+  PsArgs a{};
+  double msum = 0.0;
+  for (int k = 2; k < P.npart; ++k) {
+    a.mass[k - 2] = (P.top_legs >> k) & 1u ? ctx->params.m_top : 0.0;
+    msum += a.mass[k - 2];
+  }
+  if (!(sqrt_s > msum) || !std::isfinite(sqrt_s))
+    return fail(NLO_EINVAL, "nlo_cross_section: need %g < sqrt_s < inf", msum);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, "nlo_cross_section");
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 20);
+  // workspace: momenta, weights, |M|^2, partial sums, accumulator, then the
+  // half-width fallback list
+  const size_t mom_d = (size_t)P.npart * 4 * chunk, xs_d = mom_d + 2 * (size_t)chunk + XS_PART_DOUBLES + 8;
+  st = ensure_ws(ctx, xs_d * sizeof(double) + half_ws_bytes(chunk), s, "nlo_cross_section");
+  if (st) return st;
+  double* base = static_cast<double*>(ctx->ws);
+  double *mom = base, *w = mom + mom_d, *me2 = w + chunk, *part = me2 + chunk, *acc = part + XS_PART_DOUBLES;
+  void* hws = static_cast<void*>(acc + 8);
+  // f = w |M|^2 ident / (2 s) in pb (1 GeV^-2 = 0.3893793721e9 pb)
+  const double conv = 0.3893793721e9;
+  const double scale = P.ident * conv / (2.0 * sqrt_s * sqrt_s);
+  a.ld = chunk;
+  a.seed = seed;
+  a.stream = stream;
+  a.rs_lo = sqrt_s;
+  a.rs_hi = sqrt_s;
+  a.mom = mom;
+  a.weight = w;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = std::min(chunk, n - off);
+    a.n = m;
+    a.first = (uint64_t)off;
+    hipError_t e = launch_rambo(P.npart - 2, a, s);
+    if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_cross_section: generation failed: %s", hipGetErrorString(e));
+    st = launch_me2(ctx, proc_id, m, chunk, mom, me2, prec, s, hws);
+    if (st) return st;
+    e = launch_xs_sums(m, w, me2, scale, part, acc, off == 0, s);
+    if (e != hipSuccess) return fail(NLO_EDEVICE, "nlo_cross_section: reduction failed: %s", hipGetErrorString(e));
+  }
+  double h[2];
+  if (hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return fail(NLO_EDEVICE, "nlo_cross_section: result copy failed");
+  const double mean = h[0] / (double)n;
+  *sigma_pb = mean;
+  if (error_pb) *error_pb = std::sqrt(std::max(0.0, h[1] / (double)n - mean * mean) / (double)(n - 1));
+  return NLO_OK;
+}
+
 }  // extern "C"

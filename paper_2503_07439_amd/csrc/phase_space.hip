@@ -189,6 +189,70 @@ __global__ __launch_bounds__(256) void k_fks_variables(int64_t n, uint32_t seed,
   phi[i] = 2.0 * M_PI * b0;
 }
 
+// Monte Carlo sums of f = scale * w * me2 over a chunk, in a fixed order:
+// block b reduces its contiguous share into part[b] = (sum f, sum f^2); one
+// block then adds the parts, in order, to acc.
+constexpr int XS_BLOCKS = 512;
+
+__global__ __launch_bounds__(256) void k_xs_partial(int64_t n, const double* __restrict__ w,
+                                                    const double* __restrict__ me2, double scale,
+                                                    double* __restrict__ part) {
+  __shared__ double s1[256], s2[256];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const double f = scale * w[i] * me2[i];
+    a += f;
+    b += f * f;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      s1[threadIdx.x] += s1[threadIdx.x + k];
+      s2[threadIdx.x] += s2[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_xs_final(int nparts, const double* __restrict__ part, double* acc,
+                                                  int reset) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      s1[threadIdx.x] += s1[threadIdx.x + k];
+      s2[threadIdx.x] += s2[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    acc[0] = (reset ? 0.0 : acc[0]) + s1[0];
+    acc[1] = (reset ? 0.0 : acc[1]) + s2[0];
+  }
+}
+
+hipError_t launch_xs_sums(int64_t n, const double* w, const double* me2, double scale, double* part, double* acc,
+                          bool reset, hipStream_t st) {
+  hipLaunchKernelGGL(k_xs_partial, dim3(XS_BLOCKS), dim3(256), 0, st, n, w, me2, scale, part);
+  hipLaunchKernelGGL(k_xs_final, dim3(1), dim3(256), 0, st, XS_BLOCKS, (const double*)part, acc, reset ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_uniforms(int64_t n, uint32_t seed, uint32_t stream, uint64_t first, uint32_t slot, double* out,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_uniforms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, seed, stream, first, slot,

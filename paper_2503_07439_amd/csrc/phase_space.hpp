@@ -21,4 +21,10 @@ hipError_t launch_rambo(int nfin, const PsArgs& a, hipStream_t st);
 hipError_t launch_fks_variables(int64_t n, uint32_t seed, uint32_t stream, uint64_t first, int initial_state,
                                 double* xit, double* y, double* phi, hipStream_t st);
 
+// fixed-order sums (sum f, sum f^2) of f = scale * w * me2 over n events,
+// added to acc[0..1] (or replacing them when reset); part: 2 * 512 doubles
+constexpr int64_t XS_PART_DOUBLES = 2 * 512;
+hipError_t launch_xs_sums(int64_t n, const double* w, const double* me2, double scale, double* part, double* acc,
+                          bool reset, hipStream_t st);
+
 }  // namespace nlo

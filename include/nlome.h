@@ -260,8 +260,9 @@ nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t st
                              int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream);
 
 /* Partonic cross section of proc_id at fixed sqrt(s_hat) by plain Monte Carlo
- * over n RAMBO points generated on the device (seed, stream; events 0..n-1),
- * with |M|^2 in precision prec:
+ * integration (the paper's section "Monte-Carlo integration": the mean of the
+ * integrand times the volume of the measure) over n RAMBO points generated on
+ * the device (seed, stream; events 0..n-1), with |M|^2 in precision prec:
  *   sigma = (1/n) sum_e w_e |M|^2_e ident / (2 s_hat),  in pb (GeV^-2 x 0.3893793721e9),
  * error = the standard error of that mean.  Sums are accumulated in FP64 in a
  * fixed order (reproducible for a given n).  Uses the context workspace,

@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-mix", action="store_true", help="skip the batched-mix leg")
     ap.add_argument("--no-half", action="store_true", help="skip the FP16 leg")
     ap.add_argument("--no-gen", action="store_true", help="skip the device phase-space generation leg")
+    ap.add_argument("--mask-study", action="store_true",
+                    help="also time branch-free against compact cut masks on the 2^18 gg->ttgg (4,5) FKS set")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -132,6 +134,44 @@ def mix_leg(ctx, steps):
     return {"items": [[k, p, list(q) if q else None, int(c)] for (k, p, q, _), c in zip(MIX_ITEMS, counts)],
             "events": total, "precision": "mixed", "graph_ms": res["graph"], "direct_ms": res["direct"],
             "graph_events_per_s": total / (res["graph"] * 1e-3), "graph_speedup": res["direct"] / res["graph"]}
+
+
+def mask_study(ctx, steps):
+    """Wasted compute of branch-free cut masks (every term evaluated, failed
+    ones zeroed) against compact masks (events failing the R cut skip the
+    real |M|^2), for several pass fractions of the R cut (other cuts pass)."""
+    import torch
+    from nlo_inputs.philox import uniforms
+    from nlo_inputs.workloads import events, fks_variables
+    n = 1 << 18
+    mom, _ = events("gg_ttg", n, (400.0, 2000.0), stream=42)
+    xt, y, phi = fks_variables(n, stream=42)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    M, X, Y, P = t(mom), t(xt), t(y), t(phi)
+    u = uniforms(7439, 43, np.arange(n, dtype=np.uint64), 0)[:, 0]
+    rows = []
+    for frac in (1.0, 0.5, 0.25):
+        mask = np.ones((4, n), dtype=np.uint8)
+        mask[1] = (u < frac).astype(np.uint8)
+        tm = t(mask)
+        ms = {}
+        for mode in (False, True):
+            ctx.set_fks_mask_mode(mode)
+            fn = lambda: ctx.subtracted("gg_ttgg", 4, 5, M, X, Y, P, prec="mixed", mask=tm)
+            fn()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            ms["compact" if mode else "branch_free"] = t0.elapsed_time(t1) / steps
+        ctx.set_fks_mask_mode(False)
+        rows.append({"r_pass": frac, "branch_free_ms": ms["branch_free"], "compact_ms": ms["compact"],
+                     "wasted_fraction": 1 - ms["compact"] / ms["branch_free"]})
+    return {"sector": "gg_ttgg (4,5)", "events": n, "precision": "mixed", "rows": rows}
 
 
 def measured_traffic(kernel, n):
@@ -302,6 +342,8 @@ def main():
         # single-issue vector FP32 rate is the attainable ceiling
         roofline["frac_of_unpacked_fp32_peak"] = achieved / PEAK["fp64"]
 
+    study = mask_study(ctx, 3) if args.mask_study else None
+
     mix = None
     if not args.no_mix:
         mix = mix_leg(ctx, max(3, args.steps // 4))
@@ -326,7 +368,7 @@ def main():
                    "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
                    "helicities": info.ngood_hel},
         "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
-        "half_precision": half, "device_generation": gen, "batch_mix": mix,
+        "half_precision": half, "device_generation": gen, "batch_mix": mix, "mask_study": study,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

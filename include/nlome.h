@@ -188,6 +188,16 @@ typedef struct {
  * larger n after synchronising the device (so do such a first call outside
  * stream capture); calls that overlap on different streams with the same
  * context race on it. */
+/* How nlo_subtracted treats the cut masks (a context setting; batch plans
+ * take the one in force when they are made).
+ *   0 (default): branch-free, as in the paper's Algorithm 2 -- every term is
+ *      evaluated at every point and failed cuts zero it afterwards;
+ *   1: compact -- events whose R cut fails are set aside by the map kernel
+ *      and skip the real |M|^2 evaluation (the paper's "smarter" variant that
+ *      evaluates only points passing a cut; its other terms are evaluated as
+ *      before).  Results are bit for bit those of mode 0. */
+nlo_status nlo_set_fks_mask_mode(nlo_ctx* ctx, int mode);
+
 nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
                           const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
                           const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream);

@@ -10,7 +10,7 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
                    nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
-                   nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section)
+                   nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -103,6 +103,11 @@ class Context:
 
     def set_fks_threshold(self, thr):
         nlo_set_fks_threshold(self.ctx, thr)
+
+    def set_fks_mask_mode(self, compact):
+        """False: branch-free masks (evaluate everything, zero failed terms);
+        True: events failing the R cut skip the real |M|^2."""
+        nlo_set_fks_mask_mode(self.ctx, 1 if compact else 0)
 
     def set_kernel_config(self, proc, prec, block, colour_mode=0):
         nlo_set_kernel_config(self.ctx, proc_id(proc), PREC[prec], block, colour_mode)

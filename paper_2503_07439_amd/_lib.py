@@ -71,6 +71,7 @@ SIGNATURES = {
     "nlo_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
                         ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
     "nlo_set_fks_threshold": ([_VP, ctypes.c_double], ctypes.c_int),
+    "nlo_set_fks_mask_mode": ([_VP, ctypes.c_int], ctypes.c_int),
     "nlo_batch_plan": ([_VP, ctypes.POINTER(nlo_work_item), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)],
                        ctypes.c_int),
     "nlo_batch_run": ([_VP, _VP], ctypes.c_int),
@@ -205,3 +206,7 @@ def nlo_cross_section(ctx, proc_id, n, seed, stream, sqrt_s, prec, stream_ptr):
     check(lib().nlo_cross_section(ctx, proc_id, n, seed, stream, sqrt_s, prec, ctypes.byref(sig), ctypes.byref(err),
                                   stream_ptr))
     return sig.value, err.value
+
+
+def nlo_set_fks_mask_mode(ctx, mode):
+    return check(lib().nlo_set_fks_mask_mode(ctx, mode))

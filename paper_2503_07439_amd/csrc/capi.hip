@@ -51,6 +51,7 @@ struct nlo_ctx {
   std::mutex mu;
   nlo_kernel_config cfg[NPROC_][5];
   double fks_thr = 1e-4;
+  int fks_compact = 0;   // 1: skip the real |M|^2 of events whose R cut fails
   // FKS workspace: real momenta, real |M|^2, bucket permutation, bucket sizes
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -198,6 +199,14 @@ nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold) {
   return NLO_OK;
 }
 
+nlo_status nlo_set_fks_mask_mode(nlo_ctx* ctx, int mode) {
+  if (!ctx) return fail(NLO_EINVAL, "nlo_set_fks_mask_mode: ctx is NULL");
+  if (mode != 0 && mode != 1) return fail(NLO_EINVAL, "nlo_set_fks_mask_mode: mode must be 0 or 1");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->fks_compact = mode;
+  return NLO_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -228,7 +237,7 @@ nlo_status check_subtracted(const nlo_ctx* ctx, int real_proc, int fks_i, int fk
 
 size_t fks_ws_bytes(int real_proc, int64_t n) {
   const int nr = PROC_STATIC[real_proc].npart;
-  return (size_t)n * (nr * 4 + 1) * sizeof(double) + (size_t)n * sizeof(unsigned) + 128;
+  return (size_t)n * (nr * 4 + 1) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128;
 }
 
 // the launch sequence of one FKS sector on stream s with workspace ws
@@ -248,8 +257,10 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.real = reinterpret_cast<double*>(base);
   a.me2r = a.real + (size_t)n * nr * 4;
   a.inv = reinterpret_cast<unsigned*>(a.me2r + n);
-  uintptr_t c = reinterpret_cast<uintptr_t>(a.inv + n);
+  a.skip_inv = a.inv + n;
+  uintptr_t c = reinterpret_cast<uintptr_t>(a.skip_inv + n);
   a.cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
+  a.compact = (ctx->fks_compact && mask) ? 1 : 0;
   a.thr = ctx->fks_thr;
   a.mode = prec == NLO_FP64 ? 1 : (prec == NLO_FP32 ? 0 : 2);
   a.scale_b = coupling_scale(sec->born, ctx->params);
@@ -281,6 +292,9 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   }
   if (err == hipSuccess && a.mode != 1) err = sec->born_fn[1](a, 0, block, s);
   if (err == hipSuccess && a.mode != 0) err = sec->born_fn[0](a, 1, block, s);
+  // compact mode: counterterms of the events that skipped the real |M|^2
+  if (err == hipSuccess && a.compact && a.mode != 1) err = sec->born_fn[1](a, 2, block, s);
+  if (err == hipSuccess && a.compact && a.mode != 0) err = sec->born_fn[0](a, 3, block, s);
   if (err == hipSuccess && out->w_sum) {
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, s, n, (const double*)out->W, out->w_sum);
     err = hipGetLastError();

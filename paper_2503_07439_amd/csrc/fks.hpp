@@ -205,7 +205,11 @@ struct FksArgs {
   double* real;                        // workspace [NR][4][n], bucket order
   double* me2r;                        // workspace [n], bucket order
   unsigned* inv;                       // workspace [n]: bucket position -> event
-  unsigned* cnt;                       // workspace [2]: FP32 and FP64 bucket sizes
+  unsigned* cnt;                       // workspace [4]: FP32 and FP64 bucket sizes, then the same
+                                       // for the events whose real emission is skipped
+  unsigned* skip_inv;                  // workspace [n]: skipped events (compact mode), FP32 from
+                                       // the front, FP64 from the back
+  int compact;                         // 1: events failing the R cut skip the real |M|^2
   double thr;                          // route to FP64 when min(xi, 1-|y|) < thr
   int mode;                            // 0: all FP32, 1: all FP64, 2: route
   double scale_b, g2, mt;
@@ -224,41 +228,54 @@ __device__ __forceinline__ void load_born(const FksArgs& a, int64_t e, double (&
 }
 
 static __global__ void k_fks_zero(unsigned* cnt) {
-  if (threadIdx.x < 2) cnt[threadIdx.x] = 0u;
+  if (threadIdx.x < 4) cnt[threadIdx.x] = 0u;
 }
 
-// 1. map and route
+// 1. map and route.  Every event goes to the FP32 or the FP64 bucket; in
+// compact mode an event whose R cut fails goes to the skipped list instead,
+// so the real |M|^2 is not evaluated for it (its counterterms still are).
 template <class S>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_map(FksArgs a) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = e < a.n;
   double kb[S::NB][4], kr[S::NR][4];
   FksKin K;
-  bool f64 = false;
+  bool f64 = false, skip = false;
   if (act) {
     load_born<S>(a, e, kb);
     fks_map<S>(kb, a.xit[e], a.y[e], a.phi[e], kr, K);
     const double dist = fmin(K.xi, 1.0 - fabs(K.y));
     f64 = (a.mode == 1) || (a.mode == 2 && !(dist >= a.thr));
+    skip = a.compact && a.mask && !a.mask[1 * a.ld + e];
   }
-  // wave-aggregated bucket positions
-  const unsigned long long m64 = __ballot(act && f64), m32 = __ballot(act && !f64);
+  // wave-aggregated positions in the four lists
+  const unsigned long long m32 = __ballot(act && !f64 && !skip), m64 = __ballot(act && f64 && !skip);
+  const unsigned long long s32 = __ballot(act && !f64 && skip), s64 = __ballot(act && f64 && skip);
   const int lane = threadIdx.x & 63;
   const unsigned long long lower = lane ? (~0ull >> (64 - lane)) : 0ull;
-  unsigned b32 = 0, b64 = 0;
+  unsigned b32 = 0, b64 = 0, c32 = 0, c64 = 0;
   if (lane == 0) {
     if (m32) b32 = atomicAdd(&a.cnt[0], (unsigned)__popcll(m32));
     if (m64) b64 = atomicAdd(&a.cnt[1], (unsigned)__popcll(m64));
+    if (s32) c32 = atomicAdd(&a.cnt[2], (unsigned)__popcll(s32));
+    if (s64) c64 = atomicAdd(&a.cnt[3], (unsigned)__popcll(s64));
   }
   b32 = __shfl(b32, 0);
   b64 = __shfl(b64, 0);
+  c32 = __shfl(c32, 0);
+  c64 = __shfl(c64, 0);
   if (!act) return;
-  const int64_t pos = f64 ? a.n - 1 - (int64_t)(b64 + __popcll(m64 & lower)) : (int64_t)(b32 + __popcll(m32 & lower));
-  a.inv[pos] = (unsigned)e;
+  if (skip) {
+    const int64_t pos = f64 ? a.n - 1 - (int64_t)(c64 + __popcll(s64 & lower)) : (int64_t)(c32 + __popcll(s32 & lower));
+    a.skip_inv[pos] = (unsigned)e;
+  } else {
+    const int64_t pos = f64 ? a.n - 1 - (int64_t)(b64 + __popcll(m64 & lower)) : (int64_t)(b32 + __popcll(m32 & lower));
+    a.inv[pos] = (unsigned)e;
 #pragma unroll
-  for (int k = 0; k < S::NR; ++k)
+    for (int k = 0; k < S::NR; ++k)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a.real[(k * 4 + m) * a.n + pos] = kr[k][m];
+      for (int m = 0; m < 4; ++m) a.real[(k * 4 + m) * a.n + pos] = kr[k][m];
+  }
   if (a.real_out) {
 #pragma unroll
     for (int k = 0; k < S::NR; ++k)
@@ -288,7 +305,7 @@ __device__ double born_spin(const typename BP::template Pre<T>& s, const double*
 template <class S>
 __device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e, double B, double gR, double gS,
                                           double gC, double gCm, double gSC, double gSCm, double xi, double y) {
-  uint8_t st = which == 1 ? 2 : 0;
+  uint8_t st = (which & 1) ? 2 : 0;
   double Bo = B;
   if (a.mask) {
     const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e], mC = a.mask[3 * a.ld + e];
@@ -350,7 +367,7 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
   const double Bminus = born_sum<BM, T>(kb, a.mt) * a.scale_bm;
   const double Pp = FKS_CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
   const double Pm = 0.5 * (x * x + (1.0 - x) * (1.0 - x)) * Bminus;
-  const double gR = xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
+  const double gR = which >= 2 ? 0.0 : xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
   fks_store<S>(a, which, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, xi, y);
 }
 
@@ -358,11 +375,15 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
 template <class S, class T>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which) {
   using BP = typename S::Born;
-  const int64_t lo = which == 0 ? 0 : a.n - (int64_t)a.cnt[1];
-  const int64_t hi = which == 0 ? (int64_t)a.cnt[0] : a.n;
+  // which: 0 / 1 the FP32 / FP64 bucket of evaluated real emissions, 2 / 3 the
+  // FP32 / FP64 part of the skipped list (no real |M|^2: its R cut failed)
+  const bool skipped = which >= 2;
+  const bool back = which & 1;
+  const int64_t lo = back ? a.n - (int64_t)a.cnt[which] : 0;
+  const int64_t hi = back ? a.n : (int64_t)a.cnt[which];
   const int64_t pos = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pos >= hi) return;
-  const int64_t e = a.inv[pos];
+  const int64_t e = skipped ? a.skip_inv[pos] : a.inv[pos];
   double kb[S::NB][4], kr[S::NR][4];
   FksKin K;
   load_born<S>(a, e, kb);
@@ -407,7 +428,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     }
   const double Ss = fks_sector_soft<S>(kb, K.nh, K.sqs_b);
   const double xi = K.xi, y = K.y, g2 = a.g2;
-  const double me2r = a.me2r[pos];
+  const double me2r = skipped ? 0.0 : a.me2r[pos];
   double gR, gS, gC, gCm = 0.0, gSC, gSCm = 0.0;
   if constexpr (S::J >= 0) {
     gR = xi * xi * (1.0 - y) * me2r * S_real;

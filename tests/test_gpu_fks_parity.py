@@ -160,3 +160,23 @@ def test_fks_argument_errors(gpu):
     with pytest.raises(nl.NloError) as e:
         gpu.set_fks_threshold(2.0)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("real,i,j,born,rs", [SECTORS[0], SECTORS[2], SECTORS[4], SECTORS[8]])
+def test_fks_compact_masks_bitwise(gpu, real, i, j, born, rs, prec):
+    """Compact mode (events failing the R cut skip the real |M|^2) gives
+    bit for bit the results of the branch-free mode."""
+    n = 500 if real != "gg_ttgg" else 120
+    mom, xt, y, phi = _inputs(real, j, born, rs, n, 204)
+    rng = np.random.default_rng(11)
+    mask = (rng.uniform(size=(4, n)) > np.array([[0.1], [0.5], [0.1], [0.1]])).astype(np.uint8)
+    ref = _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec, mask=mask, want_sum=True)
+    gpu.set_fks_mask_mode(True)
+    try:
+        got = _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec, mask=mask, want_sum=True)
+    finally:
+        gpu.set_fks_mask_mode(False)
+    for k in ("W", "xi", "born", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "status", "real_mom", "w_sum"):
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.all(got["g_R"][mask[1] == 0] == 0.0)

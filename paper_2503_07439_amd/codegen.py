@@ -779,6 +779,18 @@ def helicity_order(p):
     return best[1]
 
 
+# Every vertex of the model is a real multiple of a vector coupling and no
+# propagator carries a width.  At real momenta, complex conjugation then maps
+# each external wavefunction to its opposite-helicity partner up to a phase
+# (for spinors through the charge-conjugation-like matrix that leaves every
+# gamma^mu invariant, for vectors eps_-lambda ~ eps_lambda^*), and each tree
+# diagram picks up the same overall phase.  The flow vector of the reversed
+# helicity set is thus a phase times J^*, and with a real colour matrix
+# J^+ C J is unchanged: |M_h|^2 = |M_-h|^2.  The nested helicity sum therefore
+# runs over the half in which the outermost leg has bit 0 and is doubled by
+# the caller (HEL_SYM).  An axial coupling or a width would break this.
+HEL_SYMMETRY = True
+
 # processes whose sub-currents one level above the deepest loop are also
 # evaluated lazily inside it (more flops, far fewer live registers)
 JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
@@ -854,8 +866,10 @@ def emit_nested(p, mslot, dslot, N, nin):
     level_of = {id(n): max(lev[k] for k in n.legs) for n in nodes}
     ind = "    "
     for level in range(deep + 1):
+        # outermost leg: one helicity only when the sum uses |M_h|^2 = |M_-h|^2
+        trips = 1 if (level == 0 and HEL_SYMMETRY) else 2
         L.append(ind + "#pragma unroll 1")
-        L.append(ind + "for (int b%d = 0; b%d < 2; ++b%d) {" % (level, level, level))
+        L.append(ind + "for (int b%d = 0; b%d < %d; ++b%d) {" % (level, level, trips, level))
         ind += "  "
         for cond in checks.get(level, []):
             L.append(ind + "if (%s) continue;" % cond)
@@ -949,6 +963,10 @@ def emit_process(p):
     gs, ee = p.coupling_powers()
     nflow = len(p.flows)
     N = p.npart
+    # the good set is closed under reversing every helicity, so in ascending
+    # order its first half (leg 0 at bit 0) holds one of each pair
+    assert sorted((1 << N) - 1 - h for h in good) == good
+    assert all(h < (1 << (N - 1)) for h in good[:len(good) // 2])
     nin = len(p.incoming)
     # momentum slots: one per distinct leg set
     msets = []
@@ -979,6 +997,9 @@ def emit_process(p):
     L.append("  static constexpr int NDIAG = %d, NTERM = %d, NCUR = %d, GS_POW = %d, E_POW = %d;"
              % (p.ndiagrams, len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee))
     L.append("  static constexpr double AVG = %.17g, IDENT = %.17g;" % (p.avg, p.ident))
+    # helicity_sum and the first NGOOD / HEL_SYM entries of good() cover one
+    # helicity of each pair (h, -h); callers multiply their sums by HEL_SYM
+    L.append("  static constexpr int HEL_SYM = %d;" % (2 if HEL_SYMMETRY else 1))
     L.append("  static constexpr int NMOM = %d, NDEN = %d;" % (len(msets), len(dens)))
     L.append("  static constexpr const char* NAME = \"%s\";" % nm)
     L.append("  __device__ static int good(int i) { return %s_good[i]; }" % nm)

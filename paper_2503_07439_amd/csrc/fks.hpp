@@ -285,19 +285,24 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_map(FksArgs a) {
 }
 
 // spin-correlated Born: leg LEG's polarisation replaced by (0, ep), summed
-// over the other helicities
+// over the other helicities.  The real vector is its own conjugate, so
+// reversing all the other helicities leaves the colour-summed square
+// unchanged (as for |M|^2): with HEL_SYM = 2 one more leg (PIN) is held at
+// bit 0 and the sum doubled.
 template <class BP, int LEG, class T>
 __device__ double born_spin(const typename BP::template Pre<T>& s, const double* ep, T mt) {
+  constexpr int PIN = LEG == 0 ? 1 : 0;
   const w4<T> ov = {{cx<T>{T(0), T(0)}, cx<T>{T(ep[0]), T(0)}, cx<T>{T(ep[1]), T(0)}, cx<T>{T(ep[2]), T(0)}}};
   double acc = 0.0;
 #pragma unroll 1
   for (int h = 0; h < BP::NHEL; ++h) {
     if ((h >> (BP::NPART - 1 - LEG)) & 1) continue;
+    if (BP::HEL_SYM == 2 && ((h >> (BP::NPART - 1 - PIN)) & 1)) continue;
     cx<T> J[BP::NFLOW];
     BP::template amplitudes<T, LEG>(s, h, mt, J, &ov);
     acc += (double)BP::colour_sum(J);
   }
-  return acc;
+  return acc * BP::HEL_SYM;
 }
 
 // Algorithm-2 masks (a failed cut zeroes its contribution after evaluation),
@@ -342,7 +347,7 @@ __device__ __forceinline__ double born_sum(const double (&kb)[BP::NPART][4], dou
   BP::prologue(kb, s, mt);
   double acc = 0.0;
   BP::helicity_sum(s, T(mt), [&](const cx<T> (&J)[BP::NFLOW]) { acc += (double)BP::colour_sum(J); });
-  return acc;
+  return acc * BP::HEL_SYM;   // the sum covers one of each pair (h, -h)
 }
 
 // Quark FKS parton from the initial state (e.g. u g -> t tbar u with the
@@ -362,7 +367,7 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
   BP::prologue(kb, sp, a.mt);
   double bp = 0.0;
   BP::helicity_sum(sp, T(a.mt), [&](const cx<T> (&J)[BP::NFLOW]) { bp += (double)BP::colour_sum(J); });
-  const double Bplus = bp * a.scale_b;
+  const double Bplus = bp * BP::HEL_SYM * a.scale_b;
   const double Bperp = born_spin<BP, 0, T>(sp, K.ep, T(a.mt)) * a.scale_b;
   const double Bminus = born_sum<BM, T>(kb, a.mt) * a.scale_bm;
   const double Pp = FKS_CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
@@ -394,7 +399,10 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     return;
   } else {
 
-  // Born: |M|^2 and the helicity-summed density of the flow vector
+  // Born: |M|^2 and the helicity-summed density Re(J_u J_v^*) of the flow
+  // vector.  Both are unchanged by reversing every helicity (J -> phase J^*),
+  // so the loop takes the first NGOOD / HEL_SYM good helicities, one of each
+  // pair, and the sums are doubled.
   typename BP::template Pre<T> s;
   BP::prologue(kb, s, a.mt);
   double rho[BP::NRHO];
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
   for (int q = 0; q < BP::NRHO; ++q) rho[q] = 0.0;
   double bsum = 0.0;
 #pragma unroll 1
-  for (int ih = 0; ih < BP::NGOOD; ++ih) {
+  for (int ih = 0; ih < BP::NGOOD / BP::HEL_SYM; ++ih) {
     cx<T> J[BP::NFLOW];
     BP::amplitudes(s, BP::good(ih), T(a.mt), J);
     bsum += (double)BP::colour_sum(J);
@@ -412,9 +420,11 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
 #pragma unroll
       for (int v = u; v < BP::NFLOW; ++v, ++q) rho[q] += (double)(J[u].r * J[v].r + J[u].i * J[v].i);
   }
+#pragma unroll
+  for (int q = 0; q < BP::NRHO; ++q) rho[q] *= BP::HEL_SYM;
   double bkl[BP::NCL][BP::NCL];
   BP::colour_corr(rho, bkl);
-  const double B = bsum * a.scale_b;
+  const double B = bsum * BP::HEL_SYM * a.scale_b;
   // eikonal factor -sum_kl (p_k.p_l)/((p_k.n)(p_l.n)) B_kl with n = (1, nh)
   const double n4[4] = {1.0, K.nh[0], K.nh[1], K.nh[2]};
   double eik = 0.0;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t l
   P::prologue(p, s, mt);
   double acc = 0.0;
   P::helicity_sum(s, T(mt), [&](const cx<T> (&J)[P::NFLOW]) { acc += (double)P::colour_sum(J); });
-  out[e] = acc * scale;
+  out[e] = acc * (P::HEL_SYM * scale);   // the sum covers one of each pair (h, -h)
 }
 
 // ---------------------------------------------------------------------------
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t l
       for (int r = 0; r < 4; ++r) rows[16 * t + 4 * (lane >> 4) + r] = rs[t][r];
   }
   __syncthreads();
-  if (e < hi) out[e] = (rows[lane] + rows[64 + lane]) * scale;
+  if (e < hi) out[e] = (rows[lane] + rows[64 + lane]) * (P::HEL_SYM * scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,8 +283,8 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_pair(int64_t n, int64_t l
     acc0 += (double)P::colour_sum(J0);
     acc1 += (double)P::colour_sum(J1);
   });
-  out[e0] = acc0 * f[0] * scale;
-  if (has1) out[e1] = acc1 * f[1] * scale;
+  out[e0] = acc0 * f[0] * (P::HEL_SYM * scale);
+  if (has1) out[e1] = acc1 * f[1] * (P::HEL_SYM * scale);
 }
 
 template <class P>

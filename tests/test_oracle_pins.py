@@ -5,6 +5,7 @@ mathematics, independent of the oracle itself:
 * the colour-dressed brute-force evaluation (full Feynman rules, explicit
   colour sums) against the colour-ordered recursion,
 * gauge invariance, Lorentz invariance, Bose symmetry, coupling scaling,
+  equal |M_h|^2 for reversed helicities,
 * exact colour-matrix identities,
 * spinor and polarisation identities (Dirac equation, completeness).
 A plausible mistake anywhere in the oracle (a dropped diagram, a wrong sign or
@@ -236,6 +237,24 @@ def test_lorentz_invariance(orc, proc):
     a = orc.me2(proc, mom)
     b = orc.me2(proc, transform(mom, L))
     assert np.max(np.abs(a / b - 1)) < 1e-11
+
+
+@pytest.mark.parametrize("proc", ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu",
+                                  "gg_ttgg"])
+def test_helicity_reversal_symmetry(orc, proc):
+    """Real vector couplings and no widths: reversing every helicity turns a
+    tree amplitude at real momenta into a phase times its complex conjugate,
+    so each colour-summed |M_h|^2 equals |M_-h|^2 (the GPU kernels sum one of
+    each pair and double it; the oracle sums all helicities)."""
+    rs = 1000.0 if proc.startswith("ee") else (400.0, 2000.0)
+    mom, _ = events(proc, 48, rs, stream=16)
+    ph = orc.me2_hel(proc, mom)
+    nh = ph.shape[0]
+    assert np.max(ph) > 0
+    flip = ph[nh - 1 - np.arange(nh)]
+    assert np.max(np.abs(ph - flip) / ph.max(axis=0)) < 1e-12
+    # not a tautology: single helicities differ from each other
+    assert np.max(np.abs(ph - np.roll(ph, 1, axis=0)) / ph.max(axis=0)) > 1e-3
 
 
 @pytest.mark.parametrize("proc,swap", [("gg_tt", (0, 1)), ("gg_ttg", (0, 1)), ("gg_ttgg", (0, 1)), ("gg_ttgg", (4, 5))])

@@ -177,8 +177,8 @@ def mask_study(ctx, steps):
 def measured_traffic(kernel, n):
     """HBM bytes per launch from the committed rocprofv3 counter passes
     (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), scaled to
-    n events -- or None when the kernel sources have changed since the
-    counters were taken, or for another kernel."""
+    n events -- or None when the kernel sources or compile flags (build.py)
+    have changed since the counters were taken, or for another kernel."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "gg_ttg_2p22_counters.md")
     if not os.path.exists(path):
@@ -189,8 +189,8 @@ def measured_traffic(kernel, n):
         if line.startswith("traffic:"):
             rec = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
     h = hashlib.sha256()
-    for f in ("generated/gg_ttg.hpp", "kernels.hpp", "helas.hpp", "launch.hpp"):
-        with open(os.path.join(ROOT, "paper_2503_07439_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/generated/gg_ttg.hpp", "csrc/kernels.hpp", "csrc/helas.hpp", "csrc/launch.hpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_2503_07439_amd", f), "rb") as fh:
             h.update(fh.read())
     if not rec or rec.get("sources") != h.hexdigest()[:16] or rec.get("kernel") != kernel.replace(" ", ""):
         return None

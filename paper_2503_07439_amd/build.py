@@ -25,6 +25,30 @@ HIPCC_FLAGS = [
 # rounded back) takes about 14 minutes to optimise at -O3 and 4 at -O1.
 UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-O1",)}
 
+# |M|^2 units in FP64, FP32 and with MFMA colour (tu_<process>_<0|1|2>.hip):
+# external polarisation vectors have a zero time component and a real z
+# component, and massless spinors have a zero chiral half.  Under strict IEEE
+# rules the compiler must keep every product with those zeros (x * 0 is NaN
+# for infinite x and -0 for negative x); these kernels test no value for NaN
+# or infinity and never produce one from finite momenta, so they drop those
+# rules and the products fold away (about 11 % fewer instructions for
+# g g -> t tbar g).  The FKS units keep IEEE semantics: they test the
+# subtracted weight for finiteness.  The FP16/BF16 units also keep them (the
+# compiler's instruction selection fails on their packed conversions).
+# The FP64 g g -> t tbar g g unit is left out: its spill code gets slower with
+# them (136 against 125 ms per 2^20 events, measured).
+ME2_FAST_VARIANTS = ("0", "1", "2")
+ME2_FAST_EXCLUDE = ("tu_gg_ttgg_0.hip",)
+ME2_FAST_FLAGS = ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros")
+
+
+def unit_flags(base):
+    flags = list(UNIT_FLAGS.get(base, ()))
+    if base.startswith("tu_") and not base.startswith("tu_fks_") and base not in ME2_FAST_EXCLUDE:
+        if os.path.splitext(base)[0].rsplit("_", 1)[1] in ME2_FAST_VARIANTS:
+            flags += ME2_FAST_FLAGS
+    return flags
+
 
 def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -60,7 +84,7 @@ def _compile(src, extra, verbose, force):
         t = os.path.getmtime(obj)
         if all(os.path.getmtime(d) <= t for d in _deps(src) if os.path.exists(d)):
             return obj
-    cmd = [_hipcc()] + HIPCC_FLAGS + list(extra) + list(UNIT_FLAGS.get(os.path.basename(src), ())) + ["-c", "-o", obj, src]
+    cmd = [_hipcc()] + HIPCC_FLAGS + list(extra) + unit_flags(os.path.basename(src)) + ["-c", "-o", obj, src]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr[-4000:]))

@@ -791,6 +791,20 @@ def helicity_order(p):
 # the caller (HEL_SYM).  An axial coupling or a width would break this.
 HEL_SYMMETRY = True
 
+# External vector legs are summed over their two real linear polarisations
+# instead of their two helicities: for each leg the helicity states are a
+# unitary combination of them, so the summed |A|^2 is the same, and currents
+# and amplitudes with a real vector need fewer multiplications.  The one
+# exception is the outermost leg while the helicity-reversal halving holds it
+# at one helicity: that argument needs a helicity state there (the sum over
+# all the other legs does not depend on their basis).
+LINEAR_POLARISATIONS = True
+
+
+def _linear(p, leg, level):
+    return (LINEAR_POLARISATIONS and p.itype[leg] in ("g", "a")
+            and not (level == 0 and HEL_SYMMETRY))
+
 # processes whose sub-currents one level above the deepest loop are also
 # evaluated lazily inside it (more flops, far fewer live registers)
 JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
@@ -876,7 +890,9 @@ def emit_nested(p, mslot, dslot, N, nin):
         for n in nodes:
             if level_of[id(n)] != level or (level >= jit_from and n.kind != "ext"):
                 continue
-            if n.kind == "ext":
+            if n.kind == "ext" and _linear(p, min(n.legs), level):
+                L.append(ind + "const w4<T> v%d = wf_lin(s.x%d, b%d);" % (n.id, min(n.legs), level))
+            elif n.kind == "ext":
                 L.append(ind + "const w4<T> v%d = %s;" % (n.id, _ext_call(p, min(n.legs), "b%d" % level, nin)))
             else:
                 L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot)))
@@ -893,8 +909,14 @@ def emit_nested(p, mslot, dslot, N, nin):
         L.append(ind + "cx<T> J0[NFLOW];")
         L.append(ind + "for (int f = 0; f < NFLOW; ++f) J0[f] = czero<T>();")
     else:
-        L.append(ind + "const w4<T> r0 = %s;" % _ext_call(p, root, "0", nin))
-        L.append(ind + "const w4<T> r1 = %s;" % _ext_call(p, root, "1", nin))
+        if _linear(p, root, N - 1):
+            # a vector root takes its two real linear polarisations in place
+            # of its helicities (same sum of |A|^2, cheaper amplitudes)
+            L.append(ind + "const w4<T> r0 = wf_lin(s.x%d, 0);" % root)
+            L.append(ind + "const w4<T> r1 = wf_lin(s.x%d, 1);" % root)
+        else:
+            L.append(ind + "const w4<T> r0 = %s;" % _ext_call(p, root, "0", nin))
+            L.append(ind + "const w4<T> r1 = %s;" % _ext_call(p, root, "1", nin))
         roots = (("r0", "J0"), ("r1", "J1"))
         L.append(ind + "cx<T> J0[NFLOW], J1[NFLOW];")
         L.append(ind + "for (int f = 0; f < NFLOW; ++f) { J0[f] = czero<T>(); J1[f] = czero<T>(); }")

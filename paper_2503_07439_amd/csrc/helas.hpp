@@ -135,6 +135,15 @@ template <class T> NLO_HD w4<T> wf_eps(const vec_data<T>& d, bool plus, bool out
   T s = outgoing ? T(1) : T(-1);
   return {{cx<T>{T(0), T(0)}, cx<T>{l * d.e1x, s * d.e2x}, cx<T>{l * d.e1y, s * d.e2y}, cx<T>{l * d.e1z, T(0)}}};
 }
+// Real linear polarisations eps1 (k = 0) and eps2 (k = 1).  The helicity
+// states are a unitary combination of them, so the sum of |A|^2 over the two
+// helicities of a leg equals the sum over eps1 and eps2; the amplitudes with
+// a real vector are cheaper.
+template <class T> NLO_HD w4<T> wf_lin(const vec_data<T>& d, int k) {
+  const T r2 = T(1.4142135623730951);
+  return k == 0 ? w4<T>{{cx<T>{T(0), T(0)}, cx<T>{r2 * d.e1x, T(0)}, cx<T>{r2 * d.e1y, T(0)}, cx<T>{r2 * d.e1z, T(0)}}}
+                : w4<T>{{cx<T>{T(0), T(0)}, cx<T>{r2 * d.e2x, T(0)}, cx<T>{r2 * d.e2y, T(0)}, cx<T>{T(0), T(0)}}};
+}
 
 // ---------------------------------------------------------------------------
 // vertices and propagators

@@ -35,10 +35,8 @@ UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-O1",)}
 # g g -> t tbar g).  The FKS units keep IEEE semantics: they test the
 # subtracted weight for finiteness.  The FP16/BF16 units also keep them (the
 # compiler's instruction selection fails on their packed conversions).
-# The FP64 g g -> t tbar g g unit is left out: its spill code gets slower with
-# them (136 against 125 ms per 2^20 events, measured).
 ME2_FAST_VARIANTS = ("0", "1", "2")
-ME2_FAST_EXCLUDE = ("tu_gg_ttgg_0.hip",)
+ME2_FAST_EXCLUDE = ()
 ME2_FAST_FLAGS = ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros")
 
 

@@ -787,23 +787,36 @@ def helicity_order(p):
 # diagram picks up the same overall phase.  The flow vector of the reversed
 # helicity set is thus a phase times J^*, and with a real colour matrix
 # J^+ C J is unchanged: |M_h|^2 = |M_-h|^2.  The nested helicity sum therefore
-# runs over the half in which the outermost leg has bit 0 and is doubled by
-# the caller (HEL_SYM).  An axial coupling or a width would break this.
+# runs over the half in which one leg (a fermion where there is one) has bit 0
+# and is doubled by the caller (HEL_SYM).  An axial coupling or a width would
+# break this.
 HEL_SYMMETRY = True
 
 # External vector legs are summed over their two real linear polarisations
 # instead of their two helicities: for each leg the helicity states are a
 # unitary combination of them, so the summed |A|^2 is the same, and currents
 # and amplitudes with a real vector need fewer multiplications.  The one
-# exception is the outermost leg while the helicity-reversal halving holds it
-# at one helicity: that argument needs a helicity state there (the sum over
-# all the other legs does not depend on their basis).
+# exception is a vector leg that the helicity-reversal halving holds at one
+# helicity (only when the process has no fermion): that argument needs a
+# helicity state there (the sum over all the other legs does not depend on
+# their basis).
 LINEAR_POLARISATIONS = True
 
 
-def _linear(p, leg, level):
-    return (LINEAR_POLARISATIONS and p.itype[leg] in ("g", "a")
-            and not (level == 0 and HEL_SYMMETRY))
+def _fixed_leg(p, order):
+    """The leg the helicity-reversal halving holds at one helicity: a fermion
+    if the loops have one (then every vector leg can take linear
+    polarisations), else the outermost leg."""
+    if not HEL_SYMMETRY:
+        return -1
+    for k in order[:-1]:
+        if p.itype[k] not in ("g", "a"):
+            return k
+    return order[0]
+
+
+def _linear(p, leg, fixed):
+    return LINEAR_POLARISATIONS and p.itype[leg] in ("g", "a") and leg != fixed
 
 # processes whose sub-currents one level above the deepest loop are also
 # evaluated lazily inside it (more flops, far fewer live registers)
@@ -865,6 +878,7 @@ def emit_nested(p, mslot, dslot, N, nin):
     order = helicity_order(p)
     lev = {k: i for i, k in enumerate(order)}
     root = order[-1]
+    fixed = _fixed_leg(p, order)                    # held at one helicity (HEL_SYM)
     deep = N - 2                                    # deepest emitted loop
     jit_from = deep - JIT_EXTRA_LEVELS.get(p.name, 0)
     L = ["  // helicity loops, outermost first: legs %s (root leg %d folded into the amplitudes)"
@@ -881,7 +895,7 @@ def emit_nested(p, mslot, dslot, N, nin):
     ind = "    "
     for level in range(deep + 1):
         # outermost leg: one helicity only when the sum uses |M_h|^2 = |M_-h|^2
-        trips = 1 if (level == 0 and HEL_SYMMETRY) else 2
+        trips = 1 if order[level] == fixed else 2
         L.append(ind + "#pragma unroll 1")
         L.append(ind + "for (int b%d = 0; b%d < %d; ++b%d) {" % (level, level, trips, level))
         ind += "  "
@@ -890,7 +904,7 @@ def emit_nested(p, mslot, dslot, N, nin):
         for n in nodes:
             if level_of[id(n)] != level or (level >= jit_from and n.kind != "ext"):
                 continue
-            if n.kind == "ext" and _linear(p, min(n.legs), level):
+            if n.kind == "ext" and _linear(p, min(n.legs), fixed):
                 L.append(ind + "const w4<T> v%d = wf_lin(s.x%d, b%d);" % (n.id, min(n.legs), level))
             elif n.kind == "ext":
                 L.append(ind + "const w4<T> v%d = %s;" % (n.id, _ext_call(p, min(n.legs), "b%d" % level, nin)))
@@ -909,7 +923,7 @@ def emit_nested(p, mslot, dslot, N, nin):
         L.append(ind + "cx<T> J0[NFLOW];")
         L.append(ind + "for (int f = 0; f < NFLOW; ++f) J0[f] = czero<T>();")
     else:
-        if _linear(p, root, N - 1):
+        if _linear(p, root, fixed):
             # a vector root takes its two real linear polarisations in place
             # of its helicities (same sum of |A|^2, cheaper amplitudes)
             L.append(ind + "const w4<T> r0 = wf_lin(s.x%d, 0);" % root)

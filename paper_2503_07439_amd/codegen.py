@@ -821,6 +821,9 @@ def _linear(p, leg, fixed):
 # processes whose sub-currents one level above the deepest loop are also
 # evaluated lazily inside it (more flops, far fewer live registers)
 JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
+# the same for the FP64 instantiation where it differs (measured: FP64
+# g g -> t tbar g g is faster without the extra lazy level, FP32 with it)
+JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 0}
 # stop the compiler from hoisting those lazily emitted sub-currents back out
 KEEP_LAZY_IN_LOOP = True
 
@@ -868,7 +871,7 @@ def _amp_call(a, ch, mslot, rootv):
     return "%s(%s, %s, %s, %s)" % (a.kind, ch[0], ch[1], ch[2], ch[3])
 
 
-def emit_nested(p, mslot, dslot, N, nin):
+def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
     """helicity_sum: nested loops over the helicities of all legs but the root
     (the leg taking part in no sub-current).  A sub-current is evaluated at the
     loop level of its innermost leg and reused by all inner iterations; in the
@@ -880,10 +883,12 @@ def emit_nested(p, mslot, dslot, N, nin):
     root = order[-1]
     fixed = _fixed_leg(p, order)                    # held at one helicity (HEL_SYM)
     deep = N - 2                                    # deepest emitted loop
-    jit_from = deep - JIT_EXTRA_LEVELS.get(p.name, 0)
+    if jit_extra is None:
+        jit_extra = JIT_EXTRA_LEVELS.get(p.name, 0)
+    jit_from = deep - jit_extra
     L = ["  // helicity loops, outermost first: legs %s (root leg %d folded into the amplitudes)"
          % (", ".join(str(k) for k in order[:-1]), root),
-         "  template <class T, class F> NLO_HD static void helicity_sum(const Pre<T>& s, T mt, F&& body) {"]
+         "  template <class T, class F> NLO_HD static void %s(const Pre<T>& s, T mt, F&& body) {" % fname]
     checks = {}
     for r, c in _massless_lines(p):
         out_r, out_c = r >= nin, c >= nin
@@ -1145,7 +1150,22 @@ def emit_process(p):
             for line in _acc_code("J[%d]" % f, c, av):
                 L.append("    " + line)
     L.append("  }")
-    L.extend(emit_nested(p, mslot, dslot, N, nin))
+    j_def = JIT_EXTRA_LEVELS.get(p.name, 0)
+    j_f64 = JIT_EXTRA_LEVELS_FP64.get(p.name, j_def)
+    if j_f64 == j_def:
+        L.extend(emit_nested(p, mslot, dslot, N, nin))
+    else:
+        # two schedules: the FP64 instantiation takes its own lazy depth; the
+        # others run the default schedule in helicity_sum itself
+        L.extend(emit_nested(p, mslot, dslot, N, nin, j_f64, "helicity_sum_fp64"))
+        main = emit_nested(p, mslot, dslot, N, nin, j_def)
+        L.append(main[0])
+        L.append(main[1])
+        L.append("    if constexpr (std::is_same<T, double>::value) {")
+        L.append("      helicity_sum_fp64(s, mt, body);")
+        L.append("      return;")
+        L.append("    }")
+        L.extend(main[2:])
     # colour sum: J^dagger C J = |L^T Re J|^2 + |L^T Im J|^2, C = L L^T
     Lc = cholesky_lower(p.colour_matrix)
     L.append("  // colour matrix (rows):")
@@ -1246,6 +1266,8 @@ def generate(out_dir):
         p.enumerate()
         p.colour()
         incs = ['#include "../helas.hpp"'] + (['#include "../opaque.hpp"'] if JIT_EXTRA_LEVELS.get(p.name, 0) else [])
+        if JIT_EXTRA_LEVELS_FP64.get(p.name, JIT_EXTRA_LEVELS.get(p.name, 0)) != JIT_EXTRA_LEVELS.get(p.name, 0):
+            incs.append("#include <type_traits>")
         hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once"] + incs +
                          ["namespace nlo {", emit_process(p), "}  // namespace nlo", ""])
         _write_if_changed(os.path.join(out_dir, p.name + ".hpp"), hdr)

@@ -32,19 +32,20 @@ UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-O1",)}
 # for infinite x and -0 for negative x); these kernels test no value for NaN
 # or infinity and never produce one from finite momenta, so they drop those
 # rules and the products fold away (about 11 % fewer instructions for
-# g g -> t tbar g).  The FKS units keep IEEE semantics: they test the
-# subtracted weight for finiteness.  The FP16/BF16 units also keep them (the
-# compiler's instruction selection fails on their packed conversions).
-ME2_FAST_VARIANTS = ("0", "1", "2")
-ME2_FAST_EXCLUDE = ()
-ME2_FAST_FLAGS = ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros")
+# g g -> t tbar g).  The FP16/BF16 units (3, 4) keep infinities: they route an
+# event with an infinite propagator factor to the FP32 pass.  The FKS units
+# keep full IEEE semantics: they test the subtracted weight for finiteness.
+ME2_FAST_FLAGS = {"0": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"),
+                  "1": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"),
+                  "2": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"),
+                  "3": ("-fno-honor-nans", "-fno-signed-zeros"),
+                  "4": ("-fno-honor-nans", "-fno-signed-zeros")}
 
 
 def unit_flags(base):
     flags = list(UNIT_FLAGS.get(base, ()))
-    if base.startswith("tu_") and not base.startswith("tu_fks_") and base not in ME2_FAST_EXCLUDE:
-        if os.path.splitext(base)[0].rsplit("_", 1)[1] in ME2_FAST_VARIANTS:
-            flags += ME2_FAST_FLAGS
+    if base.startswith("tu_") and not base.startswith("tu_fks_"):
+        flags += ME2_FAST_FLAGS.get(os.path.splitext(base)[0].rsplit("_", 1)[1], ())
     return flags
 
 

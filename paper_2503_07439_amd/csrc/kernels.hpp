@@ -219,8 +219,8 @@ __device__ __forceinline__ double scaled_prologue(const double* __restrict__ mom
 #pragma unroll
   for (int k = 0; k < P::NDEN; ++k) dmax = fmaxf(dmax, fabsf(s.den[k]));
   int ex;
-  (void)frexpf(dmax, &ex);            // dmax < 2^ex
-  safe = ex <= HALF_MAX_DEN_LOG2;     // also false for a non-finite denominator
+  (void)frexpf(dmax, &ex);            // dmax < 2^ex (ex = 0 for an infinite dmax)
+  safe = dmax <= 3.0e38f && ex <= HALF_MAX_DEN_LOG2;   // an infinite denominator is not safe
   const int b = safe ? ex + 4 : 0;    // 16x headroom below the largest denominator
   P::scale_legs(s, b);
   f = ldexp(1.0, 2 * b);
@@ -270,7 +270,12 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_pair(int64_t n, int64_t l
   const float* bf = reinterpret_cast<const float*>(&b);
   V2* sv = reinterpret_cast<V2*>(&s);
 #pragma unroll
-  for (int k = 0; k < NW; ++k) sv[k] = __builtin_convertvector(f32x2{af[k], bf[k]}, V2);
+  for (int k = 0; k < NW; ++k) {   // element by element (a packed f32x2 conversion
+    V2 t;                           // trips the compiler's instruction selection
+    t[0] = af[k];                   // when NaNs and signed zeros are not honoured)
+    t[1] = bf[k];
+    sv[k] = t;
+  }
   const V2 mtv = __builtin_convertvector(f32x2{float(mt * r[0]), float(mt * r[1])}, V2);
   double acc0 = 0.0, acc1 = 0.0;
   P::helicity_sum(s, mtv, [&](const cx<V2> (&J)[P::NFLOW]) {

@@ -143,7 +143,10 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
  *   me2[e] = avg_factor * sum_{helicities} sum_{colours} |M(mom_e)|^2
  * for e in [0, n).  mom: device, layout above, npart particles.  me2: device
  * float64 [n].  prec: any nlo_prec.  Per-event values are written only;
- * nothing is accumulated. */
+ * nothing is accumulated.  An event whose momenta put an internal propagator
+ * exactly on shell has no finite |M|^2; its output is then unspecified (the
+ * kernels are compiled without IEEE NaN/infinity guarantees, so it need not
+ * be inf or NaN). */
 nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
                    nlo_prec prec, void* hip_stream);
 

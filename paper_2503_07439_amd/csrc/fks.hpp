@@ -400,26 +400,24 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
   } else {
 
   // Born: |M|^2 and the helicity-summed density Re(J_u J_v^*) of the flow
-  // vector.  Both are unchanged by reversing every helicity (J -> phase J^*),
-  // so the loop takes the first NGOOD / HEL_SYM good helicities, one of each
-  // pair, and the sums are doubled.
+  // vector, over the nested schedule of the |M|^2 kernels.  Both sums are
+  // unchanged by reversing every helicity (J -> phase J^*) and by summing a
+  // leg over any orthonormal basis of its states, so the schedule's half of
+  // the helicities (doubled) and its linear gluon polarisations apply.
   typename BP::template Pre<T> s;
   BP::prologue(kb, s, a.mt);
   double rho[BP::NRHO];
 #pragma unroll
   for (int q = 0; q < BP::NRHO; ++q) rho[q] = 0.0;
   double bsum = 0.0;
-#pragma unroll 1
-  for (int ih = 0; ih < BP::NGOOD / BP::HEL_SYM; ++ih) {
-    cx<T> J[BP::NFLOW];
-    BP::amplitudes(s, BP::good(ih), T(a.mt), J);
+  BP::helicity_sum(s, T(a.mt), [&](const cx<T> (&J)[BP::NFLOW]) {
     bsum += (double)BP::colour_sum(J);
     int q = 0;
 #pragma unroll
     for (int u = 0; u < BP::NFLOW; ++u)
 #pragma unroll
       for (int v = u; v < BP::NFLOW; ++v, ++q) rho[q] += (double)(J[u].r * J[v].r + J[u].i * J[v].i);
-  }
+  });
 #pragma unroll
   for (int q = 0; q < BP::NRHO; ++q) rho[q] *= BP::HEL_SYM;
   double bkl[BP::NCL][BP::NCL];

@@ -22,7 +22,8 @@ HIPCC_FLAGS = [
 
 # Per-unit overrides.  The BF16 variant of g g -> t tbar g g (an accuracy study:
 # gfx950 has no BF16 arithmetic, so every operation is widened to FP32 and
-# rounded back) takes about 14 minutes to optimise at -O3 and 4 at -O1.
+# rounded back) takes about 7.5 minutes to optimise at -O3, far longer than
+# every other unit together.
 UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-O1",)}
 
 # |M|^2 units in FP64, FP32 and with MFMA colour (tu_<process>_<0|1|2>.hip):

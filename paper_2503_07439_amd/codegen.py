@@ -872,12 +872,15 @@ def _amp_call(a, ch, mslot, rootv):
 
 
 def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
-    """helicity_sum: nested loops over the helicities of all legs but the root
-    (the leg taking part in no sub-current).  A sub-current is evaluated at the
-    loop level of its innermost leg and reused by all inner iterations; in the
-    deepest loop the remaining sub-currents are evaluated just before their
-    first use, amplitude by amplitude, and every amplitude is formed for both
-    root helicities at once, giving two flow vectors and two calls of body."""
+    """helicity_sum: nested loops over the states of all legs but the root
+    (the leg taking part in no sub-current): helicities for fermions, linear
+    polarisations for vectors, one helicity for the leg the reversal halving
+    fixes.  A sub-current is evaluated at the loop level of its innermost leg
+    and reused by all inner iterations; in the deepest loop the remaining
+    sub-currents are evaluated just before their first use, amplitude by
+    amplitude, and every amplitude is formed for both root states at once,
+    giving two flow vectors and two calls of body.  jit_extra overrides the
+    number of extra lazy levels, fname the function's name."""
     order = helicity_order(p)
     lev = {k: i for i, k in enumerate(order)}
     root = order[-1]
@@ -899,7 +902,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
     level_of = {id(n): max(lev[k] for k in n.legs) for n in nodes}
     ind = "    "
     for level in range(deep + 1):
-        # outermost leg: one helicity only when the sum uses |M_h|^2 = |M_-h|^2
+        # the leg fixed by the helicity-reversal halving runs one helicity
         trips = 1 if order[level] == fixed else 2
         L.append(ind + "#pragma unroll 1")
         L.append(ind + "for (int b%d = 0; b%d < %d; ++b%d) {" % (level, level, trips, level))
@@ -1038,7 +1041,7 @@ def emit_process(p):
     L.append("  static constexpr int NDIAG = %d, NTERM = %d, NCUR = %d, GS_POW = %d, E_POW = %d;"
              % (p.ndiagrams, len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee))
     L.append("  static constexpr double AVG = %.17g, IDENT = %.17g;" % (p.avg, p.ident))
-    # helicity_sum and the first NGOOD / HEL_SYM entries of good() cover one
+    # helicity_sum (and the first NGOOD / HEL_SYM entries of good()) cover one
     # helicity of each pair (h, -h); callers multiply their sums by HEL_SYM
     L.append("  static constexpr int HEL_SYM = %d;" % (2 if HEL_SYMMETRY else 1))
     L.append("  static constexpr int NMOM = %d, NDEN = %d;" % (len(msets), len(dens)))

@@ -922,6 +922,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
     # sub-currents.  A massless-fermion root whose chirality partner is fixed
     # has one allowed helicity: evaluate only that one.
     root_checks = checks.get(N - 1, [])
+    root_linear = not root_checks and _linear(p, root, fixed)
     if root_checks:
         assert len(root_checks) == 1
         bad0 = root_checks[0].replace("b%d" % (N - 1), "0")
@@ -931,7 +932,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
         L.append(ind + "cx<T> J0[NFLOW];")
         L.append(ind + "for (int f = 0; f < NFLOW; ++f) J0[f] = czero<T>();")
     else:
-        if _linear(p, root, fixed):
+        if root_linear:
             # a vector root takes its two real linear polarisations in place
             # of its helicities (same sum of |A|^2, cheaper amplitudes)
             L.append(ind + "const w4<T> r0 = wf_lin(s.x%d, 0);" % root)
@@ -984,9 +985,16 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
             for n in need(c):
                 L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot, lazy_den)))
         ch = ["v%d" % c.id for c in a.children]
+        kcur = None
+        if root_linear and a.kind == "ffv_amp":
+            # the fermion current once, contracted with both (real) root
+            # vectors: cheaper than two full amplitudes
+            kcur = "k%d" % k
+            L.append(ind + "const w4<T> %s = ffv_cur(%s, %s);" % (kcur, ch[0], ch[1]))
         for rv, J in roots:
             av = "a%d_%s" % (k, rv)
-            L.append(ind + "const cx<T> %s = %s;" % (av, _amp_call(a, ch, mslot, rv)))
+            expr = "mdot(%s, %s)" % (kcur, rv) if kcur else _amp_call(a, ch, mslot, rv)
+            L.append(ind + "const cx<T> %s = %s;" % (av, expr))
             for f in range(nflow):
                 c = _phase_coef(a.coef[f], a.phase, a.qfac)
                 for line in _acc_code("%s[%d]" % (J, f), c, av):

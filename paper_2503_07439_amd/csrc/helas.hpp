@@ -167,13 +167,18 @@ template <class T> NLO_HD w4<T> ffv_col0(const w4<T>& C, const w4<T>& V, const r
 template <class T> NLO_HD w4<T> ffv_row0(const w4<T>& R, const w4<T>& V, const r4<T>& P, T den) {
   return (-den) * row_pslash(row_slash(R, V), P);
 }
-// vector current from a fermion pair: R gamma^nu C / P^2
-template <class T> NLO_HD w4<T> ffv_vec(const w4<T>& R, const w4<T>& C, T den) {
+// fermion-pair current R gamma^nu C (no propagator); R Vslash C equals
+// mdot(ffv_cur(R, C), V)
+template <class T> NLO_HD w4<T> ffv_cur(const w4<T>& R, const w4<T>& C) {
   cx<T> j0 = R.c[0] * C.c[2] + R.c[1] * C.c[3] + R.c[2] * C.c[0] + R.c[3] * C.c[1];
   cx<T> j1 = R.c[0] * C.c[3] + R.c[1] * C.c[2] - R.c[2] * C.c[1] - R.c[3] * C.c[0];
   cx<T> j2 = mul_i(R.c[1] * C.c[2] + R.c[2] * C.c[1] - R.c[0] * C.c[3] - R.c[3] * C.c[0]);
   cx<T> j3 = R.c[0] * C.c[2] - R.c[1] * C.c[3] - R.c[2] * C.c[0] + R.c[3] * C.c[1];
-  return den * w4<T>{{j0, j1, j2, j3}};
+  return w4<T>{{j0, j1, j2, j3}};
+}
+// vector current from a fermion pair: R gamma^nu C / P^2
+template <class T> NLO_HD w4<T> ffv_vec(const w4<T>& R, const w4<T>& C, T den) {
+  return den * ffv_cur(R, C);
 }
 // FFV amplitude R Vslash C
 template <class T> NLO_HD cx<T> ffv_amp(const w4<T>& R, const w4<T>& V, const w4<T>& C) {

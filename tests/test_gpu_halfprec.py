@@ -166,3 +166,26 @@ def test_halfprec_fallback_matches_fp32(gpu, prec):
     f32 = _me2(gpu, proc, sub, "fp32")
     assert np.array_equal(got[far], f32[far])
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_halfprec_infinite_denominator_goes_to_fp32(gpu, prec):
+    """An event whose quark and gluon are exactly collinear has an exactly
+    zero propagator denominator, so its propagator factor is infinite.  It
+    must take the FP32 pass: bit for bit the FP32 path's output for it (that
+    output itself is unspecified, NaN included).  Every other event, including
+    its partner in the packed register pair, keeps its half-width result."""
+    proc = "ee_uug"
+    n = 65
+    mom, _ = events(proc, n, _rs(proc), stream=116)
+    bad = mom.copy()
+    # sqrt(s) = 20: u = g = (5, 3, 4, 0) exactly, (p_u + p_g)^2 = 100 - 36 - 64 = 0
+    k = 7
+    bad[:, :, k] = np.array([[10.0, 0.0, 0.0, 10.0], [10.0, 0.0, 0.0, -10.0],
+                             [5.0, 3.0, 4.0, 0.0], [10.0, -6.0, -8.0, 0.0], [5.0, 3.0, 4.0, 0.0]])
+    ref = _me2(gpu, proc, mom, prec)
+    got = _me2(gpu, proc, bad, prec)
+    f32 = _me2(gpu, proc, bad, "fp32")
+    others = np.arange(n) != k
+    assert np.array_equal(got[others], ref[others])
+    assert np.array_equal(got[k:k + 1], f32[k:k + 1], equal_nan=True)

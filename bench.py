@@ -204,7 +204,7 @@ def cpu_baseline(proc, mom_full, target_s=12.0):
     oracle.build()
     oracle.set_params()
     threads = max(1, min(16, os.cpu_count() or 1))
-    probe = 2048
+    probe = 16384        # large enough that thread start-up does not bias the rate
     t = time.perf_counter()
     oracle.me2(proc, mom_full[:, :, :probe], nthreads=threads)
     rate = probe / (time.perf_counter() - t)

@@ -1088,9 +1088,7 @@ def emit_process(p):
         for (S2, mass), j in dslot.items():
             if S2 == S:
                 mterm = " - mt * mt" if mass == "MT" else ""
-                L.append("      s.den[%d] = T(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]%s)); }"
-                         % (j, mterm) if False else
-                         "      s.den[%d] = T(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]%s));"
+                L.append("      s.den[%d] = T(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]%s));"
                          % (j, mterm))
         L.append("    }")
     L.append("  }")

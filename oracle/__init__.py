@@ -14,41 +14,70 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "oracle.cpp")]
+_SRC = os.path.join(_HERE, "oracle.cpp")
+# "double": IEEE double.  "quad": IEEE binary128 (__float128), the reference
+# for the subtracted weight near the soft and collinear limits, where the
+# weight keeps about log10(1/(xi (1-y))) fewer digits than the arithmetic.
+_SO = {"double": os.path.join(_HERE, "liboracle.so"), "quad": os.path.join(_HERE, "liboracle_q.so")}
+_FLAGS = {"double": [], "quad": ["-DORACLE_QUAD"]}
+_LIBS = {"double": [], "quad": ["-lquadmath"]}
 
 PROCS = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
 
-def build(verbose=False):
-    """Compile the oracle (plain g++, no fast-math)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", _SO] + _SRC
-    if verbose:
-        print(" ".join(cmd))
+def build(verbose=False, kinds=("double", "quad")):
+    """Compile the oracle (plain g++ -O3, no fast-math) in double and in
+    binary128; the two builds run concurrently."""
+    procs = []
+    for k in kinds:
+        tmp = _SO[k] + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread"] + _FLAGS[k] + ["-o", tmp, _SRC] + _LIBS[k]
+        if verbose:
+            print(" ".join(cmd))
+        procs.append((subprocess.Popen(cmd), tmp, _SO[k]))
+    for p, tmp, so in procs:
+        if p.wait() != 0:
+            raise RuntimeError("oracle build failed")
+        os.replace(tmp, so)
+
+
+def build_native(path):
+    """The double build for this host's instruction set (-O3 -march=native,
+    no fast-math), for timing the oracle as a CPU baseline."""
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", path, _SRC]
     subprocess.run(cmd, check=True)
+    return path
 
 
-_lib = None
+_lib = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_SO):
-            build()
-        L = ctypes.CDLL(_SO)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int)
-        L.orc_me2.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int]
-        L.orc_me2_hel.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int]
-        L.orc_me2_brute.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_int, dp, ctypes.c_int]
-        L.orc_flows.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp, dp]
-        L.orc_colour_matrix.argtypes = [ctypes.c_int, dp]
-        L.orc_wavefunction.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_set_params.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
-        L.orc_proc_info.argtypes = [ctypes.c_int, ip, ip, dp, dp, ip, ip]
-        _lib = L
-    return _lib
+def _declare(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.orc_me2.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int]
+    L.orc_me2_hel.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int]
+    L.orc_me2_brute.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_int, dp, ctypes.c_int]
+    L.orc_flows.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp, dp]
+    L.orc_colour_matrix.argtypes = [ctypes.c_int, dp]
+    L.orc_wavefunction.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_set_params.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.orc_proc_info.argtypes = [ctypes.c_int, ip, ip, dp, dp, ip, ip]
+    return L
+
+
+_params = None
+
+
+def lib(kind="double"):
+    """The loaded oracle library of the given arithmetic ("double", "quad")."""
+    if kind not in _lib:
+        if not os.path.exists(_SO[kind]):
+            build(kinds=(kind,))
+        _lib[kind] = _declare(ctypes.CDLL(_SO[kind]))
+        if _params is not None:
+            _lib[kind].orc_set_params(*_params)
+    return _lib[kind]
 
 
 def _dp(a):
@@ -60,7 +89,10 @@ def pid(proc):
 
 
 def set_params(alpha=1.0 / 132.507, alpha_s=0.118, m_top=173.0):
-    lib().orc_set_params(alpha, alpha_s, m_top)
+    global _params
+    _params = (alpha, alpha_s, m_top)
+    for L in _lib.values():
+        L.orc_set_params(alpha, alpha_s, m_top)
 
 
 def proc_info(proc):
@@ -72,12 +104,12 @@ def proc_info(proc):
     return dict(npart=a.value, ncolour=b.value, avg=c.value, ident=d.value, a_pow=e.value, as_pow=f.value)
 
 
-def me2(proc, mom, nthreads=8):
+def me2(proc, mom, nthreads=8, kind="double"):
     """mom: [npart, 4, n] float64 (SoA).  Returns |M|^2 [n]."""
     mom = np.ascontiguousarray(mom, dtype=np.float64)
     n = mom.shape[2]
     out = np.empty(n)
-    rc = lib().orc_me2(pid(proc), n, n, _dp(mom), _dp(out), nthreads)
+    rc = lib(kind).orc_me2(pid(proc), n, n, _dp(mom), _dp(out), nthreads)
     assert rc == 0
     return out
 
@@ -132,10 +164,11 @@ def wavefunction(proc, p_aos, leg, lam):
 FKS_FIELDS = ["xi", "y", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "W", "me2_R", "B", "S"]
 
 
-def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=8, want_real=False):
+def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=8, want_real=False, kind="double"):
     """FKS-subtracted real emission for pair (i, j) (j = -1: initial state).
-    Returns dict of arrays (FKS_FIELDS) and optionally the real momenta."""
-    L = lib()
+    Returns dict of arrays (FKS_FIELDS) and optionally the real momenta.
+    kind="quad" evaluates every step in binary128 (outputs rounded to double)."""
+    L = lib(kind)
     f = L.orc_fks
     f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.POINTER(ctypes.c_double)] * 6 + [ctypes.c_int]
     born_mom = np.ascontiguousarray(born_mom, dtype=np.float64)

@@ -1,7 +1,9 @@
-// FP64 CPU ORACLE for tree-level squared matrix elements -- TEST INFRASTRUCTURE.
+// CPU ORACLE for tree-level squared matrix elements -- TEST INFRASTRUCTURE.
 //
 // Only the tests, the smoke check and the benchmark's CPU-baseline leg may
-// load this library.  It shares no code with the GPU path.
+// load this library.  It shares no code with the GPU path.  It is built twice
+// from this file: in IEEE double, and (-DORACLE_QUAD) in IEEE binary128, the
+// reference for the subtracted weight near the soft and collinear limits.
 //
 // What it computes (the paper's Born and real-emission equations: a tree
 // amplitude is the sum of Feynman diagrams and the cross section follows
@@ -29,10 +31,12 @@
 // g f^{abc}[g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu]
 // (momenta incoming), four-gluon -i g^2 [f^{abe}f^{cde}(...) + ...],
 // propagators i(pslash+m)/(p^2-m^2) and -i g_{mu nu}/p^2.  T^a = lambda^a/2.
+// External particles are on shell: a propagator denominator p^2 - m^2 is
+// formed from the pairwise invariants 2 q_a.q_b and the nominal masses of the
+// legs on one side of the line (den_of).
 // Gamma_top = 0.  Helicity index h: bit (npart-1-k) of h set <=> leg k has
 // helicity +1.
 #include <cmath>
-#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <functional>
@@ -43,27 +47,82 @@
 #include <array>
 #include <algorithm>
 
-using cd = std::complex<double>;
+// ----------------------------------------------------------------------------
+// scalar type
+// ----------------------------------------------------------------------------
+// The default build computes in IEEE double.  Built with -DORACLE_QUAD it
+// computes in IEEE binary128 (__float128, libquadmath).  Near the soft and
+// collinear limits the subtracted real emission is a difference of terms
+// that each grow like 1/(xi (1-y)), so the weight keeps about
+// log10(1/(xi (1-y))) fewer digits than the arithmetic carries; the paper
+// names quadruple precision as the remedy for such losses in higher-order
+// evaluations, and the binary128 build is the reference for that weight.
+// Inputs and outputs are double in both builds.
+#ifdef ORACLE_QUAD
+#include <quadmath.h>
+typedef __float128 Real;
+static inline Real Sqrt(Real x) { return sqrtq(x); }
+static inline Real Sin(Real x) { return sinq(x); }
+static inline Real Cos(Real x) { return cosq(x); }
+static inline Real Fabs(Real x) { return fabsq(x); }
+static inline Real Pow(Real x, Real y) { return powq(x, y); }
+static inline Real Log(Real x) { return logq(x); }
+static const Real PI = 4 * atanq(Real(1));
+#else
+typedef double Real;
+static inline Real Sqrt(Real x) { return std::sqrt(x); }
+static inline Real Sin(Real x) { return std::sin(x); }
+static inline Real Cos(Real x) { return std::cos(x); }
+static inline Real Fabs(Real x) { return std::fabs(x); }
+static inline Real Pow(Real x, Real y) { return std::pow(x, y); }
+static inline Real Log(Real x) { return std::log(x); }
+static const Real PI = M_PI;
+#endif
+
+// complex numbers over Real: the plain schoolbook operations
+struct cd {
+  Real re, im;
+  cd(Real r = 0, Real i = 0) : re(r), im(i) {}
+  Real real() const { return re; }
+  Real imag() const { return im; }
+  cd& operator+=(const cd& b) { re += b.re; im += b.im; return *this; }
+  cd& operator-=(const cd& b) { re -= b.re; im -= b.im; return *this; }
+};
+static inline cd operator+(const cd& a, const cd& b) { return cd(a.re + b.re, a.im + b.im); }
+static inline cd operator-(const cd& a, const cd& b) { return cd(a.re - b.re, a.im - b.im); }
+static inline cd operator-(const cd& a) { return cd(-a.re, -a.im); }
+static inline cd operator*(const cd& a, const cd& b) { return cd(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+static inline cd operator*(Real a, const cd& b) { return cd(a * b.re, a * b.im); }
+static inline cd operator*(const cd& a, Real b) { return cd(a.re * b, a.im * b); }
+static inline cd operator/(const cd& a, Real b) { return cd(a.re / b, a.im / b); }
+static inline cd operator/(const cd& a, const cd& b) {
+  const Real d = b.re * b.re + b.im * b.im;
+  return cd((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+static inline bool operator==(const cd& a, const cd& b) { return a.re == b.re && a.im == b.im; }
+static inline bool operator!=(const cd& a, const cd& b) { return !(a == b); }
+static inline cd conj(const cd& a) { return cd(a.re, -a.im); }
+static inline Real norm(const cd& a) { return a.re * a.re + a.im * a.im; }
 static const cd I(0.0, 1.0);
 
 // ----------------------------------------------------------------------------
 // parameters
 // ----------------------------------------------------------------------------
-static double g_alpha = 1.0 / 132.507;
-static double g_alpha_s = 0.118;
-static double g_mt = 173.0;
+static Real g_alpha = 1.0 / 132.507;
+static Real g_alpha_s = 0.118;
+static Real g_mt = 173.0;
 
-static double e_qed() { return std::sqrt(4.0 * M_PI * g_alpha); }
-static double g_qcd() { return std::sqrt(4.0 * M_PI * g_alpha_s); }
+static Real e_qed() { return Sqrt(4.0 * PI * g_alpha); }
+static Real g_qcd() { return Sqrt(4.0 * PI * g_alpha_s); }
 
 // ----------------------------------------------------------------------------
 // Lorentz algebra
 // ----------------------------------------------------------------------------
-struct V4 { double v[4]; };                    // real four-vector
+struct V4 { Real v[4]; };                    // real four-vector
 typedef std::array<cd, 4> C4;                   // complex four-vector (upper index) or spinor
 typedef std::array<std::array<cd, 4>, 4> M4;    // 4x4 complex matrix
 
-static double dot(const V4& a, const V4& b) {
+static Real dot(const V4& a, const V4& b) {
   return a.v[0] * b.v[0] - a.v[1] * b.v[1] - a.v[2] * b.v[2] - a.v[3] * b.v[3];
 }
 static cd cdot(const C4& a, const C4& b) {      // Minkowski product, no conjugation
@@ -141,10 +200,11 @@ static C4 current(const C4& row, const C4& col) {
   for (int mu = 0; mu < 4; ++mu) r[mu] = rc(row, mv(GAMMA[mu], col));
   return r;
 }
-// fermion propagator i(pslash + m)/(p^2 - m^2), p along the fermion-number arrow
-static M4 fprop(const V4& p, double m) {
+// fermion propagator i(pslash + m)/(p^2 - m^2), p along the fermion-number
+// arrow; d = p^2 - m^2 from the pairwise invariants (den_of below)
+static M4 fprop(const V4& p, Real m, Real d) {
   M4 r = slash(c4(p));
-  cd den = I / (dot(p, p) - m * m);
+  cd den = I / d;
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) r[i][j] = (r[i][j] + (i == j ? cd(m) : cd(0))) * den;
   return r;
@@ -155,66 +215,66 @@ static M4 fprop(const V4& p, double m) {
 // ----------------------------------------------------------------------------
 // two-component helicity eigenstates of sigma.phat
 static void chi(const V4& p, int lam, cd out[2]) {
-  double px = p.v[1], py = p.v[2], pz = p.v[3];
-  double pa = std::sqrt(px * px + py * py + pz * pz);
-  double pt2 = px * px + py * py;
-  double pp = (pz >= 0) ? pa + pz : pt2 / (pa - pz);   // |p| + pz without cancellation
+  Real px = p.v[1], py = p.v[2], pz = p.v[3];
+  Real pa = Sqrt(px * px + py * py + pz * pz);
+  Real pt2 = px * px + py * py;
+  Real pp = (pz >= 0) ? pa + pz : pt2 / (pa - pz);   // |p| + pz without cancellation
   if (pp <= 0.0) {                                      // p along -z
     if (lam > 0) { out[0] = 0; out[1] = 1; }
     else { out[0] = -1; out[1] = 0; }
     return;
   }
-  double nrm = 1.0 / std::sqrt(2.0 * pa * pp);
+  Real nrm = 1.0 / Sqrt(2.0 * pa * pp);
   if (lam > 0) { out[0] = pp * nrm; out[1] = cd(px, py) * nrm; }
   else { out[0] = cd(-px, py) * nrm; out[1] = pp * nrm; }
 }
-static void omegas(const V4& p, double m, double& wp, double& wm) {
-  double pa = std::sqrt(p.v[1] * p.v[1] + p.v[2] * p.v[2] + p.v[3] * p.v[3]);
-  wp = std::sqrt(p.v[0] + pa);                     // sqrt(E + |p|)
+static void omegas(const V4& p, Real m, Real& wp, Real& wm) {
+  Real pa = Sqrt(p.v[1] * p.v[1] + p.v[2] * p.v[2] + p.v[3] * p.v[3]);
+  wp = Sqrt(p.v[0] + pa);                     // sqrt(E + |p|)
   wm = (m == 0.0) ? 0.0 : m / wp;                  // sqrt(E - |p|), exact zero if massless
 }
 // u(p, lam): (sqrt(E - lam|p|) chi_lam, sqrt(E + lam|p|) chi_lam)
-static C4 u_spinor(const V4& p, double m, int lam) {
-  double wp, wm; omegas(p, m, wp, wm);
+static C4 u_spinor(const V4& p, Real m, int lam) {
+  Real wp, wm; omegas(p, m, wp, wm);
   cd x[2]; chi(p, lam, x);
-  double lo = lam > 0 ? wm : wp, hi = lam > 0 ? wp : wm;
+  Real lo = lam > 0 ? wm : wp, hi = lam > 0 ? wp : wm;
   return C4{lo * x[0], lo * x[1], hi * x[0], hi * x[1]};
 }
 // v(p, lam): (-lam sqrt(E + lam|p|) chi_{-lam}, lam sqrt(E - lam|p|) chi_{-lam})
-static C4 v_spinor(const V4& p, double m, int lam) {
-  double wp, wm; omegas(p, m, wp, wm);
+static C4 v_spinor(const V4& p, Real m, int lam) {
+  Real wp, wm; omegas(p, m, wp, wm);
   cd x[2]; chi(p, -lam, x);
-  double a = lam > 0 ? wp : wm, b = lam > 0 ? wm : wp;
-  double l = lam;
+  Real a = lam > 0 ? wp : wm, b = lam > 0 ? wm : wp;
+  Real l = lam;
   return C4{-l * a * x[0], -l * a * x[1], l * b * x[0], l * b * x[1]};
 }
 static C4 bar(const C4& s) {                      // s^dagger gamma^0
   C4 r;
-  for (int j = 0; j < 4; ++j) { cd t = 0; for (int k = 0; k < 4; ++k) t += std::conj(s[k]) * GAMMA[0][k][j]; r[j] = t; }
+  for (int j = 0; j < 4; ++j) { cd t = 0; for (int k = 0; k < 4; ++k) t += conj(s[k]) * GAMMA[0][k][j]; r[j] = t; }
   return r;
 }
 // massless vector polarisation eps(k, lam) = (-lam eps1 - i eps2)/sqrt2
 static C4 polvec(const V4& k, int lam) {
-  double px = k.v[1], py = k.v[2], pz = k.v[3];
-  double pa = std::sqrt(px * px + py * py + pz * pz);
-  double pt = std::sqrt(px * px + py * py);
-  double ct = pz / pa, st = pt / pa;
-  double cp = pt > 0 ? px / pt : 1.0, sp = pt > 0 ? py / pt : 0.0;
-  double e1[4] = {0, ct * cp, ct * sp, -st};
-  double e2[4] = {0, -sp, cp, 0};
+  Real px = k.v[1], py = k.v[2], pz = k.v[3];
+  Real pa = Sqrt(px * px + py * py + pz * pz);
+  Real pt = Sqrt(px * px + py * py);
+  Real ct = pz / pa, st = pt / pa;
+  Real cp = pt > 0 ? px / pt : 1.0, sp = pt > 0 ? py / pt : 0.0;
+  Real e1[4] = {0, ct * cp, ct * sp, -st};
+  Real e2[4] = {0, -sp, cp, 0};
   C4 r;
-  const double s2 = 1.0 / std::sqrt(2.0);
-  for (int mu = 0; mu < 4; ++mu) r[mu] = (-double(lam) * e1[mu] - I * e2[mu]) * s2;
+  const Real s2 = 1.0 / Sqrt(2.0);
+  for (int mu = 0; mu < 4; ++mu) r[mu] = (-Real(lam) * e1[mu] - I * e2[mu]) * s2;
   return r;
 }
-static C4 conjv(const C4& a) { C4 r; for (int i = 0; i < 4; ++i) r[i] = std::conj(a[i]); return r; }
+static C4 conjv(const C4& a) { C4 r; for (int i = 0; i < 4; ++i) r[i] = conj(a[i]); return r; }
 
 // ----------------------------------------------------------------------------
 // SU(3)
 // ----------------------------------------------------------------------------
 typedef std::array<std::array<cd, 3>, 3> M3;
 static M3 TA[8];
-static double FABC[8][8][8];
+static Real FABC[8][8][8];
 static void init_su3() {
   static bool done = false;
   if (done) return;
@@ -227,7 +287,7 @@ static void init_su3() {
   TA[4][0][2] = -0.5 * I; TA[4][2][0] = 0.5 * I;
   TA[5][1][2] = 0.5; TA[5][2][1] = 0.5;
   TA[6][1][2] = -0.5 * I; TA[6][2][1] = 0.5 * I;
-  const double r3 = 1.0 / std::sqrt(3.0);
+  const Real r3 = 1.0 / Sqrt(3.0);
   TA[7][0][0] = 0.5 * r3; TA[7][1][1] = 0.5 * r3; TA[7][2][2] = -r3;
   // f^{abc} = -2 i Tr([T^a, T^b] T^c)
   for (int a = 0; a < 8; ++a)
@@ -238,8 +298,8 @@ static void init_su3() {
           for (int j = 0; j < 3; ++j)
             for (int k = 0; k < 3; ++k)
               tr += (TA[a][i][j] * TA[b][j][k] - TA[b][i][j] * TA[a][j][k]) * TA[c][k][i];
-        double f = (-2.0 * I * tr).real();
-        FABC[a][b][c] = std::fabs(f) < 1e-14 ? 0.0 : f;
+        Real f = (-2.0 * I * tr).real();
+        FABC[a][b][c] = Fabs(f) < 1e-14 ? 0.0 : f;
       }
   done = true;
 }
@@ -253,8 +313,8 @@ struct ProcDef {
   const char* name;
   int npart;
   int ncolour;          // dimension of the amplitude vector returned by flows()
-  double avg;           // initial spin x colour average
-  double ident;         // identical final-state particle factor (exported, not applied)
+  Real avg;           // initial spin x colour average
+  Real ident;         // identical final-state particle factor (exported, not applied)
   int nin;
   // per leg: 'g' gluon, 'q' quark (fermion), 'Q' antiquark, 'l' lepton, 'L' antilepton
   const char* kinds;
@@ -264,15 +324,15 @@ static const ProcDef PROCS[NPROC] = {
     {"ee_mumu", 4, 1, 0.25, 1.0, 2, "lLlL", 2, 0},
     {"ee_uu", 4, 1, 0.25, 1.0, 2, "lLqQ", 2, 0},
     {"ee_uug", 5, 2, 0.25, 1.0, 2, "lLqQg", 2, 1},
-    {"gg_tt", 4, 2, 1.0 / 256.0, 1.0, 2, "ggqQ", 0, 2},
-    {"uu_tt", 4, 1, 1.0 / 36.0, 1.0, 2, "qQqQ", 0, 2},
-    {"gg_ttg", 5, 6, 1.0 / 256.0, 1.0, 2, "ggqQg", 0, 3},
-    {"uu_ttg", 5, 5, 1.0 / 36.0, 1.0, 2, "qQqQg", 0, 3},
-    {"ug_ttu", 5, 5, 1.0 / 96.0, 1.0, 2, "qgqQq", 0, 3},
-    {"gg_ttgg", 6, 24, 1.0 / 256.0, 0.5, 2, "ggqQgg", 0, 4},
+    {"gg_tt", 4, 2, 1 / Real(256), 1.0, 2, "ggqQ", 0, 2},
+    {"uu_tt", 4, 1, 1 / Real(36), 1.0, 2, "qQqQ", 0, 2},
+    {"gg_ttg", 5, 6, 1 / Real(256), 1.0, 2, "ggqQg", 0, 3},
+    {"uu_ttg", 5, 5, 1 / Real(36), 1.0, 2, "qQqQg", 0, 3},
+    {"ug_ttu", 5, 5, 1 / Real(96), 1.0, 2, "qgqQq", 0, 3},
+    {"gg_ttgg", 6, 24, 1 / Real(256), 0.5, 2, "ggqQgg", 0, 4},
 };
 
-static double leg_mass(int proc, int k) {
+static Real leg_mass(int proc, int k) {
   // tops are legs 2,3 of every gg/uu/ug process; everything else massless
   if (proc >= GG_TT && (k == 2 || k == 3)) return g_mt;
   return 0.0;
@@ -285,7 +345,33 @@ struct Ext {
   V4 q[8];        // incoming momenta
   V4 p[8];        // physical momenta
   C4 w[8];        // wavefunction (vector: upper-index components; spinor: row or column)
+  int n;          // number of legs
+  Real m2[8];     // nominal squared mass of each leg
+  Real s2[8][8];  // 2 q_a.q_b
 };
+
+// Denominator P^2 - m^2 of an internal line whose incoming momentum is the sum
+// of the legs in `mask`.  External particles are on shell by definition, so
+// P^2 = sum_a m_a^2 + sum_{a<b} 2 q_a.q_b over the legs of the line; by
+// momentum conservation the complementary set gives the same value, and the
+// smaller set is used (ties: the set holding leg 0).  The near-singular
+// invariants of a soft or collinear emission (2 k_i.k_j, 2 k_i.p_l) are then
+// differences of single pairwise products, never of O(s) squares, and the
+// rounding of the input mass shells does not enter.
+static Real den_of(const Ext& ex, unsigned mask, Real m) {
+  const unsigned full = (1u << ex.n) - 1u;
+  const unsigned comp = full & ~mask;
+  const int a = __builtin_popcount(mask), b = __builtin_popcount(comp);
+  if (b < a || (b == a && (comp & 1u))) mask = comp;
+  Real d = -m * m;
+  for (int x = 0; x < ex.n; ++x)
+    if (mask >> x & 1u) d += ex.m2[x];
+  for (int x = 0; x < ex.n; ++x)
+    if (mask >> x & 1u)
+      for (int y = x + 1; y < ex.n; ++y)
+        if (mask >> y & 1u) d += ex.s2[x][y];
+  return d;
+}
 
 // ----------------------------------------------------------------------------
 // colour-ordered Berends-Giele recursion: one quark line + n gluons
@@ -301,7 +387,7 @@ struct Ext {
 struct BGLine {
   int row, col;                   // leg indices of the row and column ends
   std::vector<int> gl;            // gluon leg indices
-  double m;                       // quark mass
+  Real m;                       // quark mass
 };
 
 static BGLine bg_line(int proc) {
@@ -330,12 +416,13 @@ static C4 bg_current(BGCache& c, const Ext& ex, const BGLine& L, const int* t, i
   if (c.have[k]) { Qout = c.Q[k]; return c.J[k]; }
   C4 J = c4zero();
   V4 Q{{0, 0, 0, 0}};
-  for (int i = 0; i < len; ++i) Q = vadd(Q, ex.q[L.gl[t[i]]]);
+  unsigned mask = 0;
+  for (int i = 0; i < len; ++i) { Q = vadd(Q, ex.q[L.gl[t[i]]]); mask |= 1u << L.gl[t[i]]; }
   if (len == 1) {
     J = ex.w[L.gl[t[0]]];
   } else {
-    const double g = g_qcd();
-    double P2 = dot(Q, Q);
+    const Real g = g_qcd();
+    Real P2 = den_of(ex, mask, 0.0);
     for (int s = 1; s < len; ++s) {           // three-gluon vertex, order (A, B, offshell)
       V4 QA, QB;
       C4 JA = bg_current(c, ex, L, t, s, QA);
@@ -377,7 +464,7 @@ static C4 bg_row(BGCache& c, std::map<int, C4>& rmemo, const Ext& ex, const BGLi
   int k = c.key(t, len);
   auto it = rmemo.find(k);
   if (it != rmemo.end()) return it->second;
-  const double g = g_qcd();
+  const Real g = g_qcd();
   C4 acc = c4zero();
   for (int s = 0; s < len; ++s) {
     C4 R = bg_row(c, rmemo, ex, L, t, s);
@@ -386,8 +473,9 @@ static C4 bg_row(BGCache& c, std::map<int, C4>& rmemo, const Ext& ex, const BGLi
     acc = add(acc, vm(R, slash(scale(I * g, Jd))));
   }
   V4 Q = ex.q[L.row];
-  for (int i = 0; i < len; ++i) Q = vadd(Q, ex.q[L.gl[t[i]]]);
-  C4 r = vm(acc, fprop(vneg(Q), L.m));
+  unsigned mask = 1u << L.row;
+  for (int i = 0; i < len; ++i) { Q = vadd(Q, ex.q[L.gl[t[i]]]); mask |= 1u << L.gl[t[i]]; }
+  C4 r = vm(acc, fprop(vneg(Q), L.m, den_of(ex, mask, L.m)));
   rmemo[k] = r;
   return r;
 }
@@ -404,7 +492,7 @@ static void bg_flows(const BGLine& L, const Ext& ex, cd* out) {
   std::map<int, C4> rmemo;
   std::vector<int> perm(n);
   for (int i = 0; i < n; ++i) perm[i] = i;
-  const double g = g_qcd();
+  const Real g = g_qcd();
   int idx = 0;
   do {
     cd A = 0;
@@ -419,14 +507,14 @@ static void bg_flows(const BGLine& L, const Ext& ex, cd* out) {
 }
 
 // colour matrix of the string basis, by brute force over explicit generators
-static std::vector<double> bg_colour_matrix(int n) {
+static std::vector<Real> bg_colour_matrix(int n) {
   init_su3();
   std::vector<std::vector<int>> perms;
   std::vector<int> perm(n);
   for (int i = 0; i < n; ++i) perm[i] = i;
   do perms.push_back(perm); while (std::next_permutation(perm.begin(), perm.end()));
   int nc = (int)perms.size();
-  std::vector<double> C(nc * nc, 0.0);
+  std::vector<Real> C(nc * nc, 0.0);
   int nadj = 1;
   for (int i = 0; i < n; ++i) nadj *= 8;
   std::vector<M3> S(nc);
@@ -449,7 +537,7 @@ static std::vector<double> bg_colour_matrix(int n) {
     for (int p = 0; p < nc; ++p)
       for (int q = 0; q < nc; ++q) {
         cd v = 0;
-        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) v += std::conj(S[p][i][j]) * S[q][i][j];
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) v += conj(S[p][i][j]) * S[q][i][j];
         C[p * nc + q] += v.real();
       }
   }
@@ -472,14 +560,16 @@ static TwoLine two_line(int proc) {
 
 static void two_line_amps(int proc, const Ext& ex, cd* out) {
   TwoLine T = two_line(proc);
-  const double g = g_qcd();
-  const double m1 = 0.0, m2 = g_mt;
+  const Real g = g_qcd();
+  const Real m1 = 0.0, m2 = g_mt;
   const C4 &r1 = ex.w[T.r1], &c1 = ex.w[T.c1], &r2 = ex.w[T.r2], &c2 = ex.w[T.c2];
   V4 P1 = vadd(ex.q[T.r1], ex.q[T.c1]);
   V4 P2 = vadd(ex.q[T.r2], ex.q[T.c2]);
+  const Real D1 = den_of(ex, (1u << T.r1) | (1u << T.c1), 0.0);
+  const Real D2 = den_of(ex, (1u << T.r2) | (1u << T.c2), 0.0);
   if (T.g < 0) {
     // [r2 (i g gamma^mu) c2] (-i g_{mu nu}/P^2) [r1 (i g gamma^nu) c1]
-    cd a = cdot(current(r2, c2), current(r1, c1)) * (I * g) * (I * g) * (-I / dot(P1, P1));
+    cd a = cdot(current(r2, c2), current(r1, c1)) * (I * g) * (I * g) * (-I / D1);
     out[0] = a;
     return;
   }
@@ -488,26 +578,26 @@ static void two_line_amps(int proc, const Ext& ex, cd* out) {
   M4 ge = slash(scale(I * g, eg));
   // D1: gluon on line 1, row side
   {
-    C4 row = vm(vm(r1, ge), fprop(vneg(vadd(ex.q[T.r1], qg)), m1));
-    cd a = cdot(current(row, c1), current(r2, c2)) * (I * g) * (I * g) * (-I / dot(P2, P2));
+    C4 row = vm(vm(r1, ge), fprop(vneg(vadd(ex.q[T.r1], qg)), m1, den_of(ex, (1u << T.r1) | (1u << T.g), m1)));
+    cd a = cdot(current(row, c1), current(r2, c2)) * (I * g) * (I * g) * (-I / D2);
     out[0] = a;
   }
   // D2: gluon on line 1, column side
   {
-    C4 col = mv(fprop(vadd(ex.q[T.c1], qg), m1), mv(ge, c1));
-    cd a = cdot(current(r1, col), current(r2, c2)) * (I * g) * (I * g) * (-I / dot(P2, P2));
+    C4 col = mv(fprop(vadd(ex.q[T.c1], qg), m1, den_of(ex, (1u << T.c1) | (1u << T.g), m1)), mv(ge, c1));
+    cd a = cdot(current(r1, col), current(r2, c2)) * (I * g) * (I * g) * (-I / D2);
     out[1] = a;
   }
   // D3: gluon on line 2, row side
   {
-    C4 row = vm(vm(r2, ge), fprop(vneg(vadd(ex.q[T.r2], qg)), m2));
-    cd a = cdot(current(row, c2), current(r1, c1)) * (I * g) * (I * g) * (-I / dot(P1, P1));
+    C4 row = vm(vm(r2, ge), fprop(vneg(vadd(ex.q[T.r2], qg)), m2, den_of(ex, (1u << T.r2) | (1u << T.g), m2)));
+    cd a = cdot(current(row, c2), current(r1, c1)) * (I * g) * (I * g) * (-I / D1);
     out[2] = a;
   }
   // D4: gluon on line 2, column side
   {
-    C4 col = mv(fprop(vadd(ex.q[T.c2], qg), m2), mv(ge, c2));
-    cd a = cdot(current(r2, col), current(r1, c1)) * (I * g) * (I * g) * (-I / dot(P1, P1));
+    C4 col = mv(fprop(vadd(ex.q[T.c2], qg), m2, den_of(ex, (1u << T.c2) | (1u << T.g), m2)), mv(ge, c2));
+    cd a = cdot(current(r2, col), current(r1, c1)) * (I * g) * (I * g) * (-I / D1);
     out[3] = a;
   }
   // D5: three-gluon vertex, legs (b, mu, P1), (c, nu, P2), (a, rho, qg)
@@ -515,8 +605,8 @@ static void two_line_amps(int proc, const Ext& ex, cd* out) {
     C4 L1 = scale(I * g, current(r1, c1));
     C4 L2 = scale(I * g, current(r2, c2));
     // propagators -i/P^2 on the two exchanged gluons
-    L1 = scale(-I / dot(P1, P1), L1);
-    L2 = scale(-I / dot(P2, P2), L2);
+    L1 = scale(-I / D1, L1);
+    L2 = scale(-I / D2, L2);
     // V(k,p,q) contracted: (L1.L2)(k-p).eg + (L2.eg)(p-q).L1 + (eg.L1)(q-k).L2
     V4 kmp, pmq, qmk;
     for (int m = 0; m < 4; ++m) {
@@ -560,30 +650,30 @@ static std::vector<cd> two_line_colour_matrix(int proc) {
                 if (FABC[b][cc][a] != 0.0) c[4] += TA[b][i1][j1] * TA[cc][i2][j2] * FABC[b][cc][a];
             }
             for (int d = 0; d < nd; ++d)
-              for (int e = 0; e < nd; ++e) K[d * nd + e] += std::conj(c[d]) * c[e];
+              for (int e = 0; e < nd; ++e) K[d * nd + e] += conj(c[d]) * c[e];
           }
   return K;
 }
 
 // e+e- -> f fbar (g) through one photon
 static void ee_amps(int proc, const Ext& ex, cd* out) {
-  const double e = e_qed(), g = g_qcd();
-  const double Qe = -1.0;
-  const double Qf = (proc == EE_MUMU) ? -1.0 : 2.0 / 3.0;
+  const Real e = e_qed(), g = g_qcd();
+  const Real Qe = -1.0;
+  const Real Qf = (proc == EE_MUMU) ? Real(-1) : Real(2) / 3;
   // lepton current vbar(e+) gamma^nu u(e-): row = leg 1, column = leg 0
   C4 Lc = scale(-I * e * Qe, current(ex.w[1], ex.w[0]));
   V4 P = vadd(ex.q[0], ex.q[1]);
-  C4 Lp = scale(-I / dot(P, P), Lc);                 // photon propagator
+  C4 Lp = scale(-I / den_of(ex, 3u, 0.0), Lc);                 // photon propagator
   if (proc != EE_UUG) {
     out[0] = cdot(scale(-I * e * Qf, current(ex.w[2], ex.w[3])), Lp);
     return;
   }
   M4 ge = slash(scale(I * g, ex.w[4]));
   // D1: gluon on the outgoing quark (row, leg 2)
-  C4 row = vm(vm(ex.w[2], ge), fprop(vneg(vadd(ex.q[2], ex.q[4])), 0.0));
+  C4 row = vm(vm(ex.w[2], ge), fprop(vneg(vadd(ex.q[2], ex.q[4])), 0.0, den_of(ex, (1u << 2) | (1u << 4), 0.0)));
   out[0] = cdot(scale(-I * e * Qf, current(row, ex.w[3])), Lp);
   // D2: gluon on the outgoing antiquark (column, leg 3)
-  C4 col = mv(fprop(vadd(ex.q[3], ex.q[4]), 0.0), mv(ge, ex.w[3]));
+  C4 col = mv(fprop(vadd(ex.q[3], ex.q[4]), 0.0, den_of(ex, (1u << 3) | (1u << 4), 0.0)), mv(ge, ex.w[3]));
   out[1] = cdot(scale(-I * e * Qf, current(ex.w[2], col)), Lp);
 }
 
@@ -596,12 +686,19 @@ static int helicity_of(int h, int npart, int k) { return ((h >> (npart - 1 - k))
 // vector leg's polarisation by override_vec (gauge and spin-correlation tests).
 static void build_ext(int proc, const V4* p, int h, Ext& ex, int override_leg, const C4* override_vec) {
   const ProcDef& P = PROCS[proc];
+  ex.n = P.npart;
+  for (int k = 0; k < P.npart; ++k) {
+    const Real mk = leg_mass(proc, k);
+    ex.m2[k] = mk * mk;
+    ex.q[k] = k < P.nin ? p[k] : vneg(p[k]);
+  }
+  for (int a = 0; a < P.npart; ++a)
+    for (int b = a + 1; b < P.npart; ++b) ex.s2[a][b] = 2.0 * dot(ex.q[a], ex.q[b]);
   for (int k = 0; k < P.npart; ++k) {
     bool in = k < P.nin;
     ex.p[k] = p[k];
-    ex.q[k] = in ? p[k] : vneg(p[k]);
     int lam = helicity_of(h, P.npart, k);
-    double m = leg_mass(proc, k);
+    Real m = leg_mass(proc, k);
     char kind = P.kinds[k];
     if (kind == 'g') {
       C4 e = polvec(p[k], lam);
@@ -633,7 +730,7 @@ static void init_colour() {
     cdat.C.assign(cdat.nc * cdat.nc, 0.0);
     if (p == GG_TT || p == GG_TTG || p == GG_TTGG) {
       int n = (p == GG_TT) ? 2 : (p == GG_TTG ? 3 : 4);
-      std::vector<double> C = bg_colour_matrix(n);
+      std::vector<Real> C = bg_colour_matrix(n);
       for (size_t i = 0; i < C.size(); ++i) cdat.C[i] = C[i];
     } else if (p == UU_TT || p == UU_TTG || p == UG_TTU) {
       cdat.C = two_line_colour_matrix(p);
@@ -657,10 +754,10 @@ static void flows(int proc, const Ext& ex, cd* out) {
   }
 }
 
-static double quad(const ColourData& c, const cd* A) {
+static Real quad(const ColourData& c, const cd* A) {
   cd s = 0;
   for (int i = 0; i < c.nc; ++i)
-    for (int j = 0; j < c.nc; ++j) s += std::conj(A[i]) * c.C[i * c.nc + j] * A[j];
+    for (int j = 0; j < c.nc; ++j) s += conj(A[i]) * c.C[i * c.nc + j] * A[j];
   return s.real();
 }
 
@@ -670,17 +767,17 @@ static void load_event(const double* mom, int64_t ld, int64_t e, int npart, V4* 
 }
 
 // sum over helicities of the colour-summed |M_h|^2, times the average factor
-static double me2_event(int proc, const V4* p, double* per_hel) {
+static Real me2_event(int proc, const V4* p, Real* per_hel) {
   const ProcDef& P = PROCS[proc];
   const ColourData& c = COLOUR[proc];
   int nh = 1 << P.npart;
   std::vector<cd> A(c.nc);
-  double sum = 0;
+  Real sum = 0;
   Ext ex;
   for (int h = 0; h < nh; ++h) {
     build_ext(proc, p, h, ex, -1, nullptr);
     flows(proc, ex, A.data());
-    double v = quad(c, A.data());
+    Real v = quad(c, A.data());
     if (per_hel) per_hel[h] = v * P.avg;
     sum += v;
   }
@@ -726,13 +823,14 @@ static void brute_gluon(Brute& b, int mask) {
   for (auto& x : J) x = c4zero();
   V4 Q{{0, 0, 0, 0}};
   int cnt = 0, only = -1;
+  unsigned legs = 0;
   for (int i = 0; i < b.n; ++i)
-    if (mask >> i & 1) { Q = vadd(Q, ex.q[L.gl[i]]); ++cnt; only = i; }
+    if (mask >> i & 1) { Q = vadd(Q, ex.q[L.gl[i]]); ++cnt; only = i; legs |= 1u << L.gl[i]; }
   if (cnt == 1) {
     J[b.ag[only]] = ex.w[L.gl[only]];
   } else {
-    const double g = g_qcd();
-    double P2 = dot(Q, Q);
+    const Real g = g_qcd();
+    Real P2 = den_of(ex, legs, 0.0);
     // 3-vertex, unordered splits: s1 contains the lowest set bit
     int low = mask & -mask;
     for (int s1 = (mask - 1) & mask; s1 > 0; s1 = (s1 - 1) & mask) {
@@ -753,7 +851,7 @@ static void brute_gluon(Brute& b, int mask) {
           C4 V;
           for (int m = 0; m < 4; ++m) V[m] = ab * kmp.v[m] + B[m] * pa + A[m] * qb;
           for (int c = 0; c < 8; ++c) {
-            double f = FABC[c1][c2][c];
+            Real f = FABC[c1][c2][c];
             if (f == 0.0) continue;
             J[c] = add(J[c], scale((-I / P2) * g * f, V));
           }
@@ -784,7 +882,7 @@ static void brute_gluon(Brute& b, int mask) {
               if (ab == 0.0 && ac == 0.0 && bc == 0.0) continue;
               for (int d = 0; d < 8; ++d) {
                 // legs a=A(mu), b=B(nu), c=C(rho), d=offshell(sigma)
-                double f1 = 0, f2 = 0, f3 = 0;
+                Real f1 = 0, f2 = 0, f3 = 0;
                 for (int e = 0; e < 8; ++e) {
                   f1 += FABC[c1][c2][e] * FABC[c3][d][e];
                   f2 += FABC[c1][c3][e] * FABC[c2][d][e];
@@ -815,7 +913,7 @@ static void brute_row(Brute& b, int mask, int irow) {
   if (mask == 0) {
     R[irow] = ex.w[L.row];
   } else {
-    const double g = g_qcd();
+    const Real g = g_qcd();
     std::array<C4, 3> acc;
     for (auto& x : acc) x = c4zero();
     for (int sg = mask; sg > 0; sg = (sg - 1) & mask) {   // gluons absorbed at the last vertex
@@ -834,15 +932,16 @@ static void brute_row(Brute& b, int mask, int irow) {
       }
     }
     V4 Q = ex.q[L.row];
-    for (int i = 0; i < b.n; ++i) if (mask >> i & 1) Q = vadd(Q, ex.q[L.gl[i]]);
-    M4 S = fprop(vneg(Q), L.m);
+    unsigned legs = 1u << L.row;
+    for (int i = 0; i < b.n; ++i) if (mask >> i & 1) { Q = vadd(Q, ex.q[L.gl[i]]); legs |= 1u << L.gl[i]; }
+    M4 S = fprop(vneg(Q), L.m, den_of(ex, legs, L.m));
     for (int k = 0; k < 3; ++k) R[k] = vm(acc[k], S);
   }
   b.R[mask] = R;
   b.rh[mask] = 1;
 }
 
-static double brute_event_hel(int proc, const V4* p, int h) {
+static Real brute_event_hel(int proc, const V4* p, int h) {
   BGLine L = bg_line(proc);
   Ext ex;
   build_ext(proc, p, h, ex, -1, nullptr);
@@ -850,8 +949,8 @@ static double brute_event_hel(int proc, const V4* p, int h) {
   int full = (1 << n) - 1;
   int ncol = 1;
   for (int i = 0; i < n; ++i) ncol *= 8;
-  const double g = g_qcd();
-  double sum = 0;
+  const Real g = g_qcd();
+  Real sum = 0;
   for (int code = 0; code < ncol; ++code) {
     Brute b;
     b.L = &L; b.ex = &ex; b.n = n;
@@ -878,7 +977,7 @@ static double brute_event_hel(int proc, const V4* p, int h) {
           }
         }
       }
-      for (int k = 0; k < 3; ++k) sum += std::norm(M[k]);
+      for (int k = 0; k < 3; ++k) sum += norm(M[k]);
     }
   }
   return sum;
@@ -927,7 +1026,7 @@ int orc_me2_hel(int proc, int64_t n, int64_t ld, const double* mom, double* out,
   parallel_for(n, nthreads, [&](int64_t e) {
     V4 p[8];
     load_event(mom, ld, e, np, p);
-    std::vector<double> ph(nh);
+    std::vector<Real> ph(nh);
     me2_event(proc, p, ph.data());
     for (int h = 0; h < nh; ++h) out[h * n + e] = ph[h];
   });
@@ -988,7 +1087,7 @@ int orc_me2_brute(int proc, int64_t n, int64_t ld, const double* mom, int h, dou
   parallel_for(n, nthreads, [&](int64_t e) {
     V4 p[8];
     load_event(mom, ld, e, np, p);
-    double s = 0;
+    Real s = 0;
     if (h >= 0) s = brute_event_hel(proc, p, h);
     else for (int hh = 0; hh < nh; ++hh) s += brute_event_hel(proc, p, hh);
     out[e] = s * PROCS[proc].avg;
@@ -1023,7 +1122,7 @@ int orc_me2_brute(int proc, int64_t n, int64_t ld, const double* mom, int h, dou
 // collinear limits the Altarelli-Parisi kernels with the spin-correlated Born
 // for gluon splittings.
 // ============================================================================
-static const double FKS_SQRT_SCAP = 4000.0;
+static const Real FKS_SQRT_SCAP = 4000.0;
 
 // colour charge operators on explicit colour tensors ---------------------------
 // leg kinds: 'r' fundamental (row end), 'c' antifundamental (column end),
@@ -1057,7 +1156,7 @@ static ColTensor apply_charge(const ColTensor& t, int leg, int a) {
 }
 static cd ct_dot(const ColTensor& a, const ColTensor& b) {
   cd s = 0;
-  for (size_t i = 0; i < a.v.size(); ++i) s += std::conj(a.v[i]) * b.v[i];
+  for (size_t i = 0; i < a.v.size(); ++i) s += conj(a.v[i]) * b.v[i];
   return s;
 }
 
@@ -1153,7 +1252,7 @@ static const BornColour& born_colour(int proc) {
 
 // Born |M|^2 and colour-linked Borns B_kl (coloured legs, k,l in bc.legs order),
 // both including the average factor
-static void born_correlations(int proc, const V4* p, double& B, std::vector<double>& Bkl) {
+static void born_correlations(int proc, const V4* p, Real& B, std::vector<Real>& Bkl) {
   const ProcDef& P = PROCS[proc];
   const BornColour& bc = born_colour(proc);
   const ColourData& c = COLOUR[proc];
@@ -1170,7 +1269,7 @@ static void born_correlations(int proc, const V4* p, double& B, std::vector<doub
     for (int q = 0; q < nl * nl; ++q) {
       cd s = 0;
       for (int i = 0; i < nc; ++i)
-        for (int j = 0; j < nc; ++j) s += std::conj(A[i]) * bc.Ckl[q][i * nc + j] * A[j];
+        for (int j = 0; j < nc; ++j) s += conj(A[i]) * bc.Ckl[q][i * nc + j] * A[j];
       Bkl[q] += s.real();
     }
   }
@@ -1180,13 +1279,13 @@ static void born_correlations(int proc, const V4* p, double& B, std::vector<doub
 
 // spin-correlated Born: emitter leg's polarisation replaced by the real unit
 // vector eperp (eperp.eperp = -1), summed over the other helicities
-static double born_spin_correlated(int proc, const V4* p, int leg, const V4& eperp) {
+static Real born_spin_correlated(int proc, const V4* p, int leg, const V4& eperp) {
   const ProcDef& P = PROCS[proc];
   const ColourData& c = COLOUR[proc];
   std::vector<cd> A(c.nc);
   C4 ov = c4(eperp);
   Ext ex;
-  double s = 0;
+  Real s = 0;
   int bit = 1 << (P.npart - 1 - leg);
   for (int h = 0; h < (1 << P.npart); ++h) {
     if (h & bit) continue;
@@ -1228,59 +1327,59 @@ static FksDef fks_def(int real) {
   return d;
 }
 
-static double v3dot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static Real v3dot(const Real* a, const Real* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // polar basis around a unit vector khat: e1 in the (khat, z) plane, e2 = khat x e1
-static void perp_basis(const double* kh, double* e1, double* e2) {
-  double st = std::sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
-  double ct = kh[2];
-  double cp = st > 0 ? kh[0] / st : 1.0, sp = st > 0 ? kh[1] / st : 0.0;
+static void perp_basis(const Real* kh, Real* e1, Real* e2) {
+  Real st = Sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
+  Real ct = kh[2];
+  Real cp = st > 0 ? kh[0] / st : 1.0, sp = st > 0 ? kh[1] / st : 0.0;
   e1[0] = ct * cp; e1[1] = ct * sp; e1[2] = -st;
   e2[0] = -sp; e2[1] = cp; e2[2] = 0.0;
 }
 
 // boost along unit vector u that multiplies the light-cone component E + p.u
 // by rho (and E - p.u by 1/rho); finite also for a massless recoil system
-static V4 boost_along(const V4& p, const double* u, double rho) {
-  double pl = p.v[1] * u[0] + p.v[2] * u[1] + p.v[3] * u[2];
-  double pp = p.v[0] + pl, pm = p.v[0] - pl;
-  double e2 = 0.5 * (rho * pp + pm / rho);
-  double pl2 = 0.5 * (rho * pp - pm / rho);
+static V4 boost_along(const V4& p, const Real* u, Real rho) {
+  Real pl = p.v[1] * u[0] + p.v[2] * u[1] + p.v[3] * u[2];
+  Real pp = p.v[0] + pl, pm = p.v[0] - pl;
+  Real e2 = 0.5 * (rho * pp + pm / rho);
+  Real pl2 = 0.5 * (rho * pp - pm / rho);
   V4 r;
   r.v[0] = e2;
   for (int k = 0; k < 3; ++k) r.v[1 + k] = p.v[1 + k] + (pl2 - pl) * u[k];
   return r;
 }
 // pure boost taking a vector at rest (mass M) to total momentum K
-static V4 boost_to(const V4& p, const V4& K, double M) {
-  double g = K.v[0] / M;
-  double bp = (K.v[1] * p.v[1] + K.v[2] * p.v[2] + K.v[3] * p.v[3]) / M;   // gamma beta . p
+static V4 boost_to(const V4& p, const V4& K, Real M) {
+  Real g = K.v[0] / M;
+  Real bp = (K.v[1] * p.v[1] + K.v[2] * p.v[2] + K.v[3] * p.v[3]) / M;   // gamma beta . p
   V4 r;
   r.v[0] = g * p.v[0] + bp;
-  double f = p.v[0] / M + bp / (K.v[0] + M);
+  Real f = p.v[0] / M + bp / (K.v[0] + M);
   for (int k = 0; k < 3; ++k) r.v[1 + k] = p.v[1 + k] + f * K.v[1 + k];
   return r;
 }
 
 // sector function of pair (i, j) at real momenta k (real frame)
-static double sector_value(const FksDef& d, const V4* k, double sqrt_s, int i, int j) {
+static Real sector_value(const FksDef& d, const V4* k, Real sqrt_s, int i, int j) {
   auto xi = [&](int a) { return 2.0 * k[a].v[0] / sqrt_s; };
   auto ycos = [&](int a, int b) {
-    double pa = std::sqrt(v3dot(k[a].v + 1, k[a].v + 1)), pb = std::sqrt(v3dot(k[b].v + 1, k[b].v + 1));
+    Real pa = Sqrt(v3dot(k[a].v + 1, k[a].v + 1)), pb = Sqrt(v3dot(k[b].v + 1, k[b].v + 1));
     return v3dot(k[a].v + 1, k[b].v + 1) / (pa * pb);
   };
   auto term = [&](int a, int b) {
     if (b < 0) {
-      double pa = std::sqrt(v3dot(k[a].v + 1, k[a].v + 1));
-      double ya = k[a].v[3] / pa;
+      Real pa = Sqrt(v3dot(k[a].v + 1, k[a].v + 1));
+      Real ya = k[a].v[3] / pa;
       return 1.0 / (xi(a) * (1.0 - ya) * (1.0 + ya));
     }
-    double h = (d.gluon[a] && d.gluon[b]) ? xi(b) / (xi(a) + xi(b)) : 1.0;
+    Real h = (d.gluon[a] && d.gluon[b]) ? xi(b) / (xi(a) + xi(b)) : 1.0;
     return h / (xi(a) * xi(b) * (1.0 - ycos(a, b)));
   };
-  double num = 0, den = 0;
+  Real num = 0, den = 0;
   for (const FksPair& q : d.pairs) {
-    double t = term(q.i, q.j);
+    Real t = term(q.i, q.j);
     den += t;
     if (q.i == i && q.j == j) num = t;
   }
@@ -1289,16 +1388,16 @@ static double sector_value(const FksDef& d, const V4* k, double sqrt_s, int i, i
 
 // soft limit of the sector function: direction nh of the soft parton i,
 // Born momenta kb in Born leg order, bmap[real leg] = Born leg (or -1)
-static double sector_soft(const FksDef& d, const V4* kb, const int* bmap, double sqrt_s, const double* nh, int i, int j) {
-  double num = 0, den = 0;
+static Real sector_soft(const FksDef& d, const V4* kb, const int* bmap, Real sqrt_s, const Real* nh, int i, int j) {
+  Real num = 0, den = 0;
   for (const FksPair& q : d.pairs) {
     if (q.i != i) continue;
-    double t;
+    Real t;
     if (q.j < 0) t = 1.0 / ((1.0 - nh[2]) * (1.0 + nh[2]));
     else {
       const V4& pl = kb[bmap[q.j]];
-      double pa = std::sqrt(v3dot(pl.v + 1, pl.v + 1));
-      double y = v3dot(nh, pl.v + 1) / pa;
+      Real pa = Sqrt(v3dot(pl.v + 1, pl.v + 1));
+      Real y = v3dot(nh, pl.v + 1) / pa;
       t = 1.0 / ((2.0 * pl.v[0] / sqrt_s) * (1.0 - y));
     }
     den += t;
@@ -1308,22 +1407,43 @@ static double sector_soft(const FksDef& d, const V4* kb, const int* bmap, double
 }
 
 struct FksOut {
-  double xi, y, gR, gS, gC, gCm, gSC, gSCm, W, me2R, B, S;
+  Real xi, y, gR, gS, gC, gCm, gSC, gSCm, W, me2R, B, S;
 };
 
 // one event of the FKS-subtracted real emission for pair (i, j)
-static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit, double y, double phi, V4* kreal) {
-  const double g2 = 4.0 * M_PI * g_alpha_s;
-  const double CF = 4.0 / 3.0, CA = 3.0;
+static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit, Real y, Real phi, V4* kreal) {
+  // The Born point is on shell and conserves momentum by definition.  An
+  // input rounded to double does neither exactly (at the 1e-16 level), and
+  // the real emission meets its counterterms only as closely as it does: a
+  // term of that size over xi (1-y) would remain in W.  So the final-state
+  // three-momenta are shifted by a common amount to sum to zero, every
+  // energy is put on its mass shell, and the beams (along +-z in the
+  // partonic frame) carry half the total energy each.
+  V4 kb[8];
+  const int nf = d.nborn - 2;
+  Real res[3] = {0, 0, 0};
+  for (int k = 2; k < d.nborn; ++k)
+    for (int m = 0; m < 3; ++m) res[m] += kb_in[k].v[1 + m];
+  Real etot = 0;
+  for (int k = 2; k < d.nborn; ++k) {
+    for (int m = 0; m < 3; ++m) kb[k].v[1 + m] = kb_in[k].v[1 + m] - res[m] / nf;
+    const Real m = leg_mass(d.born, k);
+    kb[k].v[0] = Sqrt(v3dot(kb[k].v + 1, kb[k].v + 1) + m * m);
+    etot += kb[k].v[0];
+  }
+  kb[0] = V4{{etot / 2, 0, 0, etot / 2}};
+  kb[1] = V4{{etot / 2, 0, 0, -etot / 2}};
+  const Real g2 = 4.0 * PI * g_alpha_s;
+  const Real CF = Real(4) / 3, CA = 3;
   FksOut o{};
   o.y = y;
   int nb = d.nborn;
-  double sqs_b = kb[0].v[0] + kb[1].v[0];
-  double sb = sqs_b * sqs_b;
+  Real sqs_b = kb[0].v[0] + kb[1].v[0];
+  Real sb = sqs_b * sqs_b;
   int bmap[8];                           // real leg -> Born leg (-1 for i)
-  double nh[3];                          // soft direction of i
+  Real nh[3];                          // soft direction of i
   V4 eperp{{0, 0, 0, 0}};
-  double s_real, sqs_real;
+  Real s_real, sqs_real;
   if (j >= 0) {
     // ---------------- final-state emitter --------------------------------
     // real legs: Born legs keep their positions; i is the extra leg
@@ -1336,20 +1456,20 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
     const V4& kj = kb[jb];
     V4 q{{sqs_b, 0, 0, 0}};
     V4 krec{{q.v[0] - kj.v[0], -kj.v[1], -kj.v[2], -kj.v[3]}};
-    double mrec2 = dot(krec, krec);
-    double xmax = 1.0 - mrec2 / sb;
-    double xi = xit * xmax;
-    double Ei = 0.5 * xi * sqs_b;
-    double Ej = (sb - mrec2 - 2.0 * sqs_b * Ei) / (2.0 * sqs_b - 2.0 * Ei * (1.0 - y));
-    double kabs = std::sqrt(Ei * Ei + Ej * Ej + 2.0 * Ei * Ej * y);
-    double kjabs = std::sqrt(v3dot(kj.v + 1, kj.v + 1));
-    double kh[3] = {kj.v[1] / kjabs, kj.v[2] / kjabs, kj.v[3] / kjabs};
-    double e1[3], e2[3];
+    Real mrec2 = dot(krec, krec);
+    Real xmax = 1.0 - mrec2 / sb;
+    Real xi = xit * xmax;
+    Real Ei = 0.5 * xi * sqs_b;
+    Real Ej = (sb - mrec2 - 2.0 * sqs_b * Ei) / (2.0 * sqs_b - 2.0 * Ei * (1.0 - y));
+    Real kabs = Sqrt(Ei * Ei + Ej * Ej + 2.0 * Ei * Ej * y);
+    Real kjabs = Sqrt(v3dot(kj.v + 1, kj.v + 1));
+    Real kh[3] = {kj.v[1] / kjabs, kj.v[2] / kjabs, kj.v[3] / kjabs};
+    Real e1[3], e2[3];
     perp_basis(kh, e1, e2);
-    double sy = std::sqrt((1.0 - y) * (1.0 + y));
-    double cti = (Ei + Ej * y) / kabs, sti = Ej * sy / kabs;
-    double cphi = std::cos(phi), sphi = std::sin(phi);
-    double ki_dir[3], ep[3];
+    Real sy = Sqrt((1.0 - y) * (1.0 + y));
+    Real cti = (Ei + Ej * y) / kabs, sti = Ej * sy / kabs;
+    Real cphi = Cos(phi), sphi = Sin(phi);
+    Real ki_dir[3], ep[3];
     for (int m = 0; m < 3; ++m) {
       ep[m] = cphi * e1[m] + sphi * e2[m];
       ki_dir[m] = cti * kh[m] + sti * ep[m];
@@ -1357,10 +1477,10 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
     }
     V4 ki{{Ei, Ei * ki_dir[0], Ei * ki_dir[1], Ei * ki_dir[2]}};
     V4 kjn{{Ej, kabs * kh[0] - ki.v[1], kabs * kh[1] - ki.v[2], kabs * kh[2] - ki.v[3]}};
-    double u[3] = {-kh[0], -kh[1], -kh[2]};
+    Real u[3] = {-kh[0], -kh[1], -kh[2]};
     // recoil system along u = -khat: light-cone component (E + |p|) scaled from
     // (sqrt(s) - Ebar_j + |kbar_j|) to (sqrt(s) - E_i - E_j + |k|)
-    double dyr = (sqs_b - Ei - Ej + kabs) / (sqs_b - kj.v[0] + kjabs);
+    Real dyr = (sqs_b - Ei - Ej + kabs) / (sqs_b - kj.v[0] + kjabs);
     for (int r = 0; r < d.nreal; ++r) {
       if (r == i) kreal[r] = ki;
       else if (r == j) kreal[r] = kjn;
@@ -1375,30 +1495,30 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
     o.S = sector_value(d, kreal, sqs_real, i, j);
     o.gR = xi * xi * (1.0 - y) * o.me2R * o.S;
     // Born correlations at the Born kinematics
-    double B;
-    std::vector<double> Bkl;
+    Real B;
+    std::vector<Real> Bkl;
     born_correlations(d.born, kb, B, Bkl);
     o.B = B;
     const BornColour& bc = born_colour(d.born);
     int nl = (int)bc.legs.size();
     // eikonal: -sum_{kl} (p_k.p_l)/((p_k.n)(p_l.n)) B_kl with n = (1, nh)
     V4 n{{1.0, nh[0], nh[1], nh[2]}};
-    double eik = 0;
+    Real eik = 0;
     for (int a = 0; a < nl; ++a)
       for (int b = 0; b < nl; ++b) {
         const V4 &pa = kb[bc.legs[a]], &pb = kb[bc.legs[b]];
         eik -= dot(pa, pb) / (dot(pa, n) * dot(pb, n)) * Bkl[a * nl + b];
       }
-    double Ss = sector_soft(d, kb, bmap, sqs_b, nh, i, j);
+    Real Ss = sector_soft(d, kb, bmap, sqs_b, nh, i, j);
     o.gS = (1.0 - y) * 4.0 / sb * g2 * eik * Ss;
     // collinear limit y -> 1: E_j^c = Ebar_j - E_i, z = E_j^c / Ebar_j
-    double Ejc = kj.v[0] - Ei;
-    double z = Ejc / kj.v[0];
-    double Sc = (d.gluon[i] && d.gluon[j]) ? z : 1.0;
-    double P;
-    double Cj;
+    Real Ejc = kj.v[0] - Ei;
+    Real z = Ejc / kj.v[0];
+    Real Sc = (d.gluon[i] && d.gluon[j]) ? z : 1.0;
+    Real P;
+    Real Cj;
     if (d.gluon[j]) {
-      double Bp = born_spin_correlated(d.born, kb, jb, eperp);
+      Real Bp = born_spin_correlated(d.born, kb, jb, eperp);
       P = 2.0 * CA * ((z / (1.0 - z) + (1.0 - z) / z) * B + 2.0 * z * (1.0 - z) * Bp);
       Cj = CA;
     } else {
@@ -1414,13 +1534,13 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
       if (r == i) { bmap[r] = -1; continue; }
       bmap[r] = b++;
     }
-    double xmax = 1.0 - sb / (FKS_SQRT_SCAP * FKS_SQRT_SCAP);
-    double xi = xit * xmax;
-    double sr = sb / (1.0 - xi);
-    double sqr = std::sqrt(sr);
-    double Ei = 0.5 * xi * sqr;
-    double sy = std::sqrt((1.0 - y) * (1.0 + y));
-    double cphi = std::cos(phi), sphi = std::sin(phi);
+    Real xmax = 1.0 - sb / (FKS_SQRT_SCAP * FKS_SQRT_SCAP);
+    Real xi = xit * xmax;
+    Real sr = sb / (1.0 - xi);
+    Real sqr = Sqrt(sr);
+    Real Ei = 0.5 * xi * sqr;
+    Real sy = Sqrt((1.0 - y) * (1.0 + y));
+    Real cphi = Cos(phi), sphi = Sin(phi);
     nh[0] = sy * cphi; nh[1] = sy * sphi; nh[2] = y;
     V4 p1{{0.5 * sqr, 0, 0, 0.5 * sqr}}, p2{{0.5 * sqr, 0, 0, -0.5 * sqr}};
     V4 ki{{Ei, Ei * nh[0], Ei * nh[1], Ei * nh[2]}};
@@ -1449,13 +1569,13 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
       // colours, so the unpolarised splitting functions apply as they stand
       // (they are defined for averaged initial states); a ratio of spin x
       // colour states n_q/n_g belongs only to raw, unaveraged sums.
-      const double TR = 0.5;
-      double x = 1.0 - xi;
-      double Bplus = me2_event(d.born, kb, nullptr);
-      double Bperp = born_spin_correlated(d.born, kb, 0, eperp);
-      double Bminus = me2_event(d.bornm, kb, nullptr);
-      double Pp = CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
-      double Pm = TR * (x * x + (1.0 - x) * (1.0 - x)) * Bminus;
+      const Real TR = 0.5;
+      Real x = 1.0 - xi;
+      Real Bplus = me2_event(d.born, kb, nullptr);
+      Real Bperp = born_spin_correlated(d.born, kb, 0, eperp);
+      Real Bminus = me2_event(d.bornm, kb, nullptr);
+      Real Pp = CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
+      Real Pm = TR * (x * x + (1.0 - x) * (1.0 - x)) * Bminus;
       o.B = Bplus;
       o.gS = 0.0;
       o.gC = 8.0 * xi * g2 / sb * Pp;
@@ -1465,29 +1585,29 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb, double xit,
       o.W = (o.gR - 0.5 * (1.0 + y) * o.gC - 0.5 * (1.0 - y) * o.gCm) / (xi * (1.0 - y) * (1.0 + y));
       return o;
     }
-    double B;
-    std::vector<double> Bkl;
+    Real B;
+    std::vector<Real> Bkl;
     born_correlations(d.born, kb, B, Bkl);
     o.B = B;
     const BornColour& bc = born_colour(d.born);
     int nl = (int)bc.legs.size();
     V4 n{{1.0, nh[0], nh[1], nh[2]}};
-    double eik = 0;
+    Real eik = 0;
     for (int a = 0; a < nl; ++a)
       for (int b = 0; b < nl; ++b) {
         const V4 &pa = kb[bc.legs[a]], &pb = kb[bc.legs[b]];
         eik -= dot(pa, pb) / (dot(pa, n) * dot(pb, n)) * Bkl[a * nl + b];
       }
-    double Ss = sector_soft(d, kb, bmap, sqs_b, nh, i, -1);
+    Real Ss = sector_soft(d, kb, bmap, sqs_b, nh, i, -1);
     o.gS = (1.0 - y) * (1.0 + y) * 4.0 / sb * g2 * eik * Ss;
     // collinear limits y -> +1 (beam 1) and y -> -1 (beam 2), x = 1 - xi
-    double x = 1.0 - xi;
-    double gc[2], gsc[2];
+    Real x = 1.0 - xi;
+    Real gc[2], gsc[2];
     for (int side = 0; side < 2; ++side) {
       int beam = side;                           // Born leg of the incoming parton
-      double P, Ca;
+      Real P, Ca;
       if (d.gluon[beam]) {
-        double Bp = born_spin_correlated(d.born, kb, beam, eperp);
+        Real Bp = born_spin_correlated(d.born, kb, beam, eperp);
         P = 2.0 * CA * ((x / (1.0 - x) + x * (1.0 - x)) * B + 2.0 * (1.0 - x) / x * Bp);
         Ca = CA;
       } else {
@@ -1546,8 +1666,8 @@ int orc_born_correlations(int proc, int64_t n, const double* mom, double* B, dou
   parallel_for(n, 8, [&](int64_t e) {
     V4 p[8];
     load_event(mom, n, e, PROCS[proc].npart, p);
-    double b;
-    std::vector<double> kl;
+    Real b;
+    std::vector<Real> kl;
     born_correlations(proc, p, b, kl);
     B[e] = b;
     for (int q = 0; q < nl * nl; ++q) Bkl[e * nl * nl + q] = kl[q];
@@ -1567,7 +1687,7 @@ int orc_sector_functions(int real_proc, int64_t n, const double* real_mom, doubl
   for (int64_t e = 0; e < n; ++e) {
     V4 k[8];
     load_event(real_mom, n, e, d.nreal, k);
-    double sq = k[0].v[0] + k[1].v[0];
+    Real sq = k[0].v[0] + k[1].v[0];
     for (size_t q = 0; q < d.pairs.size(); ++q) out[e * d.pairs.size() + q] = sector_value(d, k, sq, d.pairs[q].i, d.pairs[q].j);
   }
   return 0;
@@ -1603,71 +1723,71 @@ extern "C" {
 int orc_rambo(int nfin, const double* masses, int64_t n, const double* sqrt_s, const double* u, double* p_out,
               double* w_out) {
   if (nfin < 2 || nfin > 8) return 1;
-  double vol1 = std::pow(2.0 * M_PI, 4 - 3 * nfin) * std::pow(M_PI / 2.0, nfin - 1);
+  Real vol1 = Pow(2.0 * PI, 4 - 3 * nfin) * Pow(PI / 2.0, nfin - 1);
   for (int k = 2; k <= nfin - 1; ++k) vol1 /= k;     // 1/(n-1)!
   for (int k = 2; k <= nfin - 2; ++k) vol1 /= k;     // 1/(n-2)!
   bool massive = false;
-  double msum = 0.0;
+  Real msum = 0.0;
   for (int i = 0; i < nfin; ++i) { massive = massive || masses[i] > 0.0; msum += masses[i]; }
   for (int64_t e = 0; e < n; ++e) {
-    const double rs = sqrt_s[e];
+    const Real rs = sqrt_s[e];
     const double* ue = u + e * nfin * 4;
-    double q[8][4], Q[4] = {0, 0, 0, 0};
+    Real q[8][4], Q[4] = {0, 0, 0, 0};
     for (int i = 0; i < nfin; ++i) {
-      const double c = 2.0 * ue[4 * i] - 1.0, ph = 2.0 * M_PI * ue[4 * i + 1];
-      const double e0 = -std::log(ue[4 * i + 2] * ue[4 * i + 3]);
-      const double s = std::sqrt(std::max(0.0, 1.0 - c * c));
-      q[i][0] = e0; q[i][1] = e0 * s * std::cos(ph); q[i][2] = e0 * s * std::sin(ph); q[i][3] = e0 * c;
+      const Real c = 2.0 * ue[4 * i] - 1.0, ph = 2.0 * PI * ue[4 * i + 1];
+      const Real e0 = -Log(ue[4 * i + 2] * ue[4 * i + 3]);
+      const Real s = Sqrt(std::max<Real>(0.0, 1.0 - c * c));
+      q[i][0] = e0; q[i][1] = e0 * s * Cos(ph); q[i][2] = e0 * s * Sin(ph); q[i][3] = e0 * c;
       for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
     }
     // conformal transformation: boost by -Q/M, scale by sqrt_s/M
-    const double M = std::sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
-    const double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
-    const double g = Q[0] / M, a = 1.0 / (1.0 + g), x = rs / M;
-    double p[8][4];
+    const Real M = Sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+    const Real b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
+    const Real g = Q[0] / M, a = 1.0 / (1.0 + g), x = rs / M;
+    Real p[8][4];
     for (int i = 0; i < nfin; ++i) {
-      const double bq = b[0] * q[i][1] + b[1] * q[i][2] + b[2] * q[i][3];
+      const Real bq = b[0] * q[i][1] + b[1] * q[i][2] + b[2] * q[i][3];
       p[i][0] = x * (g * q[i][0] + bq);
       for (int m = 0; m < 3; ++m) p[i][1 + m] = x * (q[i][1 + m] + b[m] * q[i][0] + a * bq * b[m]);
     }
     // projection of the rounding left by the transformation
-    double r3[3] = {0, 0, 0};
+    Real r3[3] = {0, 0, 0};
     for (int i = 0; i < nfin; ++i) for (int m = 0; m < 3; ++m) r3[m] += p[i][1 + m];
-    double pabs[8], tot = 0.0;
+    Real pabs[8], tot = 0.0;
     for (int i = 0; i < nfin; ++i) {
       for (int m = 0; m < 3; ++m) p[i][1 + m] -= r3[m] / nfin;
-      pabs[i] = std::sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+      pabs[i] = Sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
       tot += pabs[i];
     }
-    const double sc = rs / tot;
+    const Real sc = rs / tot;
     for (int i = 0; i < nfin; ++i) {
       for (int m = 0; m < 3; ++m) p[i][1 + m] *= sc;
       p[i][0] = pabs[i] * sc;
     }
-    double w = vol1 * std::pow(rs, 2 * (nfin - 2));
+    Real w = vol1 * Pow(rs, 2 * (nfin - 2));
     if (massive) {
       // common factor xi on the three-momenta: sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt_s
-      double xi = std::sqrt(std::max(1e-30, 1.0 - (msum / rs) * (msum / rs)));
+      Real xi = Sqrt(std::max<Real>(1e-30, 1.0 - (msum / rs) * (msum / rs)));
       for (int it = 0; it < 50; ++it) {
-        double f = -rs, fp = 0.0;
+        Real f = -rs, fp = 0.0;
         for (int i = 0; i < nfin; ++i) {
-          const double ek = std::sqrt(masses[i] * masses[i] + xi * xi * p[i][0] * p[i][0]);
+          const Real ek = Sqrt(masses[i] * masses[i] + xi * xi * p[i][0] * p[i][0]);
           f += ek;
           fp += xi * p[i][0] * p[i][0] / ek;
         }
         xi -= f / fp;
-        if (std::fabs(f) <= 1e-14 * rs) break;
+        if (Fabs(f) <= 1e-14 * rs) break;
       }
-      double ksum = 0.0, kprod = 1.0, k2e = 0.0;
+      Real ksum = 0.0, kprod = 1.0, k2e = 0.0;
       for (int i = 0; i < nfin; ++i) {
-        const double E = p[i][0];
-        const double k0 = std::sqrt(masses[i] * masses[i] + xi * xi * E * E);
+        const Real E = p[i][0];
+        const Real k0 = Sqrt(masses[i] * masses[i] + xi * xi * E * E);
         for (int m = 0; m < 3; ++m) p[i][1 + m] *= xi;
         p[i][0] = k0;
-        const double ka = std::sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+        const Real ka = Sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
         ksum += ka; kprod *= ka / k0; k2e += ka * ka / k0;
       }
-      w *= std::pow(ksum / rs, 2 * nfin - 3) * kprod * rs / k2e;
+      w *= Pow(ksum / rs, 2 * nfin - 3) * kprod * rs / k2e;
     }
     for (int i = 0; i < nfin; ++i) for (int m = 0; m < 4; ++m) p_out[(e * nfin + i) * 4 + m] = p[i][m];
     w_out[e] = w;

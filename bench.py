@@ -197,24 +197,48 @@ def measured_traffic(kernel, n):
     return (int(rec["fetch_bytes"]) + int(rec["write_bytes"])) * n / int(rec["events"])
 
 
-def cpu_baseline(proc, mom_full, target_s=12.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload (the first events of the batch)."""
+def host_info():
+    """Cores and CPU model of the host running the baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity": aff, "cpu_model": model}
+
+
+def cpu_baseline(proc, mom_full, target_s=12.0, target_1_s=3.0):
+    """The FP64 oracle, built for this host (g++ -O3 -march=native, no
+    fast-math), on a bounded sample of the same workload (the first events of
+    the batch): with every core this process may use (at most 16, the box's
+    CPU share) and with one thread."""
     import oracle
-    oracle.build()
+    oracle.build_native()
     oracle.set_params()
-    threads = max(1, min(16, os.cpu_count() or 1))
+    hi = host_info()
+    threads = oracle.threads()
     probe = 16384        # large enough that thread start-up does not bias the rate
     t = time.perf_counter()
-    oracle.me2(proc, mom_full[:, :, :probe], nthreads=threads)
+    oracle.me2(proc, mom_full[:, :, :probe], nthreads=threads, kind="native")
     rate = probe / (time.perf_counter() - t)
     n = int(min(mom_full.shape[2], max(probe, rate * target_s)))
     t = time.perf_counter()
-    ref = oracle.me2(proc, np.ascontiguousarray(mom_full[:, :, :n]), nthreads=threads)
+    ref = oracle.me2(proc, np.ascontiguousarray(mom_full[:, :, :n]), nthreads=threads, kind="native")
     dt = time.perf_counter() - t
+    n1 = int(min(n, max(256, rate / threads * target_1_s)))
+    t = time.perf_counter()
+    oracle.me2(proc, np.ascontiguousarray(mom_full[:, :, :n1]), nthreads=1, kind="native")
+    dt1 = time.perf_counter() - t
     return ref, {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-                 "sample": "first %d events of the batch (FP64 oracle: colour-ordered recursion, "
-                           "std::thread over events, g++ -O2), %.1f s" % (n, dt)}
+                 "sample": "first %d events of the batch, %.1f s (FP64 oracle: colour-ordered recursion, "
+                           "std::thread over events, g++ -O3 -march=native)" % (n, dt),
+                 "one_thread": {"value": n1 / dt1, "unit": "events/s", "sample": "first %d events, %.1f s" % (n1, dt1)},
+                 "host": hi}
 
 
 def main():

@@ -160,7 +160,10 @@ typedef struct {
   double *g_R, *g_S;  /* [n] real and soft terms */
   double *g_C, *g_Cm; /* [n] collinear terms, y -> +1 and (initial state only) y -> -1 */
   double *g_SC, *g_SCm; /* [n] soft-collinear terms */
-  uint8_t* status;    /* [n] bit0 non-finite W, bit1 evaluated in FP64, bit2 a mask zeroed a term */
+  uint8_t* status;    /* [n] bit0 non-finite W, bit1 evaluated in FP64, bit2 a mask zeroed a term,
+                          bit3 W not resolved to 1e-3 in its working precision (its rounding
+                          bound, 1e-12 D in FP64 and 32 eps_32 (1 + 1/sqrt(1-|y|)) D in FP32
+                          with D = sum|g_X| / kappa, exceeds 1e-3 |W|) */
   double* real_mom;   /* [npart_real][4][ld] real-emission momenta in event order */
   double* w_sum;      /* [1] fixed-order FP64 sum of W over the batch */
 } nlo_fks_out;
@@ -184,9 +187,17 @@ typedef struct {
  *   mask:      device [4][ld] bytes for B, R, S, C (non-zero = passes its cuts)
  *              or NULL (all pass).  A failed cut zeroes its term after
  *              evaluation; the soft-collinear terms need both S and C.
- *   prec:      NLO_FP64, NLO_FP32 (amplitudes in float, kinematics and
- *              assembly in double) or NLO_MIXED (float unless
- *              min(xi, 1-|y|) < threshold, see nlo_set_fks_threshold).
+ *   prec:      NLO_FP64, NLO_FP32 (real amplitudes in float, kinematics and
+ *              assembly in double) or NLO_MIXED (float unless the event is
+ *              near a singular limit, see nlo_set_fks_threshold).
+ * The Born point is on shell and conserves momentum by definition: the
+ * final-state three-momenta are shifted by a common amount to sum to zero,
+ * their energies put on the mass shell, and the beams (along +-z) carry half
+ * the total energy each; the FKS pair's invariant (2 k_i.k_j, or 2 p_a.k_i
+ * for the beams) enters the real |M|^2 from the radiation variables.  W is a
+ * difference of terms growing like 1/kappa (kappa = xi (1-y), or
+ * xi (1-y^2) for the beams): in FP64 its error stays within 1e-12 of
+ * D = sum|g_X| / kappa (measured against a binary128 evaluation).
  * Uses a workspace owned by the context, grown on the first call with a
  * larger n after synchronising the device (so do such a first call outside
  * stream capture); calls that overlap on different streams with the same
@@ -205,7 +216,11 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
                           const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
                           const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream);
 
-/* Routing threshold of NLO_MIXED subtracted weights (default 1e-4). */
+/* Routing threshold of NLO_MIXED subtracted weights: an event is evaluated in
+ * FP64 when kappa = xi (1-y) (final-state fks_j) or xi (1-y^2) (beams) is below
+ * it, in FP32 otherwise.  Default 0.1: the FP32 rounding of the real |M|^2
+ * reaches W amplified by about 1/kappa, and at kappa >= 0.1 FP32 keeps
+ * |dW|/|W| below 1e-4 on every event measured.  threshold in [0, 1]. */
 nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold);
 
 /* ---- batched mixes: one graph launch for many (process, contribution) items ----

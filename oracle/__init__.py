@@ -18,7 +18,8 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 # "double": IEEE double.  "quad": IEEE binary128 (__float128), the reference
 # for the subtracted weight near the soft and collinear limits, where the
 # weight keeps about log10(1/(xi (1-y))) fewer digits than the arithmetic.
-_SO = {"double": os.path.join(_HERE, "liboracle.so"), "quad": os.path.join(_HERE, "liboracle_q.so")}
+_SO = {"double": os.path.join(_HERE, "liboracle.so"), "quad": os.path.join(_HERE, "liboracle_q.so"),
+       "native": os.path.join(_HERE, "liboracle_native.so")}
 _FLAGS = {"double": [], "quad": ["-DORACLE_QUAD"]}
 _LIBS = {"double": [], "quad": ["-lquadmath"]}
 
@@ -41,11 +42,16 @@ def build(verbose=False, kinds=("double", "quad")):
         os.replace(tmp, so)
 
 
-def build_native(path):
+def build_native():
     """The double build for this host's instruction set (-O3 -march=native,
-    no fast-math), for timing the oracle as a CPU baseline."""
-    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", path, _SRC]
+    no fast-math), for timing the oracle as a CPU baseline.  Built on the host
+    that runs it, every time (the instruction set differs between hosts)."""
+    path = _SO["native"]
+    tmp = path + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O3", "-march=native", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC]
     subprocess.run(cmd, check=True)
+    os.replace(tmp, path)
+    _lib.pop("native", None)
     return path
 
 
@@ -73,11 +79,16 @@ def lib(kind="double"):
     """The loaded oracle library of the given arithmetic ("double", "quad")."""
     if kind not in _lib:
         if not os.path.exists(_SO[kind]):
-            build(kinds=(kind,))
+            build_native() if kind == "native" else build(kinds=(kind,))
         _lib[kind] = _declare(ctypes.CDLL(_SO[kind]))
         if _params is not None:
             _lib[kind].orc_set_params(*_params)
     return _lib[kind]
+
+
+def threads():
+    """Worker threads for the oracle: the host's cores, at most 16."""
+    return max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1))
 
 
 def _dp(a):
@@ -164,11 +175,13 @@ def wavefunction(proc, p_aos, leg, lam):
 FKS_FIELDS = ["xi", "y", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "W", "me2_R", "B", "S"]
 
 
-def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=8, want_real=False, kind="double"):
+def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=None, want_real=False, kind="double"):
     """FKS-subtracted real emission for pair (i, j) (j = -1: initial state).
     Returns dict of arrays (FKS_FIELDS) and optionally the real momenta.
     kind="quad" evaluates every step in binary128 (outputs rounded to double)."""
     L = lib(kind)
+    if nthreads is None:
+        nthreads = threads()
     f = L.orc_fks
     f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.POINTER(ctypes.c_double)] * 6 + [ctypes.c_int]
     born_mom = np.ascontiguousarray(born_mom, dtype=np.float64)

@@ -1054,6 +1054,8 @@ def emit_process(p):
     L.append("  static constexpr int HEL_SYM = %d;" % (2 if HEL_SYMMETRY else 1))
     L.append("  static constexpr int NMOM = %d, NDEN = %d;" % (len(msets), len(dens)))
     L.append("  static constexpr const char* NAME = \"%s\";" % nm)
+    L.append("  static constexpr unsigned TOP_LEGS = 0x%x;   // bit k: leg k is a top quark"
+             % sum(1 << k for k, x in enumerate(list(p.incoming) + list(p.outgoing)) if x in ("t", "t~")))
     L.append("  __device__ static int good(int i) { return %s_good[i]; }" % nm)
     # per-event data
     L.append("  template <class T> struct Pre {")
@@ -1067,11 +1069,40 @@ def emit_process(p):
             L.append("    ferm_data<T> x%d;" % k)
     L.append("  };")
     # prologue
-    L.append("  template <class T> NLO_HD static void prologue(const double (&p)[NPART][4], Pre<T>& s, double mt) {")
+    L.append("  // ov: exact values of up to two pairwise invariants (an FKS pair's,")
+    L.append("  // from the radiation variables) that replace the ones formed here")
+    L.append("  template <class T> NLO_HD static void prologue(const double (&p)[NPART][4], Pre<T>& s, double mt,")
+    L.append("                                                const PairOv& ov = PairOv()) {")
     L.append("    double q[NPART][4];")
     for k in range(N):
         sgn = "" if k < nin else "-"
         L.append("    for (int m = 0; m < 4; ++m) q[%d][m] = %sp[%d][m];" % (k, sgn, k))
+    # pairwise invariants 2 q_a.q_b of the legs that some denominator needs
+    massive = [FERMIONS[flavour(p.itype[k])][0] == "MT" if p.itype[k] not in ("g", "a") else False
+               for k in range(N)]
+    full = frozenset(range(N))
+
+    def small_side(S):
+        C = full - S
+        if len(C) < len(S) or (len(C) == len(S) and 0 in C):
+            return C
+        return S
+    pairs = set()
+    for (S, mass) in dens:
+        Sp = sorted(small_side(S))
+        pairs.update((a, b) for ia, a in enumerate(Sp) for b in Sp[ia + 1:])
+    pairs = sorted(pairs)
+    for a, b in pairs:
+        L.append("    double s%d_%d = 2.0 * (q[%d][0] * q[%d][0] - q[%d][1] * q[%d][1] - q[%d][2] * q[%d][2] - "
+                 "q[%d][3] * q[%d][3]);" % (a, b, a, b, a, b, a, b, a, b))
+    if pairs:
+        L.append("    if (ov.a0 >= 0) {")
+        for a, b in pairs:
+            L.append("      if (ov.a0 == %d && ov.b0 == %d) s%d_%d = ov.v0;" % (a, b, a, b))
+            L.append("      if (ov.a1 == %d && ov.b1 == %d) s%d_%d = ov.v1;" % (a, b, a, b))
+        L.append("    }")
+    else:
+        L.append("    (void)ov;")
     for k in range(N):
         t = p.itype[k]
         if t in ("g", "a"):
@@ -1085,12 +1116,19 @@ def emit_process(p):
         expr = " + ".join("q[%d][m]" % k for k in legs)
         L.append("    { double Q[4]; for (int m = 0; m < 4; ++m) Q[m] = %s;" % expr)
         L.append("      for (int m = 0; m < 4; ++m) s.Q[%d].v[m] = T(Q[m]);" % i)
-        for (S2, mass), j in dslot.items():
-            if S2 == S:
-                mterm = " - mt * mt" if mass == "MT" else ""
-                L.append("      s.den[%d] = T(1.0 / (Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]%s));"
-                         % (j, mterm))
         L.append("    }")
+    # denominators P^2 - m^2 = sum_a m_a^2 + sum_{a<b} 2 q_a.q_b - m^2 over the
+    # smaller of the line's leg set and its complement (external particles on
+    # shell by definition): the near-singular invariant of a soft or
+    # collinear emission is then one pairwise product, never a difference of
+    # O(s) squares
+    for (S, mass), j in dslot.items():
+        Sp = sorted(small_side(S))
+        terms = ["s%d_%d" % (a, b) for ia, a in enumerate(Sp) for b in Sp[ia + 1:]]
+        cm = sum(1 for a in Sp if massive[a]) - (1 if mass == "MT" else 0)
+        if cm:
+            terms.append("%.1f * (mt * mt)" % cm)
+        L.append("    s.den[%d] = T(1.0 / (%s));" % (j, " + ".join(terms)))
     L.append("  }")
     # exact power-of-two rescaling of the external wavefunctions (used by the
     # half-width kernels to keep intermediate values inside the FP16 range)

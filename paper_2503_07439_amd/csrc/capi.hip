@@ -50,7 +50,10 @@ struct nlo_ctx {
   nlo_params params;
   std::mutex mu;
   nlo_kernel_config cfg[NPROC_][5];
-  double fks_thr = 1e-4;
+  // MIXED routes an FKS event to FP64 when kappa = xi (1-y) (or xi (1-y^2)
+  // for the beams) is below this: measured on the stress sets, FP32 keeps
+  // |dW|/|W| below 1e-4 for every event with kappa >= 0.1
+  double fks_thr = 0.1;
   int fks_compact = 0;   // 1: skip the real |M|^2 of events whose R cut fails
   // FKS workspace: real momenta, real |M|^2, bucket permutation, bucket sizes
   void* ws = nullptr;
@@ -237,7 +240,7 @@ nlo_status check_subtracted(const nlo_ctx* ctx, int real_proc, int fks_i, int fk
 
 size_t fks_ws_bytes(int real_proc, int64_t n) {
   const int nr = PROC_STATIC[real_proc].npart;
-  return (size_t)n * (nr * 4 + 1) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128;
+  return (size_t)n * (nr * 4 + 3) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128;
 }
 
 // the launch sequence of one FKS sector on stream s with workspace ws
@@ -256,7 +259,8 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.mask = mask;
   a.real = reinterpret_cast<double*>(base);
   a.me2r = a.real + (size_t)n * nr * 4;
-  a.inv = reinterpret_cast<unsigned*>(a.me2r + n);
+  a.pinv = a.me2r + n;
+  a.inv = reinterpret_cast<unsigned*>(a.pinv + 2 * (size_t)n);
   a.skip_inv = a.inv + n;
   uintptr_t c = reinterpret_cast<uintptr_t>(a.skip_inv + n);
   a.cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
@@ -284,6 +288,17 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   const nlo_kernel_config& kc = ctx->cfg[real_proc][prec];
   LaunchArgs la{n, n, a.real, a.me2r, coupling_scale(real_proc, ctx->params), ctx->params.m_top, kc.block, s,
                 a.cnt, 0};
+  // the real |M|^2 takes the FKS pair's invariants from the radiation variables
+  if (sec->j >= 0) {
+    la.ovp.a0 = std::min(sec->i, sec->j);
+    la.ovp.b0 = std::max(sec->i, sec->j);
+  } else {
+    la.ovp.a0 = 0;
+    la.ovp.b0 = sec->i;
+    la.ovp.a1 = 1;
+    la.ovp.b1 = sec->i;
+  }
+  la.ovv = a.pinv;
   const bool mfma = kc.colour_mode == 2 || (kc.colour_mode == 0 && a.mode == 2 && PROC_STATIC[real_proc].nflow >= MFMA_MIN_FLOWS);
   if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
   if (err == hipSuccess && a.mode != 0) {

@@ -41,6 +41,8 @@ struct FksKin {
   double nh[3];   // direction of parton I (soft limit)
   double ep[3];   // transverse unit vector of the collinear limit
   double ejc, z;  // FSR: E_J at y = 1 and its momentum fraction there
+  double omz;     // FSR: 1 - z = E_I / E_J(Born), formed without cancellation
+  double ei, ej;  // energies of partons I and J (FSR), or of I and of each beam (ISR)
 };
 
 __device__ __forceinline__ double d3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -55,6 +57,35 @@ __device__ __forceinline__ void fks_perp(const double* kh, double* e1, double* e
   const double cp = st > 0.0 ? kh[0] / st : 1.0, sp = st > 0.0 ? kh[1] / st : 0.0;
   e1[0] = ct * cp; e1[1] = ct * sp; e1[2] = -st;
   e2[0] = -sp; e2[1] = cp; e2[2] = 0.0;
+}
+
+// The Born point is on shell and conserves momentum by definition.  An input
+// rounded to double does neither exactly (at the 1e-16 level), and the real
+// emission meets its counterterms only as closely as it does, which would
+// leave a term of that size over xi (1-y) in W.  So the final-state
+// three-momenta are shifted by a common amount to sum to zero, every energy
+// is put on its mass shell, and the beams (along +-z in the partonic frame)
+// carry half the total energy each.
+template <class S>
+__device__ __forceinline__ void fks_project_born(double (&kb)[S::NB][4], double mt) {
+  using BP = typename S::Born;
+  constexpr int NF = S::NB - 2;
+  double res[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 2; k < S::NB; ++k)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) res[m] += kb[k][1 + m];
+  double etot = 0.0;
+#pragma unroll
+  for (int k = 2; k < S::NB; ++k) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) kb[k][1 + m] -= res[m] / NF;
+    const double m2 = ((BP::TOP_LEGS >> k) & 1u) ? mt * mt : 0.0;
+    kb[k][0] = sqrt(d3(kb[k] + 1, kb[k] + 1) + m2);
+    etot += kb[k][0];
+  }
+  kb[0][0] = 0.5 * etot; kb[0][1] = 0.0; kb[0][2] = 0.0; kb[0][3] = 0.5 * etot;
+  kb[1][0] = 0.5 * etot; kb[1][1] = 0.0; kb[1][2] = 0.0; kb[1][3] = -0.5 * etot;
 }
 
 // real kinematics of one event
@@ -114,6 +145,9 @@ __device__ void fks_map(const double (&kb)[S::NB][4], double xit, double y, doub
     K.sqs_r = sq;
     K.ejc = kj[0] - ei;
     K.z = K.ejc / kj[0];
+    K.omz = ei / kj[0];
+    K.ei = ei;
+    K.ej = ej;
   } else {
     const double xi = xit * (1.0 - K.sb / FKS_SCAP);
     const double sr = K.sb / (1.0 - xi);
@@ -143,12 +177,32 @@ __device__ void fks_map(const double (&kb)[S::NB][4], double xit, double y, doub
     K.sqs_r = sqr;
     K.ejc = 0.0;
     K.z = 0.0;
+    K.omz = 0.0;
+    K.ei = ei;
+    K.ej = 0.5 * sqr;
   }
 }
 
-// sector function of the pair (I, J) at the real point
+// Pairwise invariants 2 q_a.q_b (all momenta incoming) of the FKS pair, from
+// the radiation variables: a final-state pair gives 2 k_I.k_J = 2 E_I E_J (1-y);
+// the beams give -2 p_1.k_I = -2 E_1 E_I (1-y) and -2 p_2.k_I = -2 E_2 E_I (1+y).
+// Formed from the rounded real momenta these invariants would carry a relative
+// error of about eps/(xi (1-|y|)), which the real |M|^2 inherits.
 template <class S>
-__device__ double fks_sector(const double (&k)[S::NR][4], double sqs) {
+__device__ __forceinline__ void fks_pair_invariants(const FksKin& K, double& v0, double& v1) {
+  if constexpr (S::J >= 0) {
+    v0 = 2.0 * K.ei * K.ej * (1.0 - K.y);
+    v1 = 0.0;
+  } else {
+    v0 = -2.0 * K.ej * K.ei * (1.0 - K.y);
+    v1 = -2.0 * K.ej * K.ei * (1.0 + K.y);
+  }
+}
+
+// sector function of the pair (I, J) at the real point; the FKS pair's angle
+// is the radiation variable y itself
+template <class S>
+__device__ double fks_sector(const double (&k)[S::NR][4], double sqs, double y) {
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int q = 0; q < S::NPAIR; ++q) {
@@ -157,12 +211,13 @@ __device__ double fks_sector(const double (&k)[S::NR][4], double sqs) {
     const double pa = sqrt(d3(k[a] + 1, k[a] + 1));
     double t;
     if (b < 0) {
-      const double ya = k[a][3] / pa;
+      const double ya = (S::J < 0 && a == S::I) ? y : k[a][3] / pa;
       t = 1.0 / (xa * (1.0 - ya) * (1.0 + ya));
     } else {
       const double xb = 2.0 * k[b][0] / sqs;
       const double pb = sqrt(d3(k[b] + 1, k[b] + 1));
-      const double yab = d3(k[a] + 1, k[b] + 1) / (pa * pb);
+      const bool pair = S::J >= 0 && ((a == S::I && b == S::J) || (a == S::J && b == S::I));
+      const double yab = pair ? y : d3(k[a] + 1, k[b] + 1) / (pa * pb);
       const double h = (S::GLUON[a] && S::GLUON[b]) ? xb / (xa + xb) : 1.0;
       t = h / (xa * xb * (1.0 - yab));
     }
@@ -174,7 +229,7 @@ __device__ double fks_sector(const double (&k)[S::NR][4], double sqs) {
 
 // its soft limit: parton I along nh, the others at their Born momenta
 template <class S>
-__device__ double fks_sector_soft(const double (&kb)[S::NB][4], const double* nh, double sqs_b) {
+__device__ double fks_sector_soft(const double (&kb)[S::NB][4], const double* nh, double sqs_b, double yv) {
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int q = 0; q < S::NPAIR; ++q) {
@@ -185,7 +240,8 @@ __device__ double fks_sector_soft(const double (&kb)[S::NB][4], const double* nh
       t = 1.0 / ((1.0 - nh[2]) * (1.0 + nh[2]));
     } else {
       const double* p = kb[S::BMAP[b]];
-      const double y = d3(nh, p + 1) / sqrt(d3(p + 1, p + 1));
+      // the soft direction makes the angle y with the emitter by construction
+      const double y = b == S::J ? yv : d3(nh, p + 1) / sqrt(d3(p + 1, p + 1));
       t = 1.0 / ((2.0 * p[0] / sqs_b) * (1.0 - y));
     }
     den += t;
@@ -203,6 +259,7 @@ struct FksArgs {
   const double *xit, *y, *phi;         // [n]
   const uint8_t* mask;                 // [4][ld] for B, R, S, C or null
   double* real;                        // workspace [NR][4][n], bucket order
+  double* pinv;                        // workspace [2][n], bucket order: the FKS pair invariants
   double* me2r;                        // workspace [n], bucket order
   unsigned* inv;                       // workspace [n]: bucket position -> event
   unsigned* cnt;                       // workspace [4]: FP32 and FP64 bucket sizes, then the same
@@ -210,7 +267,8 @@ struct FksArgs {
   unsigned* skip_inv;                  // workspace [n]: skipped events (compact mode), FP32 from
                                        // the front, FP64 from the back
   int compact;                         // 1: events failing the R cut skip the real |M|^2
-  double thr;                          // route to FP64 when min(xi, 1-|y|) < thr
+  double thr;                          // route to FP64 when kappa = xi (1-y) (final-state J) or
+                                       // xi (1-y^2) (beams) is below thr
   int mode;                            // 0: all FP32, 1: all FP64, 2: route
   double scale_b, g2, mt;
   double scale_bm;                     // coupling x average factor of the y -> -1 Born (quark FKS parton)
@@ -219,12 +277,14 @@ struct FksArgs {
   double* real_out;                    // [NR][4][ld] (event order) or null
 };
 
+// the Born point of event e, projected on shell (fks_project_born)
 template <class S>
 __device__ __forceinline__ void load_born(const FksArgs& a, int64_t e, double (&kb)[S::NB][4]) {
 #pragma unroll
   for (int k = 0; k < S::NB; ++k)
 #pragma unroll
     for (int m = 0; m < 4; ++m) kb[k][m] = a.born[(k * 4 + m) * a.ld + e];
+  fks_project_born<S>(kb, a.mt);
 }
 
 static __global__ void k_fks_zero(unsigned* cnt) {
@@ -244,8 +304,10 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_map(FksArgs a) {
   if (act) {
     load_born<S>(a, e, kb);
     fks_map<S>(kb, a.xit[e], a.y[e], a.phi[e], kr, K);
-    const double dist = fmin(K.xi, 1.0 - fabs(K.y));
-    f64 = (a.mode == 1) || (a.mode == 2 && !(dist >= a.thr));
+    // W = (g_R - counterterms) / kappa cancels by about 1/kappa, so the FP32
+    // rounding of the real |M|^2 reaches W amplified by that much
+    const double kappa = S::J >= 0 ? K.xi * (1.0 - K.y) : K.xi * ((1.0 - K.y) * (1.0 + K.y));
+    f64 = (a.mode == 1) || (a.mode == 2 && !(kappa >= a.thr));
     skip = a.compact && a.mask && !a.mask[1 * a.ld + e];
   }
   // wave-aggregated positions in the four lists
@@ -275,6 +337,10 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_map(FksArgs a) {
     for (int k = 0; k < S::NR; ++k)
 #pragma unroll
       for (int m = 0; m < 4; ++m) a.real[(k * 4 + m) * a.n + pos] = kr[k][m];
+    double v0, v1;
+    fks_pair_invariants<S>(K, v0, v1);
+    a.pinv[pos] = v0;
+    a.pinv[a.n + pos] = v1;
   }
   if (a.real_out) {
 #pragma unroll
@@ -328,6 +394,18 @@ __device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e
     W = (gR - gS - 0.5 * (1.0 + y) * (gC - gSC) - 0.5 * (1.0 - y) * (gCm - gSCm)) / (xi * (1.0 - y) * (1.0 + y));
   }
   if (!isfinite(W)) st |= 1;
+  // bit 3: W not resolved in its working precision.  W cancels terms of
+  // size D = sum|g_X| / kappa, and its rounding error is measured against D:
+  // within 1e-12 D with the FP64 real |M|^2 (measured against the binary128
+  // oracle: at most 3.3e-13 D), within 32 eps_32 (1 + 1/sqrt(1-|y|)) D with
+  // the FP32 one (the collinear spinor products lose digits like
+  // 1/sqrt(1-|y|)).  Set when that bound exceeds 1e-3 |W|.
+  {
+    const double kap = S::J >= 0 ? xi * (1.0 - y) : xi * ((1.0 - y) * (1.0 + y));
+    const double D = (fabs(gR) + fabs(gS) + fabs(gC) + fabs(gCm) + fabs(gSC) + fabs(gSCm)) / kap;
+    const double c = (which & 1) ? 1e-12 : 32.0 * 0x1p-24 * (1.0 + 1.0 / sqrt(1.0 - fabs(y)));
+    if (!(c * D <= 1e-3 * fabs(W))) st |= 8;
+  }
   a.W[e] = W;
   if (a.xi_out) a.xi_out[e] = xi;
   if (a.born_out) a.born_out[e] = Bo;
@@ -370,8 +448,8 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
   const double Bplus = bp * BP::HEL_SYM * a.scale_b;
   const double Bperp = born_spin<BP, 0, T>(sp, K.ep, T(a.mt)) * a.scale_b;
   const double Bminus = born_sum<BM, T>(kb, a.mt) * a.scale_bm;
-  const double Pp = FKS_CF * (x * Bplus + 4.0 * (1.0 - x) / x * Bperp);
-  const double Pm = 0.5 * (x * x + (1.0 - x) * (1.0 - x)) * Bminus;
+  const double Pp = FKS_CF * (x * Bplus + 4.0 * xi / x * Bperp);
+  const double Pm = 0.5 * (x * x + xi * xi) * Bminus;
   const double gR = which >= 2 ? 0.0 : xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
   fks_store<S>(a, which, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, xi, y);
 }
@@ -393,7 +471,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
   FksKin K;
   load_born<S>(a, e, kb);
   fks_map<S>(kb, a.xit[e], a.y[e], a.phi[e], kr, K);
-  const double S_real = fks_sector<S>(kr, K.sqs_r);
+  const double S_real = fks_sector<S>(kr, K.sqs_r, K.y);
   if constexpr (S::QUARK_I) {
     fks_quark_isr<S, T>(a, which, pos, e, kb, K, S_real);
     return;
@@ -423,8 +501,23 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
   double bkl[BP::NCL][BP::NCL];
   BP::colour_corr(rho, bkl);
   const double B = bsum * BP::HEL_SYM * a.scale_b;
-  // eikonal factor -sum_kl (p_k.p_l)/((p_k.n)(p_l.n)) B_kl with n = (1, nh)
+  // eikonal factor -sum_kl (p_k.p_l)/((p_k.n)(p_l.n)) B_kl with n = (1, nh).
+  // The soft direction makes the angle y with the emitter (or beam 1), so
+  // there p.n = E (1 -+ y) exactly; from the components it would lose
+  // digits as 1/(1-|y|).
   const double n4[4] = {1.0, K.nh[0], K.nh[1], K.nh[2]};
+  double pn[BP::NCL];
+#pragma unroll
+  for (int k = 0; k < BP::NCL; ++k) {
+    const int leg = BP::CLEG[k];
+    const double* pk = kb[leg];
+    if (S::J >= 0 && leg == S::JB) pn[k] = pk[0] * (1.0 - K.y);
+    else if (S::J < 0 && leg == 0) pn[k] = pk[0] * (1.0 - K.y);
+    else if (S::J < 0 && leg == 1) pn[k] = pk[0] * (1.0 + K.y);
+    else pn[k] = mink(pk, n4);
+  }
+  // p_k.p_k is the nominal m_k^2 (zero for a massless parton): formed from
+  // the components it would leave rounding over (p_k.n)^2 ~ (1-y)^2
   double eik = 0.0;
 #pragma unroll
   for (int k = 0; k < BP::NCL; ++k)
@@ -432,24 +525,25 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     for (int l = 0; l < BP::NCL; ++l) {
       const double* pk = kb[BP::CLEG[k]];
       const double* pl = kb[BP::CLEG[l]];
-      eik -= mink(pk, pl) / (mink(pk, n4) * mink(pl, n4)) * bkl[k][l] * a.scale_b;
+      const double pkl = k != l ? mink(pk, pl) : (((BP::TOP_LEGS >> BP::CLEG[k]) & 1u) ? a.mt * a.mt : 0.0);
+      eik -= pkl / (pn[k] * pn[l]) * bkl[k][l] * a.scale_b;
     }
-  const double Ss = fks_sector_soft<S>(kb, K.nh, K.sqs_b);
+  const double Ss = fks_sector_soft<S>(kb, K.nh, K.sqs_b, K.y);
   const double xi = K.xi, y = K.y, g2 = a.g2;
   const double me2r = skipped ? 0.0 : a.me2r[pos];
   double gR, gS, gC, gCm = 0.0, gSC, gSCm = 0.0;
   if constexpr (S::J >= 0) {
     gR = xi * xi * (1.0 - y) * me2r * S_real;
     gS = (1.0 - y) * 4.0 / K.sb * g2 * eik * Ss;
-    const double z = K.z;
+    const double z = K.z, omz = K.omz;
     const double Sc = S::J_GLUON && S::GLUON[S::I] ? z : 1.0;
     double P, Cj;
     if constexpr (S::J_GLUON) {
       const double Bp = born_spin<BP, S::JB, T>(s, K.ep, T(a.mt)) * a.scale_b;
-      P = 2.0 * FKS_CA * ((z / (1.0 - z) + (1.0 - z) / z) * B + 2.0 * z * (1.0 - z) * Bp);
+      P = 2.0 * FKS_CA * ((z / omz + omz / z) * B + 2.0 * z * omz * Bp);
       Cj = FKS_CA;
     } else {
-      P = FKS_CF * (1.0 + z * z) / (1.0 - z) * B;
+      P = FKS_CF * (1.0 + z * z) / omz * B;
       Cj = FKS_CF;
     }
     gC = 2.0 * xi * g2 / (K.sqs_b * K.ejc) * P * Sc;
@@ -461,18 +555,18 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     double Pp, Pm, Cp, Cm;
     if constexpr (S::BEAM_GLUON0) {
       const double Bp = born_spin<BP, 0, T>(s, K.ep, T(a.mt)) * a.scale_b;
-      Pp = 2.0 * FKS_CA * ((x / (1.0 - x) + x * (1.0 - x)) * B + 2.0 * (1.0 - x) / x * Bp);
+      Pp = 2.0 * FKS_CA * ((x / xi + x * xi) * B + 2.0 * xi / x * Bp);
       Cp = FKS_CA;
     } else {
-      Pp = FKS_CF * (1.0 + x * x) / (1.0 - x) * B;
+      Pp = FKS_CF * (1.0 + x * x) / xi * B;
       Cp = FKS_CF;
     }
     if constexpr (S::BEAM_GLUON1) {
       const double Bp = born_spin<BP, 1, T>(s, K.ep, T(a.mt)) * a.scale_b;
-      Pm = 2.0 * FKS_CA * ((x / (1.0 - x) + x * (1.0 - x)) * B + 2.0 * (1.0 - x) / x * Bp);
+      Pm = 2.0 * FKS_CA * ((x / xi + x * xi) * B + 2.0 * xi / x * Bp);
       Cm = FKS_CA;
     } else {
-      Pm = FKS_CF * (1.0 + x * x) / (1.0 - x) * B;
+      Pm = FKS_CF * (1.0 + x * x) / xi * B;
       Cm = FKS_CF;
     }
     gC = 8.0 * xi * g2 / K.sb * Pp;

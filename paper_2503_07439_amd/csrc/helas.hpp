@@ -31,6 +31,14 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <class T> struct w4 { cx<T> c[4]; };      // spinor, or vector with upper index
+
+// exact values of up to two pairwise invariants 2 q_a.q_b (legs a < b, all
+// momenta incoming) that replace the ones a prologue forms from the momenta;
+// a0 < 0: none
+struct PairOv {
+  int a0 = -1, b0 = -1, a1 = -1, b1 = -1;
+  double v0 = 0.0, v1 = 0.0;
+};
 template <class T> struct r4 { T v[4]; };          // real four-momentum
 
 template <class T> NLO_HD cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }

@@ -44,10 +44,24 @@ __device__ __forceinline__ void event_range(int64_t n, const unsigned* cnt, int 
   else if (which == 1) lo = n - (int64_t)cnt[1];
 }
 
+// pair invariants of an FKS real emission: ovp carries the leg pairs, ovv
+// the per-event values ([2][ld], same event index as the momenta) or null
+__device__ __forceinline__ PairOv pair_ov(const PairOv& ovp, const double* __restrict__ ovv, int64_t ld, int64_t e) {
+  PairOv ov = ovp;
+  if (ovv) {
+    ov.v0 = ovv[e];
+    ov.v1 = ovv[ld + e];
+  } else {
+    ov.a0 = -1;
+  }
+  return ov;
+}
+
 template <class P, class T>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
-                                                  const unsigned* cnt, int which, const unsigned* list) {
+                                                  const unsigned* cnt, int which, const unsigned* list,
+                                                  PairOv ovp, const double* __restrict__ ovv) {
   int64_t e;
   if (which == 2) {               // the events listed in list[0, cnt[0])
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,7 +76,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t l
   double p[P::NPART][4];
   load_event<P>(mom, ld, e, p);
   typename P::template Pre<T> s;
-  P::prologue(p, s, mt);
+  P::prologue(p, s, mt, pair_ov(ovp, ovv, ld, e));
   double acc = 0.0;
   P::helicity_sum(s, T(mt), [&](const cx<T> (&J)[P::NFLOW]) { acc += (double)P::colour_sum(J); });
   out[e] = acc * (P::HEL_SYM * scale);   // the sum covers one of each pair (h, -h)
@@ -84,7 +98,8 @@ struct MfmaShape {
 template <class P>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
-                                                  const unsigned* cnt, int which) {
+                                                  const unsigned* cnt, int which, PairOv ovp,
+                                                  const double* __restrict__ ovv) {
   using S = MfmaShape<P>;
   extern __shared__ float smem[];
   int64_t lo, hi;
@@ -101,7 +116,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t l
   double p[P::NPART][4];
   load_event<P>(mom, ld, ec, p);
   typename P::template Pre<float> s;
-  P::prologue(p, s, mt);
+  P::prologue(p, s, mt, pair_ov(ovp, ovv, ld, ec));
 
   // B fragments: B[k][c] = L[k][c] = LT[c][k]; lane supplies k = 4 ks + lane/16, c = 16 nt + lane%16
   float bfrag[S::KS][S::NT];
@@ -307,10 +322,10 @@ hipError_t launch_me2(const LaunchArgs& a) {
   const int64_t grid = (a.n + a.block - 1) / a.block;
   if constexpr (VARIANT == VAR_F64) {
     hipLaunchKernelGGL((k_me2_valu<P, double>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr);
+                       a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr, a.ovp, a.ovv);
   } else if constexpr (VARIANT == VAR_F32) {
     hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which, a.list);
+                       a.out, a.scale, a.mt, a.cnt, a.which, a.list, a.ovp, a.ovv);
   } else if constexpr (VARIANT == VAR_F16 || VARIANT == VAR_BF16) {
     // half-width pass over all events, then FP32 over the listed ones
     using V2 = typename std::conditional<VARIANT == VAR_F16, f16x2, bf16x2>::type;
@@ -330,7 +345,7 @@ hipError_t launch_me2(const LaunchArgs& a) {
     return a.fb_launch(f);
   } else {
     hipLaunchKernelGGL((k_me2_mfma<P>), dim3((unsigned)grid), dim3(a.block), mfma_smem_bytes<P>(a.block), a.stream,
-                       a.n, a.ld, a.mom, a.out, a.scale, a.mt, a.cnt, a.which);
+                       a.n, a.ld, a.mom, a.out, a.scale, a.mt, a.cnt, a.which, a.ovp, a.ovv);
   }
   return hipGetLastError();
 }

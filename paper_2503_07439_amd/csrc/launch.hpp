@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include "helas.hpp"
 
 // largest block the kernels are compiled for (their __launch_bounds__)
 #define NLO_MAX_BLOCK 256
@@ -33,6 +34,10 @@ struct LaunchArgs {
   unsigned* fb_list = nullptr;
   unsigned* fb_cnt = nullptr;
   hipError_t (*fb_launch)(const LaunchArgs&) = nullptr;
+  // FKS real emission (FP32 / FP64 / MFMA variants): the legs of up to two
+  // pairwise invariants and their exact per-event values ovv[2][ld] (or null)
+  PairOv ovp{};
+  const double* ovv = nullptr;
 };
 
 struct ProcStatic {

@@ -1,8 +1,8 @@
 """FKS subtraction at the full sizes of the FKS workloads, in the
 precisions they are specified in (MIXED and FP64), one call per sector over
-the whole set: a strided sample of events matches the oracle to the bounds
-of the parity tests (test_gpu_fks_parity), every W is finite, and MIXED
-routes exactly the events with min(xi, 1-|y|) < 1e-4 to FP64.
+the whole set: a strided sample of events matches the binary128 oracle to
+the bounds of the parity tests (test_gpu_fks_parity), every W is finite, and
+MIXED routes exactly the events with kappa < 0.1 to FP64.
 
   g g -> t tbar g g, sector (4, 5) and (4, beams): 2^18 Born points
   e+e- -> u ubar g, sector (4, 2): 2^16 Born points
@@ -37,28 +37,28 @@ def test_fks_full_size_sampled(gpu, orc, real, i, j, born, rs, n):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     M, X, Y, P = t(mom), t(xt), t(y), t(phi)
     idx = np.arange(0, n, n // 64) + 5
+    ref = orc.fks(real, i, j, np.ascontiguousarray(mom[:, :, idx]), xt[idx], y[idx], phi[idx], kind="quad")
+    terms = sum(np.abs(ref[k]) for k in ("g_R", "g_S", "g_C", "g_SC", "g_Cm", "g_SCm"))
+    omy = (1 - ref["y"]) if j >= 0 else (1 - ref["y"]) * (1 + ref["y"])
+    kappa = ref["xi"] * omy
+    D = terms / kappa
     for prec in ("mixed", "fp64"):
         res = gpu.subtracted(real, i, j, M, X, Y, P, prec=prec)
         torch.cuda.synchronize()
         W = res["W"].cpu().numpy()
         st = res["status"].cpu().numpy()
         assert np.all(np.isfinite(W)) and not np.any(st & 1)
-        ref = orc.fks(real, i, j, np.ascontiguousarray(mom[:, :, idx]), xt[idx], y[idx], phi[idx])
-        terms = np.abs(ref["g_R"]) + np.abs(ref["g_S"]) + np.abs(ref["g_C"]) + np.abs(ref["g_SC"])
-        if j < 0:
-            terms = terms + np.abs(ref["g_Cm"]) + np.abs(ref["g_SCm"])
-            D = terms / (ref["xi"] * (1 - ref["y"]) * (1 + ref["y"]))
-        else:
-            D = terms / (ref["xi"] * (1 - ref["y"]))
-        kappa = ref["xi"] * (1 - np.abs(ref["y"]))
         dW = np.abs(W[idx] - ref["W"])
         routed = (st[idx] & 2) != 0
+        unres = (st[idx] & 8) != 0
+        fp64_bound = 1e-12 * (np.abs(ref["W"]) + D)
         if prec == "fp64":
             assert np.all(routed)
-            assert np.all(dW <= 1e-13 * D / kappa)
+            assert np.all(dW <= fp64_bound)
         else:
-            dist = np.minimum(ref["xi"], 1 - np.abs(ref["y"]))
-            assert np.array_equal(routed, dist < 1e-4)
-            assert np.all(dW[~routed] <= 1e-4 * D[~routed])
-            assert np.all(dW[routed] <= 1e-13 * D[routed] / kappa[routed])
-        print(real, i, j, prec, "n", n, "routed %.3f" % ((st & 2) != 0).mean(), flush=True)
+            assert np.array_equal(routed, kappa < 0.1)
+            assert np.all(dW[~routed] <= 1e-3 * np.abs(ref["W"][~routed]))
+            assert np.all(dW[routed] <= fp64_bound[routed])
+        assert np.all(dW[~unres] <= 1e-3 * np.abs(ref["W"][~unres]))
+        print(real, i, j, prec, "n", n, "routed %.3f unresolved %.4f" % (((st & 2) != 0).mean(), ((st & 8) != 0).mean()),
+              flush=True)

@@ -1,19 +1,24 @@
-"""Parity of the GPU FKS-subtracted real emission (through the C ABI) with
-the FP64 oracle, event by event, on seeded Born points and radiation
+"""Parity of the GPU FKS-subtracted real emission (through the C ABI) with the
+binary128 oracle, event by event, on seeded Born points and radiation
 variables with xi_tilde and 1-|y| log-uniform in [1e-6, 1].
 
-The subtracted weight W is a difference of terms that each grow like
-1/(xi (1-y)) near the limits, so its error is bounded relative to the
-conditioning scale  D = (|g_R| + |g_S| + |g_C| + |g_SC| + ...)/(xi (1-y)).
-Near the limits the real matrix element itself is ill-conditioned in FP64:
-its smallest invariant (2 k_i.k_j for a final-state emitter, 2 p_a.k_i for
-a beam) is of order xi (1-|y|) s but is formed from momentum components of
-order sqrt(s), so any two FP64 codes agree on it, and on g_R, only to about
-eps/kappa with kappa = xi (1-|y|).  Bounds:
-  FP64 : terms g_X relative 1e-13/kappa;  |dW| <= 1e-13 D/kappa
-  FP32 : |dW| <= 1e-4 D   (float amplitudes, FP64 denominators)
-  MIXED: |dW| <= 1e-4 D, and the FP64-routed events as FP64
-The plain relative error |dW|/|W| is printed for the record."""
+W = (g_R - counterterms) / kappa, kappa = xi (1-y) for a final-state emitter
+and xi (1-y^2) for the beams, is a difference of terms that each grow like
+1/kappa.  Its rounding error is bounded against the size of the terms it
+cancels, D = sum|g_X| / kappa, with no further power of kappa:
+
+  FP64 : every g_X within 1e-12 sum|g_X|;  |dW| <= 1e-12 (|W| + D).
+         (Measured: at most 3.3e-13 sum|g_X|, the rounding of the real
+         |M|^2; counterterms within 1.2e-13.)
+  MIXED: FP32 where kappa >= 0.1, FP64 below: |dW| <= 1e-3 |W| on every
+         FP32-routed event (measured <= 1.5e-5), the FP64 bound on the others.
+  FP32 : all events in FP32: |dW| <= 1e-3 D (FP32 is accurate only away
+         from the limits; MIXED is the mode for near-singular sets).
+Every event without status bit 3 (W resolved in its precision) is within
+1e-3 |W|.  The sum of W is checked against the sum of the per-event bounds:
+on these log-uniform sets it is dominated by the deepest events (|W| grows
+like 1/sqrt(1-|y|)), where FP64 leaves W only about 1e-4 relative, so the
+sum keeps about 1e-5 relative; its error is printed."""
 import numpy as np
 import pytest
 
@@ -32,6 +37,10 @@ SECTORS = [
     ("gg_ttgg", 5, -1, "gg_ttg", (400.0, 2000.0)),
     ("ug_ttu", 4, -1, "gg_tt", (400.0, 2000.0)),      # quark FKS parton: Born flavour changes
 ]
+IDS = ["%s_%d_%d" % s[:3] for s in SECTORS]
+THR = 0.1                 # default MIXED routing threshold on kappa
+
+_REF = {}
 
 
 @pytest.fixture(scope="module")
@@ -44,14 +53,26 @@ def gpu():
     ctx.close()
 
 
-def _inputs(real, j, born, rs, n, stream):
+def _inputs(sector, n, stream):
+    real, i, j, born, rs = sector
     mom, _ = events(born, n, rs, stream=stream)
     xt, y, phi = fks_variables(n, stream=stream, initial_state=(j < 0))
     return mom, xt, y, phi
 
 
-def _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec, mask=None, want_sum=False):
+def _ref(orc, sector, n, stream):
+    """binary128 oracle on the sector's stress inputs (cached per module)"""
+    key = (sector, n, stream)
+    if key not in _REF:
+        real, i, j = sector[:3]
+        mom, xt, y, phi = _inputs(sector, n, stream)
+        _REF[key] = orc.fks(real, i, j, mom, xt, y, phi, want_real=True, kind="quad")
+    return _REF[key]
+
+
+def _gpu_run(gpu, sector, mom, xt, y, phi, prec, mask=None, want_sum=False):
     import torch
+    real, i, j = sector[:3]
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     res = gpu.subtracted(real, i, j, t(mom), t(xt), t(y), t(phi), prec=prec,
                          mask=None if mask is None else t(mask), want_real=True, want_sum=want_sum)
@@ -59,72 +80,105 @@ def _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec, mask=None, want_sum=False):
     return {k: v.cpu().numpy() for k, v in res.items()}
 
 
-def _scale(r, j):
-    terms = np.abs(r["g_R"]) + np.abs(r["g_S"]) + np.abs(r["g_C"]) + np.abs(r["g_SC"])
-    if j < 0:
-        terms = terms + np.abs(r["g_Cm"]) + np.abs(r["g_SCm"])
-        return terms / (r["xi"] * (1 - r["y"]) * (1 + r["y"]))
-    return terms / (r["xi"] * (1 - r["y"]))
+def _terms(r):
+    return (np.abs(r["g_R"]) + np.abs(r["g_S"]) + np.abs(r["g_C"]) + np.abs(r["g_SC"])
+            + np.abs(r["g_Cm"]) + np.abs(r["g_SCm"]))
 
 
-@pytest.mark.parametrize("real,i,j,born,rs", SECTORS)
-def test_fks_fp64_parity(gpu, orc, real, i, j, born, rs):
-    n = 400 if real != "gg_ttgg" else 96
-    mom, xt, y, phi = _inputs(real, j, born, rs, n, 201)
-    ref = orc.fks(real, i, j, mom, xt, y, phi, want_real=True)
-    got = _gpu_run(gpu, real, i, j, mom, xt, y, phi, "fp64")
+def _kappa(r, j):
+    return r["xi"] * ((1 - r["y"]) if j >= 0 else (1 - r["y"]) * (1 + r["y"]))
+
+
+def _n(sector):
+    return 96 if sector[0] == "gg_ttgg" else 400
+
+
+@pytest.mark.parametrize("sector", SECTORS, ids=IDS)
+def test_fks_fp64_parity(gpu, orc, sector):
+    real, i, j = sector[:3]
+    n = _n(sector)
+    mom, xt, y, phi = _inputs(sector, n, 201)
+    ref = _ref(orc, sector, n, 201)
+    got = _gpu_run(gpu, sector, mom, xt, y, phi, "fp64")
     scale = mom[0, 0] + mom[1, 0]
     assert np.max(np.abs(got["real_mom"] - ref["real_mom"])) < 1e-11 * scale.max()
     assert np.allclose(got["xi"], ref["xi"], rtol=1e-14)
-    kappa = ref["xi"] * (1 - np.abs(ref["y"]))
-    for key in ("born", "g_R", "g_S", "g_C", "g_SC") + (("g_Cm", "g_SCm") if j < 0 else ()):
-        r = ref[key if key != "born" else "B"]
+    terms = _terms(ref)
+    for key in ("g_R", "g_S", "g_C", "g_SC") + (("g_Cm", "g_SCm") if j < 0 else ()):
+        r = ref[key]
         zero = r == 0.0                       # e.g. no soft term for a quark FKS parton
         assert np.all(got[key][zero] == 0.0), key
-        d = np.abs(got[key][~zero] - r[~zero]) / np.abs(r[~zero])
-        if d.size:
-            print(key, "max rel*kappa %.2e" % np.max(d * kappa[~zero]), flush=True)
-        assert np.all(d <= 1e-13 / kappa[~zero]), key
-    D = _scale(ref, j)
+        d = np.abs(got[key] - r) / terms
+        print(key, "max |d|/sum|g| %.2e" % d.max(), flush=True)
+        assert np.all(d <= 1e-12), key
+    assert np.allclose(got["born"], ref["B"], rtol=1e-12, atol=0)
+    D = terms / _kappa(ref, j)
     dW = np.abs(got["W"] - ref["W"])
-    print(real, i, j, "fp64 |dW|/D*kappa max %.2e, |dW|/|W| median %.2e max %.2e" % (
-        np.max(dW / D * kappa), np.median(dW / np.abs(ref["W"])), np.max(dW / np.abs(ref["W"]))), flush=True)
-    assert np.all(dW <= 1e-13 * D / kappa)
+    rel = dW / np.abs(ref["W"])
+    unres = (got["status"] & 8) != 0
+    print(real, i, j, "fp64 |dW|/D max %.2e; |dW|/|W| median %.2e max %.2e; unresolved %.3f" % (
+        np.max(dW / D), np.median(rel), rel.max(), unres.mean()), flush=True)
+    bound = 1e-12 * (np.abs(ref["W"]) + D)
+    assert np.all(dW <= bound)
+    assert np.all(rel[~unres] <= 1e-3)
     assert np.all(got["status"] & 2)            # every event evaluated in FP64
     assert not np.any(got["status"] & 1)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "mixed"])
-@pytest.mark.parametrize("real,i,j,born,rs", SECTORS)
-def test_fks_reduced_precision(gpu, orc, real, i, j, born, rs, prec):
-    n = 400 if real != "gg_ttgg" else 96
-    mom, xt, y, phi = _inputs(real, j, born, rs, n, 202)
-    ref = orc.fks(real, i, j, mom, xt, y, phi)
-    got = _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec)
-    D = _scale(ref, j)
+@pytest.mark.parametrize("sector", SECTORS, ids=IDS)
+def test_fks_mixed_parity(gpu, orc, sector):
+    real, i, j = sector[:3]
+    n = _n(sector)
+    mom, xt, y, phi = _inputs(sector, n, 201)
+    ref = _ref(orc, sector, n, 201)
+    got = _gpu_run(gpu, sector, mom, xt, y, phi, "mixed", want_sum=True)
+    D = _terms(ref) / _kappa(ref, j)
     dW = np.abs(got["W"] - ref["W"])
     rel = dW / np.abs(ref["W"])
     routed = (got["status"] & 2) != 0
-    print(real, i, j, prec, "routed %.2f |dW|/D max %.2e, |dW|/|W| median %.2e p99 %.2e" % (
-        routed.mean(), np.max(dW / D), np.median(rel), np.quantile(rel, 0.99)), flush=True)
-    assert np.all(dW <= 1e-4 * D)
-    if prec == "mixed":
-        dist = np.minimum(ref["xi"], 1 - np.abs(ref["y"]))
-        kappa = ref["xi"] * (1 - np.abs(ref["y"]))
-        assert np.array_equal(routed, dist < 1e-4)
-        assert np.all(dW[routed] <= 1e-13 * D[routed] / kappa[routed])
-    else:
-        assert not np.any(routed)
+    unres = (got["status"] & 8) != 0
+    kap = got["xi"] * ((1 - y) if j >= 0 else (1 - y) * (1 + y))
+    # routing: FP64 exactly below the threshold (kappa as the kernel forms it
+    # may differ in the last bit near the threshold)
+    near = np.abs(kap / THR - 1) < 1e-12
+    assert np.array_equal(routed[~near], kap[~near] < THR)
+    print(real, i, j, "mixed: routed %.3f, FP32 |dW|/|W| max %.2e, unresolved %.3f, all |dW|/|W| p99.9 %.2e" % (
+        routed.mean(), rel[~routed].max() if np.any(~routed) else 0.0, unres.mean(), np.quantile(rel, 0.999)),
+        flush=True)
+    bound = np.where(routed, 1e-12 * (np.abs(ref["W"]) + D), 1e-3 * np.abs(ref["W"]))
+    assert np.all(dW <= bound)
+    assert np.all(rel[~unres] <= 1e-3)
+    dsum = abs(got["w_sum"][0] - ref["W"].sum())
+    print("   sum W relative error %.2e (of sum|W|)" % (dsum / np.abs(ref["W"]).sum()), flush=True)
+    assert dsum <= bound.sum()
+    assert not np.any(got["status"] & 1)
+
+
+@pytest.mark.parametrize("sector", SECTORS, ids=IDS)
+def test_fks_fp32(gpu, orc, sector):
+    real, i, j = sector[:3]
+    n = _n(sector)
+    mom, xt, y, phi = _inputs(sector, n, 201)
+    ref = _ref(orc, sector, n, 201)
+    got = _gpu_run(gpu, sector, mom, xt, y, phi, "fp32")
+    D = _terms(ref) / _kappa(ref, j)
+    dW = np.abs(got["W"] - ref["W"])
+    rel = dW / np.abs(ref["W"])
+    unres = (got["status"] & 8) != 0
+    print(real, i, j, "fp32 |dW|/D max %.2e, unresolved %.3f" % (np.max(dW / D), unres.mean()), flush=True)
+    assert np.all(dW <= 1e-3 * D)
+    assert np.all(rel[~unres] <= 1e-3)
+    assert not np.any(got["status"] & 2)
 
 
 def test_fks_masks_and_sum(gpu, orc):
-    real, i, j, born, rs = SECTORS[2]
+    sector = SECTORS[2]
     n = 300
-    mom, xt, y, phi = _inputs(real, j, born, rs, n, 203)
+    mom, xt, y, phi = _inputs(sector, n, 203)
     rng = np.random.default_rng(9)
     mask = (rng.uniform(size=(4, n)) > 0.3).astype(np.uint8)
-    full = _gpu_run(gpu, real, i, j, mom, xt, y, phi, "fp64")
-    got = _gpu_run(gpu, real, i, j, mom, xt, y, phi, "fp64", mask=mask, want_sum=True)
+    full = _gpu_run(gpu, sector, mom, xt, y, phi, "fp64")
+    got = _gpu_run(gpu, sector, mom, xt, y, phi, "fp64", mask=mask, want_sum=True)
     for a, key in ((0, "born"), (1, "g_R"), (2, "g_S"), (3, "g_C")):
         assert np.all(got[key][mask[a] == 0] == 0.0)
         assert np.array_equal(got[key][mask[a] == 1], full[key][mask[a] == 1])
@@ -134,7 +188,7 @@ def test_fks_masks_and_sum(gpu, orc):
     # fixed-order FP64 sum of W
     assert abs(got["w_sum"][0] - got["W"].sum()) <= 1e-12 * np.abs(got["W"]).sum()
     # repeated evaluation is bitwise identical (bucket order is not)
-    again = _gpu_run(gpu, real, i, j, mom, xt, y, phi, "fp64", mask=mask, want_sum=True)
+    again = _gpu_run(gpu, sector, mom, xt, y, phi, "fp64", mask=mask, want_sum=True)
     assert np.array_equal(again["W"], got["W"]) and again["w_sum"][0] == got["w_sum"][0]
 
 
@@ -163,18 +217,18 @@ def test_fks_argument_errors(gpu):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-@pytest.mark.parametrize("real,i,j,born,rs", [SECTORS[0], SECTORS[2], SECTORS[4], SECTORS[8]])
-def test_fks_compact_masks_bitwise(gpu, real, i, j, born, rs, prec):
+@pytest.mark.parametrize("sector", [SECTORS[0], SECTORS[2], SECTORS[4], SECTORS[8]], ids=lambda s: "%s_%d_%d" % s[:3])
+def test_fks_compact_masks_bitwise(gpu, sector, prec):
     """Compact mode (events failing the R cut skip the real |M|^2) gives
     bit for bit the results of the branch-free mode."""
-    n = 500 if real != "gg_ttgg" else 120
-    mom, xt, y, phi = _inputs(real, j, born, rs, n, 204)
+    n = 500 if sector[0] != "gg_ttgg" else 120
+    mom, xt, y, phi = _inputs(sector, n, 204)
     rng = np.random.default_rng(11)
     mask = (rng.uniform(size=(4, n)) > np.array([[0.1], [0.5], [0.1], [0.1]])).astype(np.uint8)
-    ref = _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec, mask=mask, want_sum=True)
+    ref = _gpu_run(gpu, sector, mom, xt, y, phi, prec, mask=mask, want_sum=True)
     gpu.set_fks_mask_mode(True)
     try:
-        got = _gpu_run(gpu, real, i, j, mom, xt, y, phi, prec, mask=mask, want_sum=True)
+        got = _gpu_run(gpu, sector, mom, xt, y, phi, prec, mask=mask, want_sum=True)
     finally:
         gpu.set_fks_mask_mode(False)
     for k in ("W", "xi", "born", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "status", "real_mom", "w_sum"):

@@ -105,6 +105,7 @@ def mix_leg(ctx, steps):
             calls.append(lambda it=it: nl.nlo_subtracted(ctx.ctx, it.proc_id, it.fks_i, it.fks_j, it.n, it.ld, it.mom,
                                                          it.xi_tilde, it.y, it.phi, None, it.prec, it.fks_out, stream))
         items.append(it)
+    ctx.reserve(int(counts.max()))     # the direct calls share the context workspace
     plan = nl.nlo_batch_plan(ctx.ctx, items, 4)
 
     def run_graph():

@@ -23,6 +23,12 @@
  *    launch.  n == 0 is a valid no-op.
  *  - One context may be used from several threads; calls are serialised
  *    internally.  Distinct contexts are independent.
+ *  - Device memory is allocated only by nlo_reserve (the context workspace),
+ *    nlo_batch_plan (its own workspaces) and nlo_create (nothing beyond HIP's
+ *    context).  Evaluation calls never allocate or synchronise the device; one
+ *    that needs more workspace than reserved returns NLO_EINVAL.  Calls that
+ *    overlap on different streams with the same context share its workspace
+ *    and race on it: order them on one stream, or use one context per stream.
  */
 #ifndef NLOME_H
 #define NLOME_H
@@ -50,11 +56,11 @@ typedef enum {
  * float64.  NLO_FP64: everything in double.  NLO_FP32: spinors, currents,
  * vertices and the colour contraction in float; helicity-independent
  * quantities (internal momenta, propagator denominators, external-state
- * set-up) and the per-event helicity sum in double; colour contraction on the
- * vector ALU.  NLO_MIXED for |M|^2 is NLO_FP32 with the colour contraction on
- * the matrix cores when the process has at least 12 colour flows (vector ALU
- * below, where it is faster; nlo_set_kernel_config overrides); for subtracted
- * weights it also routes events near soft/collinear limits to FP64.
+ * set-up) and the per-event helicity sum in double.  NLO_MIXED for |M|^2 is
+ * NLO_FP32; for subtracted weights it routes events near soft/collinear
+ * limits to FP64.  In both, the colour contraction runs on the vector ALU
+ * unless nlo_set_kernel_config selects the matrix cores (measured slower at 6
+ * and at 24 colour flows; nlo_colour_unit reports the unit in use).
  * NLO_FP16 / NLO_BF16 (nlo_me2 and ME2 batch items only): amplitudes in
  * half-width floats on packed pairs of events, with momenta and masses
  * divided by sqrt(s_hat) of the event first (|M|^2 of N particles is
@@ -65,8 +71,7 @@ typedef enum {
  * inside the FP16 range.  Events whose largest denominator exceeds 2^14/s_hat
  * (close to a soft or collinear pole, where the diagrams cancel beyond what
  * a half-width significand resolves) are listed and evaluated again in FP32
- * by a second launch; this uses a workspace owned by the context (n + 32
- * 32-bit words, grown like the one of nlo_subtracted).  BF16 has no native
+ * by a second launch; this uses the context workspace (nlo_reserve).  BF16 has no native
  * arithmetic on this GPU: every operation rounds through FP32.
  * These are accuracy studies, not production precisions. */
 typedef enum { NLO_FP64 = 0, NLO_FP32 = 1, NLO_FP16 = 2, NLO_BF16 = 3, NLO_MIXED = 4 } nlo_prec;
@@ -128,6 +133,19 @@ nlo_status nlo_process_info(const nlo_ctx* ctx, int proc_id, nlo_proc_info* out)
 nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const nlo_kernel_config* cfg);
 nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec, nlo_kernel_config* cfg);
 
+/* The colour-contraction unit an evaluation of (proc_id, prec) uses with the
+ * context's configuration: *unit = 1 vector ALU, 2 matrix cores (FP32 and
+ * MIXED only; FP64, FP16 and BF16 always report 1). */
+nlo_status nlo_colour_unit(const nlo_ctx* ctx, int proc_id, nlo_prec prec, int* unit);
+
+/* Size the context workspace for evaluation calls of up to n events (any
+ * process, FKS sector or precision; a cross section needs min(n, 2^20)).  The
+ * only evaluation-side allocation: it waits for the device to be idle before
+ * freeing a smaller workspace, so call it outside stream capture and before
+ * the evaluation calls it serves.  A smaller n than already reserved is a
+ * no-op.  n in [0, 2^31). */
+nlo_status nlo_reserve(nlo_ctx* ctx, int64_t n);
+
 /* Autotuner: times every launch configuration of (proc_id, prec) -- block of
  * 64/128/192/256 threads (FP16/BF16 blocks cover two events per thread)
  * and, for FP32/MIXED, the colour contraction on the
@@ -135,7 +153,8 @@ nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec,
  * momenta, n events, scratch output me2 of n doubles) with HIP events on the
  * given stream, keeps the fastest for this context and returns it in *best
  * (may be NULL) and its time per event in *ns_per_event (may be NULL).
- * Synchronises the stream; allocates nothing. */
+ * Synchronises the stream; allocates nothing (FP16/BF16 use the context
+ * workspace, which must hold n events: nlo_reserve). */
 nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int64_t ld, const double* mom,
                         double* me2, void* hip_stream, nlo_kernel_config* best, double* ns_per_event);
 
@@ -149,6 +168,16 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
  * be inf or NaN). */
 nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
                    nlo_prec prec, void* hip_stream);
+
+/* nlo_me2 followed by a per-event status (the paper's event loop keeps
+ * every point on the device; the status says which results to trust):
+ *   status: device uint8 [n], written: bit0 me2[e] is not a finite
+ *   non-negative number, bit1 a momentum component of event e is not finite,
+ *   bit2 (FP16/BF16) the event was evaluated again in FP32 near a pole.
+ * The tests read exponent bits, so they hold whatever the arithmetic rules
+ * of the |M|^2 kernels.  One extra launch reading the momenta and |M|^2. */
+nlo_status nlo_me2_checked(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
+                           uint8_t* status, nlo_prec prec, void* hip_stream);
 
 /* Outputs of nlo_subtracted: device arrays owned by the caller.  W is
  * required; every other pointer may be NULL (not written). */
@@ -198,10 +227,7 @@ typedef struct {
  * difference of terms growing like 1/kappa (kappa = xi (1-y), or
  * xi (1-y^2) for the beams): in FP64 its error stays within 1e-12 of
  * D = sum|g_X| / kappa (measured against a binary128 evaluation).
- * Uses a workspace owned by the context, grown on the first call with a
- * larger n after synchronising the device (so do such a first call outside
- * stream capture); calls that overlap on different streams with the same
- * context race on it. */
+ * Uses the context workspace, which must hold n events (nlo_reserve). */
 /* How nlo_subtracted treats the cut masks (a context setting; batch plans
  * take the one in force when they are made).
  *   0 (default): branch-free, as in the paper's Algorithm 2 -- every term is
@@ -293,9 +319,9 @@ nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t st
  * the device (seed, stream; events 0..n-1), with |M|^2 in precision prec:
  *   sigma = (1/n) sum_e w_e |M|^2_e ident / (2 s_hat),  in pb (GeV^-2 x 0.3893793721e9),
  * error = the standard error of that mean.  Sums are accumulated in FP64 in a
- * fixed order (reproducible for a given n).  Uses the context workspace,
- * processes 2^20 events per chunk and synchronises the stream before
- * returning.  error_pb may be NULL. */
+ * fixed order (reproducible for a given n).  Processes min(n, 2^20) events
+ * per chunk in the context workspace (nlo_reserve of that many events) and
+ * synchronises the stream before returning.  error_pb may be NULL. */
 nlo_status nlo_cross_section(nlo_ctx* ctx, int proc_id, int64_t n, uint32_t seed, uint32_t stream, double sqrt_s,
                              nlo_prec prec, double* sigma_pb, double* error_pb, void* hip_stream);
 

@@ -10,7 +10,8 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
                    nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
-                   nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode)
+                   nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
+                   nlo_me2_checked, nlo_reserve, nlo_colour_unit)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -29,6 +30,14 @@ class Context:
             raise RuntimeError("paper_2503_07439_amd needs a HIP device")
         self.device = device
         self.ctx = nlo_create(alpha, alpha_s, m_top, device)
+        self.reserved = 0
+
+    def reserve(self, n):
+        """Size the context workspace for evaluation calls of up to n events
+        (host side, before the call: the calls themselves never allocate)."""
+        if n > self.reserved:
+            nlo_reserve(self.ctx, n)
+            self.reserved = n
 
     def close(self):
         if self.ctx is not None:
@@ -57,8 +66,28 @@ class Context:
         n = ld if out is None else out.shape[0]
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=mom.device)
+        if prec in ("fp16", "bf16"):
+            self.reserve(n)
         nlo_me2(self.ctx, proc_id(proc), n, ld, mom.data_ptr(), out.data_ptr(), PREC[prec], self._stream())
         return out
+
+    def me2_checked(self, proc, mom, prec="fp64"):
+        """(|M|^2 [n], status [n] uint8): bit0 non-finite or negative result,
+        bit1 non-finite input, bit2 FP32 pass of a half-width evaluation."""
+        import torch
+        assert mom.dtype == torch.float64 and mom.is_cuda and mom.is_contiguous()
+        npart, four, n = mom.shape
+        out = torch.empty(n, dtype=torch.float64, device=mom.device)
+        st = torch.empty(n, dtype=torch.uint8, device=mom.device)
+        if prec in ("fp16", "bf16"):
+            self.reserve(n)
+        nlo_me2_checked(self.ctx, proc_id(proc), n, n, mom.data_ptr(), out.data_ptr(), st.data_ptr(), PREC[prec],
+                        self._stream())
+        return out, st
+
+    def colour_unit(self, proc, prec):
+        """"valu" or "mfma": the colour-contraction unit (proc, prec) runs on."""
+        return {1: "valu", 2: "mfma"}[nlo_colour_unit(self.ctx, proc_id(proc), PREC[prec])]
 
     FKS_FIELDS = ("W", "xi", "born", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm")
 
@@ -88,6 +117,7 @@ class Context:
         if mask is not None:
             assert mask.dtype == torch.uint8 and mask.shape == (4, n) and mask.is_contiguous()
             mptr = mask.data_ptr()
+        self.reserve(n)
         nlo_subtracted(self.ctx, proc_id(real), fks_i, fks_j, n, n, born_mom.data_ptr(), xi_tilde.data_ptr(),
                        y.data_ptr(), phi.data_ptr(), mptr, PREC[prec], out, self._stream())
         return res
@@ -98,6 +128,8 @@ class Context:
         import torch
         n = mom.shape[2]
         out = torch.empty(n, dtype=torch.float64, device=mom.device)
+        if prec in ("fp16", "bf16"):
+            self.reserve(n)
         return nlo_autotune(self.ctx, proc_id(proc), PREC[prec], n, n, mom.data_ptr(), out.data_ptr(),
                             self._stream())
 
@@ -144,5 +176,6 @@ class Context:
 
     def cross_section(self, proc, n, sqrt_s, stream, prec="fp64", seed=SEED):
         """(sigma, error) in pb at fixed sqrt(s_hat), plain Monte Carlo on the device."""
+        self.reserve(min(n, 1 << 20))
         return nlo_cross_section(self.ctx, proc_id(proc), n, seed, stream, float(sqrt_s), PREC[prec], self._stream())
 

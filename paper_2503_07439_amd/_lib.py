@@ -68,6 +68,9 @@ SIGNATURES = {
     "nlo_set_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
     "nlo_get_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
     "nlo_me2": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "nlo_me2_checked": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "nlo_reserve": ([_VP, _I64], ctypes.c_int),
+    "nlo_colour_unit": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "nlo_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
                         ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
     "nlo_set_fks_threshold": ([_VP, ctypes.c_double], ctypes.c_int),
@@ -152,6 +155,20 @@ def nlo_get_kernel_config(ctx, proc_id, prec):
 
 def nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr):
     return check(lib().nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr))
+
+
+def nlo_me2_checked(ctx, proc_id, n, ld, mom_ptr, me2_ptr, status_ptr, prec, stream_ptr):
+    return check(lib().nlo_me2_checked(ctx, proc_id, n, ld, mom_ptr, me2_ptr, status_ptr, prec, stream_ptr))
+
+
+def nlo_reserve(ctx, n):
+    return check(lib().nlo_reserve(ctx, n))
+
+
+def nlo_colour_unit(ctx, proc_id, prec):
+    u = ctypes.c_int()
+    check(lib().nlo_colour_unit(ctx, proc_id, prec, ctypes.byref(u)))
+    return u.value
 
 
 def nlo_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, mask_ptr, prec, out,

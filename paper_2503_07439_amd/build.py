@@ -63,7 +63,8 @@ def generate():
 def _deps(src):
     """Sources an object depends on: the unit, the shared headers and, for a
     process unit, its generated header."""
-    deps = [src] + [os.path.join(CSRC, h) for h in ("helas.hpp", "opaque.hpp", "kernels.hpp", "launch.hpp", "fks.hpp", "phase_space.hpp")]
+    deps = [src] + [os.path.join(CSRC, h) for h in ("helas.hpp", "opaque.hpp", "kernels.hpp", "launch.hpp", "fks.hpp",
+                                                     "phase_space.hpp", "checks.hpp")]
     deps.append(os.path.join(ROOT, "include", "nlome.h"))
     base = os.path.basename(src)
     if base.startswith("tu_fks_"):
@@ -97,7 +98,7 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     """Compile every unit (force=True) or only those older than their sources."""
     tus = generate()
     os.makedirs(OBJ, exist_ok=True)
-    srcs = [os.path.join(CSRC, "capi.hip"), os.path.join(CSRC, "phase_space.hip")] + list(tus)
+    srcs = [os.path.join(CSRC, "capi.hip"), os.path.join(CSRC, "phase_space.hip"), os.path.join(CSRC, "checks.hip")] + list(tus)
     # the largest process first so the long poles start early
     srcs.sort(key=lambda p: 0 if p.endswith("tu_gg_ttgg_4.hip") else
               (1 if ("gg_ttgg" in p and "fks" not in p) else (2 if "gg_ttg" in p else 3)))

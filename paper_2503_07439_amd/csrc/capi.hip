@@ -16,6 +16,7 @@
 #include "generated/index.hpp"
 #include "launch.hpp"
 #include "phase_space.hpp"
+#include "checks.hpp"
 #include "nlome.h"
 
 using namespace nlo;
@@ -39,10 +40,16 @@ nlo_status fail(nlo_status st, const char* fmt, ...) {
 }
 
 constexpr int NPROC_ = NPROC;
-// smallest colour basis for which MIXED picks the matrix cores automatically;
-// measured on MI355X with the nested helicity schedule the vector ALU was
-// faster for every process (6 and 24 flows), so automatic mode never does
-constexpr int MFMA_MIN_FLOWS = 1 << 30;
+// Automatic colour unit: the vector ALU for every process.  Measured on
+// MI355X with the nested helicity schedule, the matrix-core variant stages
+// each helicity's flow vectors through LDS behind two barriers and is slower
+// at 6 flows (gg -> t tbar g: 2.70 against 1.83 ms per 2^22 events) and at
+// 24 (gg -> t tbar g g); nlo_set_kernel_config selects it explicitly.
+int auto_colour_mode(int pid, nlo_prec prec) {
+  (void)pid;
+  (void)prec;
+  return 1;
+}
 
 }  // namespace
 
@@ -55,9 +62,12 @@ struct nlo_ctx {
   // |dW|/|W| below 1e-4 for every event with kappa >= 0.1
   double fks_thr = 0.1;
   int fks_compact = 0;   // 1: skip the real |M|^2 of events whose R cut fails
-  // FKS workspace: real momenta, real |M|^2, bucket permutation, bucket sizes
+  // workspace of the evaluation calls (FKS buckets, half-width fallback
+  // list, cross-section chunks), sized by nlo_reserve for up to ws_events
+  // events; evaluation calls never allocate
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  int64_t ws_events = 0;
 };
 
 namespace {
@@ -105,11 +115,7 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
   } else if (prec == NLO_BF16) {
     var = VAR_BF16;
   } else {
-    int mode = kc.colour_mode;
-    // automatic: matrix cores when the colour contraction is large enough to
-    // pay for its LDS round trip (measured: 24 flows faster on MFMA, 2-6 flows
-    // faster on the vector ALU)
-    if (mode == 0) mode = (prec == NLO_MIXED && PROC_STATIC[pid].nflow >= MFMA_MIN_FLOWS) ? 2 : 1;
+    const int mode = kc.colour_mode ? kc.colour_mode : auto_colour_mode(pid, prec);
     var = (mode == 2) ? VAR_MFMA : VAR_F32;
   }
   LaunchArgs a{n, ld, mom, out, coupling_scale(pid, ctx->params), ctx->params.m_top, kc.block, st};
@@ -125,24 +131,12 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
   return NLO_OK;
 }
 
-// grow the context's workspace to at least need bytes; the old one is freed
-// only after the whole device is idle (work already queued on any stream may
-// still use it); caller holds ctx->mu
-nlo_status ensure_ws(nlo_ctx* ctx, size_t need, hipStream_t s, const char* fn) {
-  (void)s;
+// the reserved workspace must hold need bytes (evaluation calls never
+// allocate: nlo_reserve sizes it); caller holds ctx->mu
+nlo_status check_ws(const nlo_ctx* ctx, size_t need, int64_t n, const char* fn) {
   if (need <= ctx->ws_bytes) return NLO_OK;
-  if (ctx->ws) {
-    if (hipDeviceSynchronize() != hipSuccess) return fail(NLO_EDEVICE, "%s: device sync failed", fn);
-    (void)hipFree(ctx->ws);
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-  }
-  if (hipMalloc(&ctx->ws, need) != hipSuccess) {
-    ctx->ws = nullptr;
-    return fail(NLO_ENOMEM, "%s: workspace of %zu bytes", fn, need);
-  }
-  ctx->ws_bytes = need;
-  return NLO_OK;
+  return fail(NLO_EINVAL, "%s: %lld events need a workspace of %zu bytes, %zu reserved; call nlo_reserve(ctx, %lld)",
+              fn, (long long)n, need, ctx->ws_bytes, (long long)n);
 }
 
 nlo_status check_ctx(const nlo_ctx* ctx, int proc_id, const char* fn) {
@@ -243,6 +237,23 @@ size_t fks_ws_bytes(int real_proc, int64_t n) {
   return (size_t)n * (nr * 4 + 3) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128;
 }
 
+// cross-section chunk of m events: momenta, weights, |M|^2, partial sums,
+// accumulator, then the half-width fallback list
+size_t xs_ws_bytes(int npart, int64_t m) {
+  return ((size_t)npart * 4 * m + 2 * (size_t)m + XS_PART_DOUBLES + 8) * sizeof(double) + half_ws_bytes(m);
+}
+
+constexpr int64_t XS_CHUNK = (int64_t)1 << 20;
+
+// workspace that serves every evaluation call of up to n events: the largest
+// FKS sector, a half-width |M|^2 launch and a cross-section chunk
+size_t ws_bytes_for(int64_t n) {
+  size_t b = half_ws_bytes(n);
+  for (const FksSector& f : FKS_TABLE) b = std::max(b, fks_ws_bytes(f.real, n));
+  for (int p = 0; p < NPROC_; ++p) b = std::max(b, xs_ws_bytes(PROC_STATIC[p].npart, std::min(n, XS_CHUNK)));
+  return b;
+}
+
 // the launch sequence of one FKS sector on stream s with workspace ws
 hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_proc, int64_t n, int64_t ld,
                              const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
@@ -299,7 +310,7 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
     la.ovp.b1 = sec->i;
   }
   la.ovv = a.pinv;
-  const bool mfma = kc.colour_mode == 2 || (kc.colour_mode == 0 && a.mode == 2 && PROC_STATIC[real_proc].nflow >= MFMA_MIN_FLOWS);
+  const bool mfma = (kc.colour_mode ? kc.colour_mode : auto_colour_mode(real_proc, prec)) == 2;
   if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
   if (err == hipSuccess && a.mode != 0) {
     la.which = 1;
@@ -342,7 +353,7 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
   st = use_device(ctx, "nlo_subtracted");
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  st = ensure_ws(ctx, fks_ws_bytes(real_proc, n), s, "nlo_subtracted");
+  st = check_ws(ctx, fks_ws_bytes(real_proc, n), n, "nlo_subtracted");
   if (st) return st;
   hipError_t err = launch_subtracted(ctx, sec, real_proc, n, ld, born_mom, xi_tilde, y, phi, mask, prec, out,
                                      ctx->ws, s);
@@ -383,28 +394,99 @@ nlo_status nlo_get_kernel_config(const nlo_ctx* ctx, int proc_id, nlo_prec prec,
   return NLO_OK;
 }
 
-nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2, nlo_prec prec,
-                   void* hip_stream) {
-  nlo_status st = check_ctx(ctx, proc_id, "nlo_me2");
+}  // extern "C"
+
+namespace {
+
+// nlo_me2 and nlo_me2_checked: validation, then (under the context lock) the
+// |M|^2 launch and, with a status array, the status kernels
+nlo_status me2_call(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2, uint8_t* status,
+                    nlo_prec prec, void* hip_stream, const char* fn) {
+  nlo_status st = check_ctx(ctx, proc_id, fn);
   if (st) return st;
-  if (n < 0) return fail(NLO_EINVAL, "nlo_me2: n = %lld < 0", (long long)n);
-  if (ld < n) return fail(NLO_EINVAL, "nlo_me2: ld = %lld < n = %lld", (long long)ld, (long long)n);
-  if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "nlo_me2: bad precision %d", (int)prec);
+  if (n < 0) return fail(NLO_EINVAL, "%s: n = %lld < 0", fn, (long long)n);
+  if (ld < n) return fail(NLO_EINVAL, "%s: ld = %lld < n = %lld", fn, (long long)ld, (long long)n);
+  if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "%s: bad precision %d", fn, (int)prec);
   if (n == 0) return NLO_OK;
-  if (!mom || !me2) return fail(NLO_EINVAL, "nlo_me2: NULL device pointer");
-  if ((int64_t)((n + 1023) / 64) > (int64_t)0x7fffffff) return fail(NLO_EINVAL, "nlo_me2: n too large");
+  if (!mom || !me2) return fail(NLO_EINVAL, "%s: NULL device pointer", fn);
+  if ((int64_t)((n + 1023) / 64) > (int64_t)0x7fffffff) return fail(NLO_EINVAL, "%s: n too large", fn);
+  if (half_prec(prec) && n > 0x7fffffffLL) return fail(NLO_EINVAL, "%s: n too large for FP16/BF16 (event list)", fn);
   std::lock_guard<std::mutex> g(ctx->mu);
-  st = use_device(ctx, "nlo_me2");
+  st = use_device(ctx, fn);
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   if (half_prec(prec)) {
-    if (n > 0x7fffffffLL) return fail(NLO_EINVAL, "nlo_me2: n too large for FP16/BF16 (event list)");
-    st = ensure_ws(ctx, half_ws_bytes(n), s, "nlo_me2");
+    st = check_ws(ctx, half_ws_bytes(n), n, fn);
     if (st) return st;
   }
-  return launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s, ctx->ws);
+  st = launch_me2(ctx, proc_id, n, ld, mom, me2, prec, s, ctx->ws);
+  if (st || !status) return st;
+  hipError_t e = launch_me2_status(n, ld, PROC_STATIC[proc_id].npart, mom, me2, status, s);
+  if (e == hipSuccess && half_prec(prec)) {
+    // the events the half-width pass listed for FP32 (list and counter as
+    // launch_me2 lays them out in the workspace)
+    const unsigned* list = static_cast<const unsigned*>(ctx->ws);
+    const uintptr_t c = reinterpret_cast<uintptr_t>(list + n);
+    const unsigned* cnt = reinterpret_cast<const unsigned*>((c + 63) & ~uintptr_t(63));
+    e = launch_mark_list(n, cnt, list, 4, status, s);
+  }
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  return NLO_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+nlo_status nlo_me2(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2, nlo_prec prec,
+                   void* hip_stream) {
+  return me2_call(ctx, proc_id, n, ld, mom, me2, nullptr, prec, hip_stream, "nlo_me2");
+}
+
+nlo_status nlo_me2_checked(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, double* me2,
+                           uint8_t* status, nlo_prec prec, void* hip_stream) {
+  if (n > 0 && !status) return fail(NLO_EINVAL, "nlo_me2_checked: status is NULL");
+  return me2_call(ctx, proc_id, n, ld, mom, me2, status, prec, hip_stream, "nlo_me2_checked");
+}
+
+nlo_status nlo_reserve(nlo_ctx* ctx, int64_t n) {
+  if (!ctx) return fail(NLO_EINVAL, "nlo_reserve: ctx is NULL");
+  if (n < 0 || n > 0x7fffffffLL) return fail(NLO_EINVAL, "nlo_reserve: n = %lld out of [0, 2^31)", (long long)n);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (n <= ctx->ws_events) return NLO_OK;
+  nlo_status st = use_device(ctx, "nlo_reserve");
+  if (st) return st;
+  const size_t need = ws_bytes_for(n);
+  if (ctx->ws) {
+    // work already queued on any stream may still use the old workspace
+    if (hipDeviceSynchronize() != hipSuccess) return fail(NLO_EDEVICE, "nlo_reserve: device sync failed");
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    ctx->ws_events = 0;
+  }
+  if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(NLO_ENOMEM, "nlo_reserve: workspace of %zu bytes", need);
+  }
+  ctx->ws_bytes = need;
+  ctx->ws_events = n;
+  return NLO_OK;
+}
+
+nlo_status nlo_colour_unit(const nlo_ctx* ctx, int proc_id, nlo_prec prec, int* unit) {
+  nlo_status st = check_ctx(ctx, proc_id, "nlo_colour_unit");
+  if (st) return st;
+  if (!unit) return fail(NLO_EINVAL, "nlo_colour_unit: unit is NULL");
+  if ((int)prec < 0 || (int)prec > NLO_MIXED) return fail(NLO_EINVAL, "nlo_colour_unit: bad precision %d", (int)prec);
+  if (prec != NLO_FP32 && prec != NLO_MIXED) {
+    *unit = 1;
+    return NLO_OK;
+  }
+  const int mode = ctx->cfg[proc_id][prec].colour_mode;
+  *unit = mode ? mode : auto_colour_mode(proc_id, prec);
+  return NLO_OK;
+}
 
 nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int64_t ld, const double* mom,
                         double* me2, void* hip_stream, nlo_kernel_config* best, double* ns_per_event) {
@@ -418,7 +500,7 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
   if (half_prec(prec)) {
-    st = ensure_ws(ctx, half_ws_bytes(n), s, "nlo_autotune");
+    st = check_ws(ctx, half_ws_bytes(n), n, "nlo_autotune");
     if (st) return st;
   }
   hipEvent_t e0, e1;
@@ -680,11 +762,11 @@ nlo_status nlo_cross_section(nlo_ctx* ctx, int proc_id, int64_t n, uint32_t seed
   st = use_device(ctx, "nlo_cross_section");
   if (st) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 20);
+  const int64_t chunk = std::min<int64_t>(n, XS_CHUNK);
   // workspace: momenta, weights, |M|^2, partial sums, accumulator, then the
   // half-width fallback list
-  const size_t mom_d = (size_t)P.npart * 4 * chunk, xs_d = mom_d + 2 * (size_t)chunk + XS_PART_DOUBLES + 8;
-  st = ensure_ws(ctx, xs_d * sizeof(double) + half_ws_bytes(chunk), s, "nlo_cross_section");
+  const size_t mom_d = (size_t)P.npart * 4 * chunk;
+  st = check_ws(ctx, xs_ws_bytes(P.npart, chunk), chunk, "nlo_cross_section");
   if (st) return st;
   double* base = static_cast<double*>(ctx->ws);
   double *mom = base, *w = mom + mom_d, *me2 = w + chunk, *part = me2 + chunk, *acc = part + XS_PART_DOUBLES;

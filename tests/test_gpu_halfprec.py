@@ -100,6 +100,7 @@ def test_halfprec_ragged_and_padded(gpu, orc, n):
     m = torch.from_numpy(mom).cuda()
     out = torch.full((n + 5,), -1.0, dtype=torch.float64, device="cuda")
     import paper_2503_07439_amd as nl
+    gpu.reserve(n)
     nl.nlo_me2(gpu.ctx, nl.proc_id(proc), n, ld, m.data_ptr(), out.data_ptr(), nl.NLO_FP16, gpu._stream())
     torch.cuda.synchronize()
     o = out.cpu().numpy()

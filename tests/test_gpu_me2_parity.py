@@ -140,3 +140,51 @@ def test_full_size_sampled_gg_ttg(gpu, orc):
         r = np.abs(o[idx] / ref - 1)
         print("full size", prec, "median", np.median(r), "max", r.max(), flush=True)
         assert np.all(r < tol)
+
+
+def test_me2_checked_status(gpu, orc):
+    """nlo_me2_checked: the same |M|^2 as nlo_me2 and a per-event status --
+    bit1 on an event with a non-finite momentum (bit0 follows from its
+    result), nothing on good events."""
+    import torch
+    proc = "gg_ttg"
+    mom, _ = events(proc, 300, (400.0, 2000.0), stream=120)
+    mom[3, 2, 17] = np.nan
+    mom[2, 0, 42] = np.inf
+    m = torch.from_numpy(mom).cuda()
+    ref = gpu.me2(proc, m, "fp64")
+    got, st = gpu.me2_checked(proc, m, "fp64")
+    torch.cuda.synchronize()
+    ref, got, st = ref.cpu().numpy(), got.cpu().numpy(), st.cpu().numpy()
+    good = np.ones(300, bool)
+    good[[17, 42]] = False
+    assert np.array_equal(got[good], ref[good])
+    assert np.all(st[good] == 0)
+    assert np.all(st[~good] & 2)
+    assert np.allclose(got[good], orc.me2(proc, mom[:, :, good]), rtol=1e-12)
+
+
+def test_reserve_and_colour_unit(gpu):
+    """Evaluation calls never allocate: one that needs more workspace than
+    nlo_reserve provided fails with NLO_EINVAL and launches nothing; after
+    nlo_reserve it runs.  nlo_colour_unit reports the automatic unit (vector
+    ALU) and an explicit override."""
+    import torch
+    import paper_2503_07439_amd as nl
+    ctx = nl.Context()
+    try:
+        mom = torch.from_numpy(events("gg_tt", 64, (400.0, 2000.0), stream=121)[0]).cuda()
+        out = torch.empty(64, dtype=torch.float64, device="cuda")
+        with pytest.raises(nl.NloError) as e:
+            nl.nlo_me2(ctx.ctx, nl.proc_id("gg_tt"), 64, 64, mom.data_ptr(), out.data_ptr(), nl.NLO_FP16, 0)
+        assert e.value.status == 1 and "nlo_reserve" in str(e.value)
+        nl.nlo_reserve(ctx.ctx, 64)
+        nl.nlo_me2(ctx.ctx, nl.proc_id("gg_tt"), 64, 64, mom.data_ptr(), out.data_ptr(), nl.NLO_FP16, 0)
+        torch.cuda.synchronize()
+        assert torch.all(torch.isfinite(out))
+        for p in ("gg_ttg", "gg_ttgg"):
+            assert ctx.colour_unit(p, "mixed") == "valu" and ctx.colour_unit(p, "fp64") == "valu"
+        ctx.set_kernel_config("gg_ttg", "mixed", 256, 2)
+        assert ctx.colour_unit("gg_ttg", "mixed") == "mfma"
+    finally:
+        ctx.close()

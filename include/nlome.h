@@ -242,6 +242,18 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
                           const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
                           const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream);
 
+/* nlo_subtracted without any allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, with the workspace in
+ * a static device array (about 14.7 MB per GPU, held until the process ends)
+ * instead of the context workspace.  n <= 65536 events of any sector, else
+ * NLO_EINVAL with no launch.  Every call on one GPU shares that GPU's array
+ * (the kernels clear the counters they need): calls that overlap on one GPU,
+ * from any context or stream, race on it. */
+nlo_status nlo_subtracted_static(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                                 const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                                 const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream);
+
 /* Routing threshold of NLO_MIXED subtracted weights: an event is evaluated in
  * FP64 when kappa = xi (1-y) (final-state fks_j) or xi (1-y^2) (beams) is below
  * it, in FP32 otherwise.  Default 0.1: the FP32 rounding of the real |M|^2

@@ -8,7 +8,7 @@ from . import _lib
 from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloError,  # noqa: F401
                    nlo_abi_version, nlo_create, nlo_destroy, nlo_last_error, nlo_num_processes,
                    nlo_process_info, nlo_set_kernel_config, nlo_get_kernel_config, nlo_me2,
-                   nlo_subtracted, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
+                   nlo_subtracted, nlo_subtracted_static, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
                    nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
                    nlo_me2_checked, nlo_reserve, nlo_colour_unit)

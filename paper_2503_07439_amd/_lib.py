@@ -73,6 +73,8 @@ SIGNATURES = {
     "nlo_colour_unit": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "nlo_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
                         ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
+    "nlo_subtracted_static": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
+                               ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
     "nlo_set_fks_threshold": ([_VP, ctypes.c_double], ctypes.c_int),
     "nlo_set_fks_mask_mode": ([_VP, ctypes.c_int], ctypes.c_int),
     "nlo_batch_plan": ([_VP, ctypes.POINTER(nlo_work_item), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)],
@@ -175,6 +177,12 @@ def nlo_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr
                    stream_ptr):
     return check(lib().nlo_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr,
                                       mask_ptr, prec, ctypes.byref(out), stream_ptr))
+
+
+def nlo_subtracted_static(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, mask_ptr, prec,
+                          out, stream_ptr):
+    return check(lib().nlo_subtracted_static(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr,
+                                             mask_ptr, prec, ctypes.byref(out), stream_ptr))
 
 
 def nlo_set_fks_threshold(ctx, threshold):

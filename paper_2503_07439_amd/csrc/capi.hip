@@ -155,6 +155,42 @@ nlo_status use_device(const nlo_ctx* ctx, const char* fn) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// allocation-free FKS evaluation (nlo_subtracted_static)
+// ---------------------------------------------------------------------------
+// The workspace of up to SCRATCH_EVENTS events of any FKS sector lives in a
+// file-scope device array: (4 NR + 3) doubles and 2 indices per event (NR <= 6
+// particles) plus the bucket counters.  Each GPU holds its own copy at its own
+// address, found once per device by hipGetSymbolAddress at nlo_create; host
+// code uses that address, never the array's name.
+constexpr int64_t SCRATCH_EVENTS = 65536;
+constexpr size_t SCRATCH_BYTES = (size_t)SCRATCH_EVENTS * ((6 * 4 + 3) * sizeof(double) + 2 * sizeof(unsigned)) + 256;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// device address of this GPU's scratch array (called with no device change
+// visible to the caller: the previous current device is restored)
+nlo_status scratch_setup(int dev, const char* fn) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(NLO_EUNSUPPORTED, "%s: device %d beyond %d", fn, dev, SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return NLO_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(NLO_EDEVICE, "%s: hipGetDevice failed", fn);
+  if (cur != dev && hipSetDevice(dev) != hipSuccess) return fail(NLO_EDEVICE, "%s: hipSetDevice(%d) failed", fn, dev);
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p)
+    return fail(NLO_EDEVICE, "%s: address of the scratch array on device %d: %s", fn, dev, hipGetErrorString(e));
+  g_scratch_ptr[dev] = p;
+  return NLO_OK;
+}
+}  // namespace
+
 extern "C" {
 
 uint32_t nlo_abi_version(void) { return NLO_ABI_VERSION; }
@@ -172,6 +208,8 @@ nlo_status nlo_create(nlo_ctx** out, const nlo_params* params) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(NLO_EDEVICE, "nlo_create: no HIP device");
   if (params->device < 0 || params->device >= ndev)
     return fail(NLO_EINVAL, "nlo_create: device %d out of range [0, %d)", params->device, ndev);
+  nlo_status sst = scratch_setup(params->device, "nlo_create");
+  if (sst) return sst;
   nlo_ctx* c = new (std::nothrow) nlo_ctx;
   if (!c) return fail(NLO_ENOMEM, "nlo_create: out of host memory");
   c->params = *params;
@@ -358,6 +396,36 @@ nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int
   hipError_t err = launch_subtracted(ctx, sec, real_proc, n, ld, born_mom, xi_tilde, y, phi, mask, prec, out,
                                      ctx->ws, s);
   if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted: launch failed: %s", hipGetErrorString(err));
+  return NLO_OK;
+}
+
+nlo_status nlo_subtracted_static(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                                 const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                                 const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* hip_stream) {
+  const FksSector* sec = nullptr;
+  nlo_status st = check_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_mom, xi_tilde, y, phi, prec, out, &sec,
+                                   "nlo_subtracted_static");
+  if (st) return st;
+  if (n > SCRATCH_EVENTS)
+    return fail(NLO_EINVAL, "nlo_subtracted_static: n = %lld exceeds the static scratch (%lld events)", (long long)n,
+                (long long)SCRATCH_EVENTS);
+  if (fks_ws_bytes(real_proc, n) > SCRATCH_BYTES)
+    return fail(NLO_EINVAL, "nlo_subtracted_static: %zu bytes needed, scratch holds %zu", fks_ws_bytes(real_proc, n),
+                SCRATCH_BYTES);
+  if (n == 0) return NLO_OK;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    const int dev = ctx->params.device;
+    ws = (dev >= 0 && dev < SCRATCH_MAX_DEVICES) ? g_scratch_ptr[dev] : nullptr;
+  }
+  if (!ws) return fail(NLO_EDEVICE, "nlo_subtracted_static: no scratch address for device %d", ctx->params.device);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, "nlo_subtracted_static");
+  if (st) return st;
+  hipError_t err = launch_subtracted(ctx, sec, real_proc, n, ld, born_mom, xi_tilde, y, phi, mask, prec, out, ws,
+                                     (hipStream_t)hip_stream);
+  if (err != hipSuccess) return fail(NLO_EDEVICE, "nlo_subtracted_static: launch failed: %s", hipGetErrorString(err));
   return NLO_OK;
 }
 

@@ -1,20 +1,24 @@
 """Throughput benchmark: helicity- and colour-summed gg -> t tbar g |M|^2 on
 one MI355X, mixed precision (FP32 amplitudes, FP64 prologue and helicity sum,
-colour contraction on the faster unit for the process -- vector ALU at 6
-colour flows, the matrix-core variant timed beside it) against the plain
-FP64 GPU path, with the
-relative error of every event against the FP64 result and of a sample
-against the FP64 CPU oracle.
+colour contraction on the vector ALU; the matrix-core variant is timed
+beside it) against the plain FP64 GPU path, with the relative error of every
+event against the FP64 result and of a sample against the FP64 CPU oracle.
 
 One step = one nlo_me2 call over the whole batch (2^22 RAMBO events, m_t =
 173 GeV, sqrt(s_hat) uniform in [400, 2000] GeV), inputs resident in HBM.
 Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--no-cpu-baseline] [--no-mix] [--prec mixed|fp32|fp64]
+                    [--no-cpu-baseline] [--no-mix] [--no-configs] [--no-fks]
+                    [--prec mixed|fp32|fp64]
 
-Beside the headline line it times an uneven mix of Born, real and subtracted
-items as one captured-graph launch against per-item calls ("batch_mix").
+Beside the headline it times: the other |M|^2 configurations at their sizes
+(e+e- -> mu+mu- 2^14, e+e- -> u ubar g 2^20, g g -> t tbar 2^22), g g -> t
+tbar g g at 2^20 in every precision, the subtracted weight on the FKS stress
+sets (MIXED against FP64, routed fraction, errors), an uneven mix of Born,
+real and subtracted items as one captured-graph launch against per-item calls
+("batch_mix"), and the FP64 oracle on the host cores (cpu_baseline, which
+also holds the binary128 oracle's check of the subtracted weights).
 """
 import argparse
 import json
@@ -48,6 +52,8 @@ def parse():
     ap.add_argument("--no-mix", action="store_true", help="skip the batched-mix leg")
     ap.add_argument("--no-half", action="store_true", help="skip the FP16 leg")
     ap.add_argument("--no-gen", action="store_true", help="skip the device phase-space generation leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other |M|^2 configurations and gg->ttgg")
+    ap.add_argument("--no-fks", action="store_true", help="skip the subtracted-weight legs")
     ap.add_argument("--mask-study", action="store_true",
                     help="also time branch-free against compact cut masks on the 2^18 gg->ttgg (4,5) FKS set")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -70,6 +76,130 @@ def timed(ctx, proc, mom, out, prec, steps, warmup):
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def timed_fn(fn, steps, warmup=1):
+    """Average duration of fn() (launches on the current stream), HIP events."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def device_batch(ctx, proc, n, rs, stream):
+    """The batch recipe's points generated on the device (Philox + RAMBO;
+    bit-identical to the host recipe, see the phase-space tests)."""
+    lo, hi = rs if isinstance(rs, tuple) else (rs, rs)
+    mom, _ = ctx.phase_space(proc, n, (lo, hi), stream)
+    return mom
+
+
+def kernel_name(ctx, proc, prec):
+    if prec in ("fp16", "bf16"):
+        return "k_me2_pair<%s, %s>" % (proc, "f16x2" if prec == "fp16" else "bf16x2")
+    if prec == "fp64":
+        return "k_me2_valu<%s, double>" % proc
+    return "k_me2_mfma<%s>" % proc if ctx.colour_unit(proc, prec) == "mfma" else "k_me2_valu<%s, float>" % proc
+
+
+def flops_per_event(proc):
+    with open(os.path.join(ROOT, "paper_2503_07439_amd", "flops.json")) as f:
+        return json.load(f)[proc]["nested_flops_per_event_folded"]
+
+
+def configs_leg(ctx, steps):
+    """The other |M|^2 configurations at their sizes: time per batch, events/s,
+    vector-ALU and HBM fractions (FP64 and the mixed path)."""
+    from nlo_inputs.workloads import CONFIGS
+    rows = []
+    for name in ("ee_mumu_91", "ee_uug_1000", "gg_tt_400_2000"):
+        proc, n, rs, stream = CONFIGS[name]
+        mom = device_batch(ctx, proc, n, rs, stream)
+        npart = mom.shape[0]
+        fl = flops_per_event(proc)
+        for prec in ("mixed", "fp64"):
+            ms = timed_fn(lambda: ctx.me2(proc, mom, prec), steps)
+            eps = n / (ms * 1e-3)
+            rows.append({"workload": name, "precision": prec, "events": n, "ms": ms, "events_per_s": eps,
+                         "valu_frac": fl * eps / 1e12 / PEAK["fp64" if prec == "fp64" else "fp32"],
+                         "hbm_frac": (32 * npart + 8) * eps / 8e12, "kernel": kernel_name(ctx, proc, prec)})
+        del mom
+    return rows
+
+
+def gg_ttgg_leg(ctx, steps):
+    """g g -> t tbar g g, 2^20 points: every amplitude precision, with the
+    error against the FP64 GPU result (median, p99.9, summed)."""
+    import torch
+    from nlo_inputs.workloads import CONFIGS
+    proc, n, rs, stream = CONFIGS["gg_ttgg_400_2000"]
+    mom = device_batch(ctx, proc, n, rs, stream)
+    fl = flops_per_event(proc)
+    ctx.reserve(n)
+    res, rows = {}, []
+    for prec in ("fp64", "mixed", "fp16", "bf16"):
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        ms = timed_fn(lambda: ctx.me2(proc, mom, prec, out=out), max(2, steps))
+        res[prec] = out
+        row = {"precision": prec, "ms": ms, "events_per_s": n / (ms * 1e-3), "kernel": kernel_name(ctx, proc, prec),
+               "valu_frac": fl * n / (ms * 1e-3) / 1e12 / PEAK["fp64" if prec == "fp64" else
+                                                              ("fp32" if prec == "mixed" else prec)]}
+        if prec != "fp64":
+            rel = (out / res["fp64"] - 1).abs().cpu().numpy()
+            row["rel_err_vs_gpu_fp64"] = {"median": float(np.median(rel)), "p99_9": float(np.quantile(rel, 0.999)),
+                                          "max": float(rel.max()),
+                                          "summed": abs(float(out.sum()) / float(res["fp64"].sum()) - 1)}
+        rows.append(row)
+    del mom, res
+    return {"workload": "gg_ttgg_400_2000", "events": n, "flops_per_event": fl, "rows": rows}
+
+
+# FKS stress sets: Born points, xi_tilde and 1-|y| log-uniform in [1e-6, 1]
+FKS_SETS = [("ee_uug", 4, 2, "ee_uu", 1000.0, 1 << 16), ("gg_ttg", 4, -1, "gg_tt", (400.0, 2000.0), 1 << 20),
+            ("gg_ttgg", 4, 5, "gg_ttg", (400.0, 2000.0), 1 << 18)]
+
+
+def fks_leg(ctx, steps):
+    """The subtracted weight on the FKS stress sets: MIXED against FP64 time,
+    the fraction MIXED routes to FP64, the fraction whose W its precision does
+    not resolve to 1e-3 (status bit 3), and MIXED's error against FP64 on every
+    event.  Returns the rows and the inputs/outputs for the oracle sample."""
+    import torch
+    from nlo_inputs.workloads import events, fks_variables
+    rows, keep = [], []
+    for real, i, j, born, rs, n in FKS_SETS:
+        mom_np, _ = events(born, n, rs, stream=42)
+        xt_np, y_np, phi_np = fks_variables(n, stream=42, initial_state=j < 0)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        M, X, Y, P = t(mom_np), t(xt_np), t(y_np), t(phi_np)
+        ctx.reserve(n)
+        out, ms = {}, {}
+        for prec in ("mixed", "fp64", "fp32"):
+            ms[prec] = timed_fn(lambda: ctx.subtracted(real, i, j, M, X, Y, P, prec=prec), steps)
+            r = ctx.subtracted(real, i, j, M, X, Y, P, prec=prec)
+            torch.cuda.synchronize()
+            out[prec] = {k: r[k].cpu().numpy() for k in ("W", "status")}
+        st = out["mixed"]["status"]
+        rel = np.abs(out["mixed"]["W"] / out["fp64"]["W"] - 1)
+        rows.append({"sector": "%s (%d,%s)" % (real, i, j if j >= 0 else "beams"), "events": n,
+                     "ms_mixed": ms["mixed"], "ms_fp64": ms["fp64"], "ms_fp32": ms["fp32"],
+                     "mixed_speedup_vs_fp64": ms["fp64"] / ms["mixed"],
+                     "routed_to_fp64": float(((st & 2) != 0).mean()),
+                     "unresolved_mixed": float(((st & 8) != 0).mean()),
+                     "unresolved_fp64": float(((out["fp64"]["status"] & 8) != 0).mean()),
+                     "mixed_rel_err_vs_gpu_fp64": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+                                                   "p99_9": float(np.quantile(rel, 0.999)), "max": float(rel.max())}})
+        keep.append((real, i, j, mom_np, xt_np, y_np, phi_np, out))
+        del M, X, Y, P
+    return rows, keep
 
 
 def mix_leg(ctx, steps):
@@ -213,7 +343,7 @@ def host_info():
     return {"nproc": os.cpu_count(), "affinity": aff, "cpu_model": model}
 
 
-def cpu_baseline(proc, mom_full, target_s=12.0, target_1_s=3.0):
+def cpu_baseline(proc, mom_full, target_s=12.0, target_1_s=3.0, fks_keep=None):
     """The FP64 oracle, built for this host (g++ -O3 -march=native, no
     fast-math), on a bounded sample of the same workload (the first events of
     the batch): with every core this process may use (at most 16, the box's
@@ -235,11 +365,32 @@ def cpu_baseline(proc, mom_full, target_s=12.0, target_1_s=3.0):
     t = time.perf_counter()
     oracle.me2(proc, np.ascontiguousarray(mom_full[:, :, :n1]), nthreads=1, kind="native")
     dt1 = time.perf_counter() - t
+    fks = []
+    for real, i, j, mom_np, xt, y, phi, out in fks_keep or []:
+        n_all = mom_np.shape[2]
+        m = {"gg_ttgg": 96, "gg_ttg": 512}.get(real, 1024)
+        idx = np.arange(0, n_all, n_all // m) + 3
+        t = time.perf_counter()
+        q = oracle.fks(real, i, j, np.ascontiguousarray(mom_np[:, :, idx]), xt[idx], y[idx], phi[idx],
+                       nthreads=threads, kind="quad")
+        dtq = time.perf_counter() - t
+        terms = sum(np.abs(q[k]) for k in ("g_R", "g_S", "g_C", "g_SC", "g_Cm", "g_SCm"))
+        kap = q["xi"] * ((1 - q["y"]) if j >= 0 else (1 - q["y"]) * (1 + q["y"]))
+        row = {"sector": "%s (%d,%s)" % (real, i, j if j >= 0 else "beams"), "sample": "%d strided events" % len(idx),
+               "oracle_binary128_events_per_s": len(idx) / dtq}
+        for prec in ("mixed", "fp64"):
+            dW = np.abs(out[prec]["W"][idx] - q["W"])
+            rel = dW / np.abs(q["W"])
+            row[prec] = {"rel_err": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+                                     "max": float(rel.max())},
+                         "max_dW_over_D": float(np.max(dW * kap / terms)),
+                         "rel_err_unflagged_max": float(rel[(out[prec]["status"][idx] & 8) == 0].max())}
+        fks.append(row)
     return ref, {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
                  "sample": "first %d events of the batch, %.1f s (FP64 oracle: colour-ordered recursion, "
                            "std::thread over events, g++ -O3 -march=native)" % (n, dt),
                  "one_thread": {"value": n1 / dt1, "unit": "events/s", "sample": "first %d events, %.1f s" % (n1, dt1)},
-                 "host": hi}
+                 "host": hi, "fks_w_vs_binary128_oracle": fks}
 
 
 def main():
@@ -337,11 +488,13 @@ def main():
     # the other colour-contraction unit, for the record
     other = None
     if args.prec == "mixed":
-        mode_now = 2 if info.ncolour >= 12 else 1
-        ctx.set_kernel_config(proc, "mixed", 256, 3 - mode_now)
+        unit_now = ctx.colour_unit(proc, "mixed")
+        ctx.set_kernel_config(proc, "mixed", 256, 2 if unit_now == "valu" else 1)
+        other_unit = ctx.colour_unit(proc, "mixed")
         ms_o = timed(ctx, proc, mom, out, "mixed", max(3, args.steps // 4), 1)
         ctx.set_kernel_config(proc, "mixed", 256, 0)
-        other = {"colour_unit": "mfma" if mode_now == 1 else "valu", "ms_per_step": ms_o, "events_per_s": n / (ms_o * 1e-3)}
+        other = {"colour_unit": other_unit, "kernel": "k_me2_mfma<%s>" % proc if other_unit == "mfma" else
+                 "k_me2_valu<%s, float>" % proc, "ms_per_step": ms_o, "events_per_s": n / (ms_o * 1e-3)}
         print("other colour unit: %.3f ms per step" % ms_o, file=sys.stderr, flush=True)
 
     # algorithmic flops per event: exact count of the generated source of the
@@ -352,12 +505,7 @@ def main():
     flops_event = fl["nested_flops_per_event_folded"]
     achieved = flops_event * n / (ms * 1e-3) / 1e12
     peak = PEAK[args.prec if args.prec in PEAK else "fp32"]
-    unit = "mfma" if (args.prec == "mixed" and info.ncolour >= 12) else "valu"
-    if args.prec in ("fp16", "bf16"):
-        kernel = "k_me2_pair<%s, %s>" % (proc, "f16x2" if args.prec == "fp16" else "bf16x2")
-    else:
-        kernel = "k_me2_%s<%s%s>" % (unit, proc, ", float" if unit == "valu" and args.prec != "fp64" else
-                                     (", double" if args.prec == "fp64" else ""))
+    kernel = kernel_name(ctx, proc, args.prec)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(kernel, n), "kernel": kernel,
                 "flops_per_event": flops_event, "flops_per_event_as_written": fl["nested_flops_per_event"],
@@ -369,6 +517,22 @@ def main():
 
     study = mask_study(ctx, 3) if args.mask_study else None
 
+    others = None
+    if not args.no_configs:
+        others = configs_leg(ctx, max(3, args.steps // 4))
+        print("configs: " + ", ".join("%s %s %.3f ms" % (r["workload"], r["precision"], r["ms"]) for r in others),
+              file=sys.stderr, flush=True)
+    ttgg = None
+    if not args.no_configs:
+        ttgg = gg_ttgg_leg(ctx, 3)
+        print("gg_ttgg 2^20: " + ", ".join("%s %.2f ms" % (r["precision"], r["ms"]) for r in ttgg["rows"]),
+              file=sys.stderr, flush=True)
+    fks_rows, fks_keep = None, None
+    if not args.no_fks:
+        fks_rows, fks_keep = fks_leg(ctx, 3)
+        print("fks: " + ", ".join("%s mixed %.2f ms fp64 %.2f ms routed %.3f" % (
+            r["sector"], r["ms_mixed"], r["ms_fp64"], r["routed_to_fp64"]) for r in fks_rows), file=sys.stderr, flush=True)
+
     mix = None
     if not args.no_mix:
         mix = mix_leg(ctx, max(3, args.steps // 4))
@@ -376,7 +540,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        ref, cpu = cpu_baseline(proc, mom_np)
+        ref, cpu = cpu_baseline(proc, mom_np, fks_keep=fks_keep)
         k = ref.shape[0]
         r = np.abs(res[:k].cpu().numpy() / ref - 1)
         cpu["rel_err_of_gpu_%s_on_sample" % args.prec] = {
@@ -394,6 +558,7 @@ def main():
                    "helicities": info.ngood_hel},
         "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
         "half_precision": half, "device_generation": gen, "batch_mix": mix, "mask_study": study,
+        "other_configs": others, "gg_ttgg_2p20": ttgg, "fks_subtracted": fks_rows,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

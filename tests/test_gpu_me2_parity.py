@@ -1,12 +1,15 @@
 """Parity of the HIP |M|^2 path (through the C ABI) with the FP64 oracle,
 element by element on the same seeded inputs.
 
-Tolerances (relative, per event):
-  FP64           : median 1e-13, every event 1e-11 (same arithmetic type; the
-                   differences are rounding order over up to 159 amplitude
-                   terms with cancellations between them)
-  FP32 / MIXED   : median 1e-5, every event 1e-3 (float amplitudes; see the
-                   accuracy notes of the library)
+Tolerances (relative, per event), set a few times above what was measured:
+  FP64           : median 1e-14 (measured <= 3.0e-15), every event within
+                   1e-13 + 2e-15 c, where c = max over leg pairs of
+                   E_a E_b / |p_a.p_b| is the conditioning of the smallest
+                   pairwise invariant, which both codes form from O(sqrt s)
+                   momentum components (measured max 1.2e-12, u g -> t tbar u)
+  FP32 / MIXED   : median 1e-6 (measured <= 4.0e-7), every event 1e-5
+                   (measured <= 2.3e-6): float amplitudes and colour
+                   contraction, FP64 prologue and helicity sum
 """
 import numpy as np
 import pytest
@@ -33,6 +36,18 @@ def _rs(proc):
     return 1000.0 if proc.startswith("ee") else (400.0, 2000.0)
 
 
+def _cond(mom):
+    """max over leg pairs of E_a E_b / |p_a.p_b|"""
+    n = mom.shape[0]
+    c = np.zeros(mom.shape[2])
+    for a in range(n):
+        for b in range(a + 1, n):
+            pa, pb = mom[a], mom[b]
+            dot = pa[0] * pb[0] - pa[1] * pb[1] - pa[2] * pb[2] - pa[3] * pb[3]
+            c = np.maximum(c, pa[0] * pb[0] / np.abs(dot))
+    return c
+
+
 def _run(gpu, proc, mom, prec, block=None, colour_mode=0):
     import torch
     if block is not None:
@@ -53,9 +68,10 @@ def test_fp64_parity(gpu, orc, proc):
     ref = orc.me2(proc, mom)
     got = _run(gpu, proc, mom, "fp64")
     r = np.abs(got / ref - 1)
-    print(proc, "fp64 median", np.median(r), "max", r.max(), flush=True)
-    assert np.median(r) < 1e-13
-    assert np.all(r < 1e-11)
+    bound = 1e-13 + 2e-15 * _cond(mom)
+    print(proc, "fp64 median %.2e max %.2e max r/bound %.2f" % (np.median(r), r.max(), np.max(r / bound)), flush=True)
+    assert np.median(r) <= 1e-14
+    assert np.all(r <= bound)
 
 
 @pytest.mark.parametrize("prec,mode", [("fp32", 1), ("mixed", 2)])
@@ -66,9 +82,9 @@ def test_fp32_parity(gpu, orc, proc, prec, mode):
     ref = orc.me2(proc, mom)
     got = _run(gpu, proc, mom, prec, block=256, colour_mode=mode)
     r = np.abs(got / ref - 1)
-    print(proc, prec, "median", np.median(r), "max", r.max(), flush=True)
-    assert np.median(r) < 1e-5
-    assert np.all(r < 1e-3)
+    print(proc, prec, "median %.2e max %.2e" % (np.median(r), r.max()), flush=True)
+    assert np.median(r) <= 1e-6
+    assert np.all(r <= 1e-5)
 
 
 @pytest.mark.parametrize("block", [64, 128, 192])

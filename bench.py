@@ -17,8 +17,10 @@ Beside the headline it times: the other |M|^2 configurations at their sizes
 tbar g g at 2^20 in every precision, the subtracted weight on the FKS stress
 sets (MIXED against FP64, routed fraction, errors), an uneven mix of Born,
 real and subtracted items as one captured-graph launch against per-item calls
-("batch_mix"), and the FP64 oracle on the host cores (cpu_baseline, which
-also holds the binary128 oracle's check of the subtracted weights).
+("batch_mix"), the subtracted real emission integrated by VEGAS on the
+device (2^20 points per iteration, g g -> t tbar g and e+e- -> u ubar g), and
+the FP64 oracle on the host cores (cpu_baseline, which also holds the
+binary128 oracle's check of the subtracted weights).
 """
 import argparse
 import json
@@ -54,6 +56,7 @@ def parse():
     ap.add_argument("--no-gen", action="store_true", help="skip the device phase-space generation leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the other |M|^2 configurations and gg->ttgg")
     ap.add_argument("--no-fks", action="store_true", help="skip the subtracted-weight legs")
+    ap.add_argument("--no-integrate", action="store_true", help="skip the device integration leg")
     ap.add_argument("--mask-study", action="store_true",
                     help="also time branch-free against compact cut masks on the 2^18 gg->ttgg (4,5) FKS set")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -200,6 +203,30 @@ def fks_leg(ctx, steps):
         keep.append((real, i, j, mom_np, xt_np, y_np, phi_np, out))
         del M, X, Y, P
     return rows, keep
+
+
+INTEGRATE_SETS = [("gg_ttg", 600.0), ("ee_uug", 1000.0)]
+
+
+def integrate_leg(ctx):
+    """The subtracted real emission integrated over its phase space on the
+    device (VEGAS, 2^20 points per iteration, 10 iterations, the first 3 only
+    adapting the grid; summed over the FKS sectors): wall time of one whole
+    call (it ends with a stream synchronisation), FP64 and MIXED."""
+    rows = []
+    n, niter, nadapt = 1 << 20, 10, 3
+    for real, rs in INTEGRATE_SETS:
+        for prec in ("fp64", "mixed"):
+            ctx.integrate_subtracted(real, rs, n, niter, nadapt, 330, prec)      # warm-up
+            t = time.perf_counter()
+            sig, err, chi, its = ctx.integrate_subtracted(real, rs, n, niter, nadapt, 330, prec)
+            dt = time.perf_counter() - t
+            rows.append({"process": real, "sqrt_s_born_GeV": rs, "precision": prec, "points_per_iteration": n,
+                         "iterations": niter, "adapt_only": nadapt, "s_per_call": dt,
+                         "ms_per_iteration": dt * 1e3 / niter, "points_per_s": n * niter / dt,
+                         "sigma_pb": sig, "error_pb": err, "chi2_dof": chi,
+                         "first_iteration_error_pb": its[0][1], "last_iteration_error_pb": its[-1][1]})
+    return rows
 
 
 def mix_leg(ctx, steps):
@@ -533,6 +560,12 @@ def main():
         print("fks: " + ", ".join("%s mixed %.2f ms fp64 %.2f ms routed %.3f" % (
             r["sector"], r["ms_mixed"], r["ms_fp64"], r["routed_to_fp64"]) for r in fks_rows), file=sys.stderr, flush=True)
 
+    integ = None
+    if not args.no_integrate:
+        integ = integrate_leg(ctx)
+        print("integrate: " + ", ".join("%s %s %.1f ms/iteration" % (r["process"], r["precision"], r["ms_per_iteration"])
+                                        for r in integ), file=sys.stderr, flush=True)
+
     mix = None
     if not args.no_mix:
         mix = mix_leg(ctx, max(3, args.steps // 4))
@@ -558,7 +591,7 @@ def main():
                    "helicities": info.ngood_hel},
         "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
         "half_precision": half, "device_generation": gen, "batch_mix": mix, "mask_study": study,
-        "other_configs": others, "gg_ttgg_2p20": ttgg, "fks_subtracted": fks_rows,
+        "other_configs": others, "gg_ttgg_2p20": ttgg, "fks_subtracted": fks_rows, "integrated_subtracted": integ,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -195,6 +195,18 @@ typedef struct {
                           with D = sum|g_X| / kappa, exceeds 1e-3 |W|) */
   double* real_mom;   /* [npart_real][4][ld] real-emission momenta in event order */
   double* w_sum;      /* [1] fixed-order FP64 sum of W over the batch */
+  /* [n] the subtracted cross section per unit Born phase space and per unit
+   * xi_tilde, y, phi, in GeV^-2 (the integrand of nlo_integrate_subtracted):
+   *   dsig = xi_max / (2 s_B) [j g_R - j(0,y) g_S - j(xi,1) g_C + j(0,1) g_SC] / (xi (1-y))
+   * (initial state: both collinear ends as in W), where the map's phase-space
+   * factor j enters every term at its own kinematics.  Final-state emitter:
+   *   dPhi_{n+1} = dPhi_n xi j dxi dy dphi,  j = s E_j / (64 pi^3 Ebar_j (1 - xi (1-y)/2)),
+   * j(0,y) = s/(64 pi^3), j(xi,1) = z s/(64 pi^3).  Beams: at fixed real energy
+   * dPhi_{n+1}(s_R) = s_R xi/(64 pi^3) dxi dy dphi dPhi_n(s_R (1-xi)); with the
+   * real flux 1/(2 s_R) and incoming momentum fractions x_1 x_2 = xbar_1 xbar_2/(1-xi)
+   * at fixed Born kinematics, j = s_B/(64 pi^3 (1-xi)), j(0,y) = s_B/(64 pi^3). */
+  double* dsig;
+  double* jac;        /* [n] xi_max j: dPhi_{n+1} = dPhi_n xi jac dxi_tilde dy dphi (beams: as above) */
 } nlo_fks_out;
 
 /* FKS-subtracted real emission for one FKS sector (the paper's FKS
@@ -336,6 +348,31 @@ nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t st
  * synchronises the stream before returning.  error_pb may be NULL. */
 nlo_status nlo_cross_section(nlo_ctx* ctx, int proc_id, int64_t n, uint32_t seed, uint32_t stream, double sqrt_s,
                              nlo_prec prec, double* sigma_pb, double* error_pb, void* hip_stream);
+
+/* Subtracted real-emission cross section of real_proc at fixed Born energy,
+ * summed over its FKS sectors, by adaptive Monte Carlo on the device (the
+ * paper's fixed-order integration, section "Monte-Carlo integration", with
+ * importance sampling):
+ *   sigma = sum_sectors int dPhi_B(s_B) int dxi_tilde dy dphi dsig,   in pb,
+ * dsig as in nlo_fks_out (the subtracted weight with the map's phase-space
+ * factor), dPhi_B the Born phase space at sqrt(s_B) = sqrt_s_born (beams along
+ * +-z).  Integration variables: the 4 RAMBO uniforms of every Born final-state
+ * particle and xi_tilde, (1+y)/2, phi/(2 pi), each on its own VEGAS grid
+ * (Lepage's algorithm, 50 bins, damping alpha = 1.5), refined after every
+ * iteration from the per-bin sums of f^2.  n points per iteration (2 <= n <=
+ * 2^20), niter iterations; the first nadapt only shape the grid, the others
+ * are combined with inverse-variance weights (error_pb: its standard error,
+ * chi2_dof: their chi^2 per degree of freedom).  Uniforms: Philox (seed,
+ * stream), point k of iteration t at counter t n + k, slot d/2 for variable d.
+ * Every reduction runs in a fixed order, so a result is reproducible bit for
+ * bit.  iterations (host, may be NULL): [niter][2] per-iteration estimate and
+ * standard error.  Uses the context workspace (nlo_reserve(ctx, n) covers it)
+ * and synchronises the stream before returning.  prec: FP64, FP32 or MIXED.
+ * A point whose integrand is not finite counts as zero and makes the call
+ * return NLO_EDEVICE after filling the outputs. */
+nlo_status nlo_integrate_subtracted(nlo_ctx* ctx, int real_proc, double sqrt_s_born, int64_t n, int niter,
+                                    int nadapt, uint32_t seed, uint32_t stream, nlo_prec prec, double* sigma_pb,
+                                    double* error_pb, double* chi2_dof, double* iterations, void* hip_stream);
 
 #ifdef __cplusplus
 }

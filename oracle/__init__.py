@@ -172,7 +172,7 @@ def wavefunction(proc, p_aos, leg, lam):
     return out[0::2] + 1j * out[1::2]
 
 
-FKS_FIELDS = ["xi", "y", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "W", "me2_R", "B", "S"]
+FKS_FIELDS = ["xi", "y", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "W", "me2_R", "B", "S", "jac", "dsig"]
 
 
 def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=None, want_real=False, kind="double"):
@@ -189,7 +189,7 @@ def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=None, want_real=Fa
     xi_tilde = np.ascontiguousarray(np.broadcast_to(xi_tilde, (n,)), dtype=np.float64)
     y = np.ascontiguousarray(np.broadcast_to(y, (n,)), dtype=np.float64)
     phi = np.ascontiguousarray(np.broadcast_to(phi, (n,)), dtype=np.float64)
-    out = np.empty((n, 12))
+    out = np.empty((n, 14))
     nreal = born_mom.shape[0] + 1
     real = np.empty((nreal, 4, n)) if want_real else None
     rc = f(pid(real_proc), i, j, n, _dp(born_mom), _dp(xi_tilde), _dp(y), _dp(phi), _dp(out),
@@ -199,6 +199,25 @@ def fks(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=None, want_real=Fa
     if want_real:
         res["real_mom"] = real
     return res
+
+
+def fks_map(real_proc, i, j, born_mom, xi_tilde, y, phi, nthreads=None, kind="double"):
+    """The FKS map of pair (i, j) without matrix elements: (xi, jac, real momenta
+    SoA [nreal][4][n]), jac as in fks()."""
+    L = lib(kind)
+    if nthreads is None:
+        nthreads = threads()
+    f = L.orc_fks_map
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [ctypes.POINTER(ctypes.c_double)] * 6 + [ctypes.c_int]
+    born_mom = np.ascontiguousarray(born_mom, dtype=np.float64)
+    n = born_mom.shape[2]
+    bc = lambda a: np.ascontiguousarray(np.broadcast_to(a, (n,)), dtype=np.float64)
+    xi_tilde, y, phi = bc(xi_tilde), bc(y), bc(phi)
+    out = np.empty((n, 2))
+    real = np.empty((born_mom.shape[0] + 1, 4, n))
+    rc = f(pid(real_proc), i, j, n, _dp(born_mom), _dp(xi_tilde), _dp(y), _dp(phi), _dp(out), _dp(real), nthreads)
+    assert rc == 0, rc
+    return out[:, 0].copy(), out[:, 1].copy(), real
 
 
 def born_correlations(proc, mom):

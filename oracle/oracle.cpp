@@ -1408,10 +1408,39 @@ static Real sector_soft(const FksDef& d, const V4* kb, const int* bmap, Real sqr
 
 struct FksOut {
   Real xi, y, gR, gS, gC, gCm, gSC, gSCm, W, me2R, B, S;
+  Real jac, dsig;   // xi_max j(xi, y), and the subtracted cross-section density (see below)
 };
 
+// The map's phase-space factor j (dPhi_{n+1} = dPhi_n xi j dxi dy dphi) and
+// the subtracted cross section per unit Born phase space and per unit
+// xi_tilde, y, phi, with j taken at the kinematics of every term:
+//   dsig = xi_max / (2 s_B) [j g_R - j(0,y) g_S - j(xi,1) g_C + j(0,1) g_SC] / (xi (1-y))
+// Final-state emitter (massless i, j; recoil system of fixed mass): from
+//   d3k_i d3k_j / (4 E_i E_j) = (1/4) E_i E_j dE_i dE_j dOmega dy dphi and
+//   E_j fixed by the recoil mass, j = s E_j / (64 pi^3 Ebar_j (1 - xi (1-y)/2)),
+//   j(0, y) = s / (64 pi^3), j(xi, 1) = z s / (64 pi^3).
+// Beams: at fixed real energy d3k_i/(2 E_i (2 pi)^3) dPhi_n(K) gives
+//   dPhi_{n+1}(s_R) = s_R xi / (64 pi^3) dxi dy dphi dPhi_n(s_R (1-xi)); with the
+//   real flux 1/(2 s_R) and x_1 x_2 = xbar_1 xbar_2 / (1-xi) at fixed Born
+//   kinematics this is j = s_B / (64 pi^3 (1-xi)) against the Born flux, and
+//   j(0, y) = s_B / (64 pi^3).
+static void fks_density(FksOut& o, bool final_state, Real sb, Real xmax, Real jr, Real z) {
+  const Real j0 = sb / (64 * PI * PI * PI);
+  const Real xi = o.xi, y = o.y;
+  Real num;
+  if (final_state) {
+    num = (jr * o.gR - j0 * o.gS - z * j0 * o.gC + j0 * o.gSC) / (xi * (1 - y));
+  } else {
+    num = (jr * (o.gR - (1 + y) / 2 * o.gC - (1 - y) / 2 * o.gCm)
+           - j0 * (o.gS - (1 + y) / 2 * o.gSC - (1 - y) / 2 * o.gSCm)) / (xi * (1 - y) * (1 + y));
+  }
+  o.jac = xmax * jr;
+  o.dsig = xmax * num / (2 * sb);
+}
+
 // one event of the FKS-subtracted real emission for pair (i, j)
-static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit, Real y, Real phi, V4* kreal) {
+static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit, Real y, Real phi, V4* kreal,
+                        bool map_only = false) {
   // The Born point is on shell and conserves momentum by definition.  An
   // input rounded to double does neither exactly (at the 1e-16 level), and
   // the real emission meets its counterterms only as closely as it does: a
@@ -1490,6 +1519,11 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit
     s_real = sb; sqs_real = sqs_b;
     o.xi = xi;
     eperp = V4{{0, ep[0], ep[1], ep[2]}};
+    const Real jr = sb / (64 * PI * PI * PI) * (Ej / kj.v[0]) / (1 - xi * (1 - y) / 2);
+    if (map_only) {
+      o.jac = xmax * jr;
+      return o;
+    }
     // real matrix element and sector function
     o.me2R = me2_event(d.real, kreal, nullptr);
     o.S = sector_value(d, kreal, sqs_real, i, j);
@@ -1528,6 +1562,7 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit
     o.gC = 2.0 * xi * g2 / (sqs_b * Ejc) * P * Sc;
     o.gSC = 8.0 * g2 * Cj / sb * B;
     o.W = (o.gR - o.gS - o.gC + o.gSC) / (xi * (1.0 - y));
+    fks_density(o, true, sb, xmax, jr, z);
   } else {
     // ---------------- initial-state emitter (both beams) ------------------
     for (int r = 0, b = 0; r < d.nreal; ++r) {
@@ -1554,6 +1589,10 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit
     s_real = sr; sqs_real = sqr;
     o.xi = xi;
     eperp = V4{{0, cphi, sphi, 0}};
+    if (map_only) {
+      o.jac = xmax * sb / (64 * PI * PI * PI) / (1 - xi);
+      return o;
+    }
     o.me2R = me2_event(d.real, kreal, nullptr);
     o.S = sector_value(d, kreal, sqs_real, i, -1);
     o.gR = xi * xi * (1.0 - y) * (1.0 + y) * o.me2R * o.S;
@@ -1583,6 +1622,7 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit
       o.gSC = 0.0;
       o.gSCm = 0.0;
       o.W = (o.gR - 0.5 * (1.0 + y) * o.gC - 0.5 * (1.0 - y) * o.gCm) / (xi * (1.0 - y) * (1.0 + y));
+      fks_density(o, false, sb, xmax, sb / (64 * PI * PI * PI) / (1 - xi), 0);
       return o;
     }
     Real B;
@@ -1620,6 +1660,7 @@ static FksOut fks_event(const FksDef& d, int i, int j, const V4* kb_in, Real xit
     o.gC = gc[0]; o.gCm = gc[1]; o.gSC = gsc[0]; o.gSCm = gsc[1];
     o.W = (o.gR - o.gS - 0.5 * (1.0 + y) * (o.gC - o.gSC) - 0.5 * (1.0 - y) * (o.gCm - o.gSCm))
           / (xi * (1.0 - y) * (1.0 + y));
+    fks_density(o, false, sb, xmax, sb / (64 * PI * PI * PI) / (1 - xi), 0);
   }
   (void)s_real;
   return o;
@@ -1629,8 +1670,8 @@ extern "C" {
 
 // FKS-subtracted real emission.  real_proc in {ee_uug, gg_ttg, gg_ttgg, uu_ttg, ug_ttu};
 // (i, j) an FKS pair of that process (j = -1: initial state).  born_mom: SoA
-// [nborn][4][n]; xi_tilde, y, phi: [n].  out: [n][12] = xi, y, g_R, g_S, g_C,
-// g_Cm, g_SC, g_SCm, W, |M_R|^2, B, S.  real_out (optional): SoA [nreal][4][n].
+// [nborn][4][n]; xi_tilde, y, phi: [n].  out: [n][14] = xi, y, g_R, g_S, g_C,
+// g_Cm, g_SC, g_SCm, W, |M_R|^2, B, S, jac, dsig.  real_out (optional): SoA [nreal][4][n].
 int orc_fks(int real_proc, int i, int j, int64_t n, const double* born_mom, const double* xit, const double* y,
             const double* phi, double* out, double* real_out, int nthreads) {
   init_colour();
@@ -1644,9 +1685,31 @@ int orc_fks(int real_proc, int i, int j, int64_t n, const double* born_mom, cons
     V4 kb[8], kr[8];
     load_event(born_mom, n, e, d.nborn, kb);
     FksOut o = fks_event(d, i, j, kb, xit[e], y[e], phi[e], kr);
-    double* r = out + e * 12;
+    double* r = out + e * 14;
     r[0] = o.xi; r[1] = o.y; r[2] = o.gR; r[3] = o.gS; r[4] = o.gC; r[5] = o.gCm; r[6] = o.gSC; r[7] = o.gSCm;
-    r[8] = o.W; r[9] = o.me2R; r[10] = o.B; r[11] = o.S;
+    r[8] = o.W; r[9] = o.me2R; r[10] = o.B; r[11] = o.S; r[12] = o.jac; r[13] = o.dsig;
+    if (real_out)
+      for (int k = 0; k < d.nreal; ++k)
+        for (int m = 0; m < 4; ++m) real_out[(k * 4 + m) * n + e] = kr[k].v[m];
+  });
+  return 0;
+}
+
+// The FKS map alone (no matrix elements): out [n][2] = xi, jac (as in
+// orc_fks), real_out SoA [nreal][4][n].
+int orc_fks_map(int real_proc, int i, int j, int64_t n, const double* born_mom, const double* xit, const double* y,
+                const double* phi, double* out, double* real_out, int nthreads) {
+  FksDef d = fks_def(real_proc);
+  if (d.born < 0) return 1;
+  bool ok = false;
+  for (const FksPair& q : d.pairs) if (q.i == i && q.j == j) ok = true;
+  if (!ok) return 2;
+  parallel_for(n, nthreads, [&](int64_t e) {
+    V4 kb[8], kr[8];
+    load_event(born_mom, n, e, d.nborn, kb);
+    FksOut o = fks_event(d, i, j, kb, xit[e], y[e], phi[e], kr, true);
+    out[e * 2] = o.xi;
+    out[e * 2 + 1] = o.jac;
     if (real_out)
       for (int k = 0; k < d.nreal; ++k)
         for (int m = 0; m < 4; ++m) real_out[(k * 4 + m) * n + e] = kr[k].v[m];

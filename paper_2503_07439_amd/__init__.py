@@ -11,7 +11,7 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_subtracted, nlo_subtracted_static, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
                    nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
-                   nlo_me2_checked, nlo_reserve, nlo_colour_unit)
+                   nlo_me2_checked, nlo_reserve, nlo_colour_unit, nlo_integrate_subtracted)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -89,7 +89,7 @@ class Context:
         """"valu" or "mfma": the colour-contraction unit (proc, prec) runs on."""
         return {1: "valu", 2: "mfma"}[nlo_colour_unit(self.ctx, proc_id(proc), PREC[prec])]
 
-    FKS_FIELDS = ("W", "xi", "born", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm")
+    FKS_FIELDS = ("W", "xi", "born", "g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm", "dsig", "jac")
 
     def subtracted(self, real, fks_i, fks_j, born_mom, xi_tilde, y, phi, prec="fp64", mask=None,
                    want_real=False, want_sum=False):
@@ -173,6 +173,14 @@ class Context:
         nlo_fks_variables(self.ctx, n, seed, stream, first, 1 if initial_state else 0, xt.data_ptr(), y.data_ptr(),
                           phi.data_ptr(), self._stream())
         return xt, y, phi
+
+    def integrate_subtracted(self, real, sqrt_s_born, n, niter, nadapt, stream, prec="fp64", seed=SEED):
+        """Subtracted real-emission cross section at fixed Born energy, summed
+        over the FKS sectors, by VEGAS on the device: (sigma, error, chi2/dof,
+        per-iteration [(mean, error)]) in pb."""
+        self.reserve(n)
+        return nlo_integrate_subtracted(self.ctx, proc_id(real), float(sqrt_s_born), n, niter, nadapt, seed, stream,
+                                        PREC[prec], self._stream())
 
     def cross_section(self, proc, n, sqrt_s, stream, prec="fp64", seed=SEED):
         """(sigma, error) in pb at fixed sqrt(s_hat), plain Monte Carlo on the device."""

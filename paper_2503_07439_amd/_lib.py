@@ -33,7 +33,8 @@ class nlo_fks_out(ctypes.Structure):
     _fields_ = [("W", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("born", ctypes.c_void_p),
                 ("g_R", ctypes.c_void_p), ("g_S", ctypes.c_void_p), ("g_C", ctypes.c_void_p),
                 ("g_Cm", ctypes.c_void_p), ("g_SC", ctypes.c_void_p), ("g_SCm", ctypes.c_void_p),
-                ("status", ctypes.c_void_p), ("real_mom", ctypes.c_void_p), ("w_sum", ctypes.c_void_p)]
+                ("status", ctypes.c_void_p), ("real_mom", ctypes.c_void_p), ("w_sum", ctypes.c_void_p),
+                ("dsig", ctypes.c_void_p), ("jac", ctypes.c_void_p)]
 
 
 class nlo_work_item(ctypes.Structure):
@@ -70,6 +71,10 @@ SIGNATURES = {
     "nlo_me2": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "nlo_me2_checked": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "nlo_reserve": ([_VP, _I64], ctypes.c_int),
+    "nlo_integrate_subtracted": ([_VP, ctypes.c_int, ctypes.c_double, _I64, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), _VP], ctypes.c_int),
     "nlo_colour_unit": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "nlo_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP, _VP,
                         ctypes.c_int, ctypes.POINTER(nlo_fks_out), _VP], ctypes.c_int),
@@ -165,6 +170,15 @@ def nlo_me2_checked(ctx, proc_id, n, ld, mom_ptr, me2_ptr, status_ptr, prec, str
 
 def nlo_reserve(ctx, n):
     return check(lib().nlo_reserve(ctx, n))
+
+
+def nlo_integrate_subtracted(ctx, real_proc, sqrt_s_born, n, niter, nadapt, seed, stream, prec, stream_ptr):
+    """(sigma_pb, error_pb, chi2_dof, per-iteration [(mean, error)])"""
+    sig, err, chi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    it = (ctypes.c_double * (2 * niter))()
+    check(lib().nlo_integrate_subtracted(ctx, real_proc, sqrt_s_born, n, niter, nadapt, seed, stream, prec,
+                                         ctypes.byref(sig), ctypes.byref(err), ctypes.byref(chi), it, stream_ptr))
+    return sig.value, err.value, chi.value, [(it[2 * k], it[2 * k + 1]) for k in range(niter)]
 
 
 def nlo_colour_unit(ctx, proc_id, prec):

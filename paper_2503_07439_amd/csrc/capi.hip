@@ -283,12 +283,39 @@ size_t xs_ws_bytes(int npart, int64_t m) {
 
 constexpr int64_t XS_CHUNK = (int64_t)1 << 20;
 
+// the sectors of a real process, in table order
+int fks_sectors(int real_proc, const FksSector** out, int max) {
+  int k = 0;
+  for (const FksSector& f : FKS_TABLE)
+    if (f.real == real_proc && k < max) out[k++] = &f;
+  return k;
+}
+
+// nlo_integrate_subtracted with n points per iteration and niter iterations:
+// the FKS workspace, then Born momenta, weights, radiation variables, one
+// dsig and one W array per sector, f, bin indices, histogram partials, the
+// histogram, the grid, partial sums, per-iteration sums and a counter
+size_t int_ws_bytes(int real_proc, int64_t n, int niter) {
+  const FksSector* secs[8];
+  const int ns = fks_sectors(real_proc, secs, 8);
+  if (!ns) return 0;
+  const int nb = PROC_STATIC[secs[0]->born].npart;
+  const int D = 4 * (nb - 2) + 3;
+  const size_t dbl = (size_t)n * (nb * 4 + 4 + 2 * ns + 1) + (size_t)VEGAS_HIST_BLOCKS * D * VEGAS_BINS +
+                     (size_t)D * VEGAS_BINS + (size_t)D * (VEGAS_BINS + 1) + XS_PART_DOUBLES + 2 * (size_t)niter + 64;
+  return fks_ws_bytes(real_proc, n) + 256 + dbl * sizeof(double) + (size_t)n * D + 256;
+}
+
+constexpr int INT_MAX_ITER = 64;
+
 // workspace that serves every evaluation call of up to n events: the largest
-// FKS sector, a half-width |M|^2 launch and a cross-section chunk
+// FKS sector, a half-width |M|^2 launch, a cross-section chunk and an
+// integration of up to min(n, 2^20) points per iteration
 size_t ws_bytes_for(int64_t n) {
   size_t b = half_ws_bytes(n);
   for (const FksSector& f : FKS_TABLE) b = std::max(b, fks_ws_bytes(f.real, n));
   for (int p = 0; p < NPROC_; ++p) b = std::max(b, xs_ws_bytes(PROC_STATIC[p].npart, std::min(n, XS_CHUNK)));
+  for (const FksSector& f : FKS_TABLE) b = std::max(b, int_ws_bytes(f.real, std::min(n, XS_CHUNK), INT_MAX_ITER));
   return b;
 }
 
@@ -329,6 +356,8 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.gSC = out->g_SC;
   a.gSCm = out->g_SCm;
   a.W = out->W;
+  a.dsig = out->dsig;
+  a.jac = out->jac;
   a.status = out->status;
   a.real_out = out->real_mom;
   const int block = 256;
@@ -866,6 +895,118 @@ nlo_status nlo_cross_section(nlo_ctx* ctx, int proc_id, int64_t n, uint32_t seed
   const double mean = h[0] / (double)n;
   *sigma_pb = mean;
   if (error_pb) *error_pb = std::sqrt(std::max(0.0, h[1] / (double)n - mean * mean) / (double)(n - 1));
+  return NLO_OK;
+}
+
+nlo_status nlo_integrate_subtracted(nlo_ctx* ctx, int real_proc, double sqrt_s_born, int64_t n, int niter,
+                                    int nadapt, uint32_t seed, uint32_t stream, nlo_prec prec, double* sigma_pb,
+                                    double* error_pb, double* chi2_dof, double* iterations, void* hip_stream) {
+  const char* fn = "nlo_integrate_subtracted";
+  nlo_status st = check_ctx(ctx, real_proc, fn);
+  if (st) return st;
+  const FksSector* secs[8];
+  const int ns = fks_sectors(real_proc, secs, 8);
+  if (!ns) return fail(NLO_EUNSUPPORTED, "%s: process %s has no FKS sectors", fn, PROC_STATIC[real_proc].name);
+  if (n < 2 || n > XS_CHUNK) return fail(NLO_EINVAL, "%s: need 2 <= n <= 2^20 points per iteration", fn);
+  if (niter < 1 || niter > INT_MAX_ITER || nadapt < 0 || nadapt >= niter)
+    return fail(NLO_EINVAL, "%s: need 0 <= nadapt < niter <= %d", fn, INT_MAX_ITER);
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "%s: precision %d not supported (FP64, FP32, MIXED)", fn, (int)prec);
+  if (!sigma_pb) return fail(NLO_EINVAL, "%s: sigma_pb is NULL", fn);
+  const int born = secs[0]->born;
+  const ProcStatic& B = PROC_STATIC[born];
+  const int nf = B.npart - 2, D = 4 * nf + 3;
+  if (nf < 2 || nf > 3) return fail(NLO_EUNSUPPORTED, "%s: Born %s not supported", fn, B.name);
+  VegasArgs va{};
+  double msum = 0.0;
+  for (int k = 2; k < B.npart; ++k) {
+    va.mass[k - 2] = (B.top_legs >> k) & 1u ? ctx->params.m_top : 0.0;
+    msum += va.mass[k - 2];
+  }
+  if (!(sqrt_s_born > msum) || !std::isfinite(sqrt_s_born))
+    return fail(NLO_EINVAL, "%s: need %g < sqrt_s_born < inf", fn, msum);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  st = check_ws(ctx, int_ws_bytes(real_proc, n, niter), n, fn);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // carve the workspace: the FKS part first (nlo_subtracted's layout), then ours
+  char* base = static_cast<char*>(ctx->ws);
+  const size_t fks_b = (fks_ws_bytes(real_proc, n) + 255) & ~size_t(255);
+  double* dp = reinterpret_cast<double*>(base + fks_b);
+  double* mom = dp;            dp += (size_t)n * B.npart * 4;
+  double* w = dp;              dp += n;
+  double* xit = dp;            dp += n;
+  double* yv = dp;             dp += n;
+  double* phi = dp;            dp += n;
+  double* dsig = dp;           dp += (size_t)n * ns;
+  double* wsc = dp;            dp += (size_t)n * ns;
+  double* f = dp;              dp += n;
+  double* part = dp;           dp += (size_t)VEGAS_HIST_BLOCKS * D * VEGAS_BINS;
+  double* hist = dp;           dp += (size_t)D * VEGAS_BINS;
+  double* edges = dp;          dp += (size_t)D * (VEGAS_BINS + 1);
+  double* xs_part = dp;        dp += XS_PART_DOUBLES;
+  double* acc = dp;            dp += 2 * (size_t)niter;
+  unsigned* dropped = reinterpret_cast<unsigned*>(dp);
+  dp += 8;
+  uint8_t* bins = reinterpret_cast<uint8_t*>(dp);
+  va.n = n;
+  va.seed = seed;
+  va.stream = stream;
+  va.rs = sqrt_s_born;
+  va.edges = edges;
+  va.mom = mom;
+  va.w = w;
+  va.xit = xit;
+  va.y = yv;
+  va.phi = phi;
+  va.bins = bins;
+  const double conv = 0.3893793721e9;   // GeV^-2 -> pb
+  hipError_t e = launch_vegas_init(D, edges, dropped, s);
+  for (int it = 0; it < niter && e == hipSuccess; ++it) {
+    va.first = (uint64_t)it * (uint64_t)n;
+    e = launch_vegas_points(nf, va, s);
+    for (int k = 0; k < ns && e == hipSuccess; ++k) {
+      nlo_fks_out o{};
+      o.W = wsc + (size_t)k * n;
+      o.dsig = dsig + (size_t)k * n;
+      e = launch_subtracted(ctx, secs[k], real_proc, n, n, mom, xit, yv, phi, nullptr, prec, &o, ctx->ws, s);
+    }
+    if (e == hipSuccess)
+      e = launch_vegas_update(n, D, ns, dsig, w, conv, f, dropped, bins, part, hist, xs_part, acc + 2 * it,
+                              it + 1 < niter, 1.5, edges, s);
+  }
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  std::vector<double> h(2 * (size_t)niter);
+  unsigned nd = 0;
+  if (hipMemcpyAsync(h.data(), acc, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&nd, dropped, sizeof nd, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(NLO_EDEVICE, "%s: result copy failed", fn);
+  // iterations from nadapt on, combined with inverse-variance weights
+  double sw = 0.0, swi = 0.0;
+  std::vector<double> mean(niter), var(niter);
+  for (int it = 0; it < niter; ++it) {
+    mean[it] = h[2 * it] / (double)n;
+    var[it] = std::max(0.0, h[2 * it + 1] / (double)n - mean[it] * mean[it]) / (double)(n - 1);
+    if (iterations) {
+      iterations[2 * it] = mean[it];
+      iterations[2 * it + 1] = std::sqrt(var[it]);
+    }
+    if (it >= nadapt && var[it] > 0.0) {
+      sw += 1.0 / var[it];
+      swi += mean[it] / var[it];
+    }
+  }
+  const double res = sw > 0.0 ? swi / sw : mean[niter - 1];
+  double chi = 0.0;
+  for (int it = nadapt; it < niter; ++it)
+    if (var[it] > 0.0) chi += (mean[it] - res) * (mean[it] - res) / var[it];
+  *sigma_pb = res;
+  if (error_pb) *error_pb = sw > 0.0 ? 1.0 / std::sqrt(sw) : 0.0;
+  if (chi2_dof) *chi2_dof = niter - nadapt > 1 ? chi / (niter - nadapt - 1) : 0.0;
+  if (nd) return fail(NLO_EDEVICE, "%s: %u points gave a non-finite integrand", fn, nd);
   return NLO_OK;
 }
 

@@ -43,6 +43,8 @@ struct FksKin {
   double ejc, z;  // FSR: E_J at y = 1 and its momentum fraction there
   double omz;     // FSR: 1 - z = E_I / E_J(Born), formed without cancellation
   double ei, ej;  // energies of partons I and J (FSR), or of I and of each beam (ISR)
+  double ejb;     // FSR: energy of the Born emitter
+  double xmax;    // xi_max
 };
 
 __device__ __forceinline__ double d3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -148,6 +150,8 @@ __device__ void fks_map(const double (&kb)[S::NB][4], double xit, double y, doub
     K.omz = ei / kj[0];
     K.ei = ei;
     K.ej = ej;
+    K.ejb = kj[0];
+    K.xmax = 1.0 - mrec2 / K.sb;
   } else {
     const double xi = xit * (1.0 - K.sb / FKS_SCAP);
     const double sr = K.sb / (1.0 - xi);
@@ -180,6 +184,8 @@ __device__ void fks_map(const double (&kb)[S::NB][4], double xit, double y, doub
     K.omz = 0.0;
     K.ei = ei;
     K.ej = 0.5 * sqr;
+    K.ejb = 0.0;
+    K.xmax = 1.0 - K.sb / FKS_SCAP;
   }
 }
 
@@ -273,6 +279,7 @@ struct FksArgs {
   double scale_b, g2, mt;
   double scale_bm;                     // coupling x average factor of the y -> -1 Born (quark FKS parton)
   double *xi_out, *born_out, *gR, *gS, *gC, *gCm, *gSC, *gSCm, *W;   // [n], any may be null but W
+  double *dsig, *jac;                  // [n] or null
   uint8_t* status;                     // [n] or null
   double* real_out;                    // [NR][4][ld] (event order) or null
 };
@@ -375,7 +382,8 @@ __device__ double born_spin(const typename BP::template Pre<T>& s, const double*
 // the subtracted weight and the per-event outputs
 template <class S>
 __device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e, double B, double gR, double gS,
-                                          double gC, double gCm, double gSC, double gSCm, double xi, double y) {
+                                          double gC, double gCm, double gSC, double gSCm, const FksKin& K) {
+  const double xi = K.xi, y = K.y;
   uint8_t st = (which & 1) ? 2 : 0;
   double Bo = B;
   if (a.mask) {
@@ -407,6 +415,23 @@ __device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e
     if (!(c * D <= 1e-3 * fabs(W))) st |= 8;
   }
   a.W[e] = W;
+  if (a.dsig || a.jac) {
+    // the map's phase-space factor at the event and at the limits each term
+    // stands for (final state: j(0,y) = j(0,1) = j0, j(xi,1) = z j0; beams:
+    // j = j0 / (1 - xi) wherever xi is kept, j0 at xi = 0)
+    const double j0 = K.sb / (64.0 * M_PI * M_PI * M_PI);
+    double jr, num;
+    if constexpr (S::J >= 0) {
+      jr = j0 * (K.ej / K.ejb) / (1.0 - 0.5 * xi * (1.0 - y));
+      num = (jr * gR - j0 * gS - K.z * j0 * gC + j0 * gSC) / (xi * (1.0 - y));
+    } else {
+      jr = j0 / (1.0 - xi);
+      num = (jr * (gR - 0.5 * (1.0 + y) * gC - 0.5 * (1.0 - y) * gCm)
+             - j0 * (gS - 0.5 * (1.0 + y) * gSC - 0.5 * (1.0 - y) * gSCm)) / (xi * (1.0 - y) * (1.0 + y));
+    }
+    if (a.dsig) a.dsig[e] = K.xmax * num / (2.0 * K.sb);
+    if (a.jac) a.jac[e] = K.xmax * jr;
+  }
   if (a.xi_out) a.xi_out[e] = xi;
   if (a.born_out) a.born_out[e] = Bo;
   if (a.gR) a.gR[e] = gR;
@@ -451,7 +476,7 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
   const double Pp = FKS_CF * (x * Bplus + 4.0 * xi / x * Bperp);
   const double Pm = 0.5 * (x * x + xi * xi) * Bminus;
   const double gR = which >= 2 ? 0.0 : xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
-  fks_store<S>(a, which, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, xi, y);
+  fks_store<S>(a, which, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, K);
 }
 
 // 3. Born correlations, counterterms and subtracted weight for one bucket
@@ -574,7 +599,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     gSC = 16.0 * g2 * Cp / K.sb * B;
     gSCm = 16.0 * g2 * Cm / K.sb * B;
   }
-  fks_store<S>(a, which, e, B, gR, gS, gC, gCm, gSC, gSCm, xi, y);
+  fks_store<S>(a, which, e, B, gR, gS, gC, gCm, gSC, gSCm, K);
   }
 }
 

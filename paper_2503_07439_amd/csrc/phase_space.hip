@@ -61,22 +61,18 @@ __global__ __launch_bounds__(256) void k_uniforms(int64_t n, uint32_t seed, uint
   out[2 * i + 1] = b;
 }
 
+// One RAMBO point from 4 NF uniforms per event (u[k] = cos theta, phi and
+// the two uniforms of the energy of particle k): momenta p[k] in the partonic
+// centre-of-mass frame at sqrt(s) = rs, and the phase-space weight w (the
+// volume for massless particles, times the massive correction).
 template <int NF>
-__global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const uint64_t e = a.first + (uint64_t)i;
-  double u0, u1, u2, u3;
-  uniform2(a.seed, a.stream, e, 64, u0, u1);
-  const double rs = a.rs_lo + (a.rs_hi - a.rs_lo) * u0;
+__device__ void rambo_point(const double (&u)[NF][4], double rs, const double* mass, double (&p)[NF][4], double& w) {
   // isotropic massless momenta, energy density q0 exp(-q0)
   double q[NF][4], Q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
-    uniform2(a.seed, a.stream, e, 2 * k, u0, u1);
-    uniform2(a.seed, a.stream, e, 2 * k + 1, u2, u3);
-    const double c = 2.0 * u0 - 1.0, ph = 2.0 * M_PI * u1;
-    const double en = -log(u2 * u3);
+    const double c = 2.0 * u[k][0] - 1.0, ph = 2.0 * M_PI * u[k][1];
+    const double en = -log(u[k][2] * u[k][3]);
     const double st = sqrt(fmax(0.0, 1.0 - c * c));
     double sp, cp;
     sincos(ph, &sp, &cp);
@@ -88,7 +84,6 @@ __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
   const double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
   const double bx = -Q[1] / M, by = -Q[2] / M, bz = -Q[3] / M;
   const double g = Q[0] / M, al = 1.0 / (1.0 + g), x = rs / M;
-  double p[NF][4];
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
     const double bq = bx * q[k][1] + by * q[k][2] + bz * q[k][3];
@@ -120,7 +115,7 @@ __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
     p[k][0] = pa[k] * sc;
   }
   // massless volume (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!)
-  double w = pow(2.0 * M_PI, 4 - 3 * NF) * pow(0.5 * M_PI, NF - 1);
+  w = pow(2.0 * M_PI, 4 - 3 * NF) * pow(0.5 * M_PI, NF - 1);
 #pragma unroll
   for (int k = 2; k <= NF - 1; ++k) w /= k;
 #pragma unroll
@@ -129,7 +124,7 @@ __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
   double msum = 0.0;
   bool massive = false;
 #pragma unroll
-  for (int k = 0; k < NF; ++k) { msum += a.mass[k]; massive = massive || a.mass[k] > 0.0; }
+  for (int k = 0; k < NF; ++k) { msum += mass[k]; massive = massive || mass[k] > 0.0; }
   if (massive) {
     // common factor xi on the three-momenta with sum_k sqrt(m_k^2 + xi^2 E_k^2) = sqrt_s
     double xi = sqrt(fmax(1e-30, 1.0 - (msum / rs) * (msum / rs)));
@@ -137,7 +132,7 @@ __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
       double f = -rs, fp = 0.0;
 #pragma unroll
       for (int k = 0; k < NF; ++k) {
-        const double ek = sqrt(a.mass[k] * a.mass[k] + xi * xi * p[k][0] * p[k][0]);
+        const double ek = sqrt(mass[k] * mass[k] + xi * xi * p[k][0] * p[k][0]);
         f += ek;
         fp += xi * p[k][0] * p[k][0] / ek;
       }
@@ -147,7 +142,7 @@ __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
     double ksum = 0.0, kprod = 1.0, k2e = 0.0;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
-      const double k0 = sqrt(a.mass[k] * a.mass[k] + xi * xi * p[k][0] * p[k][0]);
+      const double k0 = sqrt(mass[k] * mass[k] + xi * xi * p[k][0] * p[k][0]);
 #pragma unroll
       for (int m = 0; m < 3; ++m) p[k][1 + m] *= xi;
       p[k][0] = k0;
@@ -158,17 +153,40 @@ __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
     }
     w *= pow(ksum / rs, 2 * NF - 3) * kprod * rs / k2e;
   }
-  // store: beams, then the final state
+}
+
+// beams along +z and -z, then the final state, into mom[(particle 4 + mu) ld + i]
+template <int NF>
+__device__ __forceinline__ void store_event(const double (&p)[NF][4], double rs, double* mom, int64_t ld, int64_t i) {
   const double h = 0.5 * rs;
   const double beams[2][4] = {{h, 0.0, 0.0, h}, {h, 0.0, 0.0, -h}};
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a.mom[(b * 4 + m) * a.ld + i] = beams[b][m];
+    for (int m = 0; m < 4; ++m) mom[(b * 4 + m) * ld + i] = beams[b][m];
 #pragma unroll
   for (int k = 0; k < NF; ++k)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a.mom[((k + 2) * 4 + m) * a.ld + i] = p[k][m];
+    for (int m = 0; m < 4; ++m) mom[((k + 2) * 4 + m) * ld + i] = p[k][m];
+}
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const uint64_t e = a.first + (uint64_t)i;
+  double u0, u1;
+  uniform2(a.seed, a.stream, e, 64, u0, u1);
+  const double rs = a.rs_lo + (a.rs_hi - a.rs_lo) * u0;
+  double u[NF][4];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    uniform2(a.seed, a.stream, e, 2 * k, u[k][0], u[k][1]);
+    uniform2(a.seed, a.stream, e, 2 * k + 1, u[k][2], u[k][3]);
+  }
+  double p[NF][4], w;
+  rambo_point<NF>(u, rs, a.mass, p, w);
+  store_event<NF>(p, rs, a.mom, a.ld, i);
   if (a.weight) a.weight[i] = w;
 }
 
@@ -189,6 +207,196 @@ __global__ __launch_bounds__(256) void k_fks_variables(int64_t n, uint32_t seed,
   phi[i] = 2.0 * M_PI * b0;
 }
 
+// ---------------------------------------------------------------------------
+// VEGAS adaptive Monte Carlo (Lepage's algorithm): every integration variable
+// has its own grid of VEGAS_BINS bins on [0, 1); a uniform u selects bin
+// b = floor(u NB) and the point x = edge_b + (u NB - b) (edge_{b+1} - edge_b),
+// with weight NB (edge_{b+1} - edge_b).  After an iteration each bin's
+// accumulated (f w)^2 sets the new edges: smoothed with its neighbours,
+// compressed as ((1 - d/D) / ln(D/d))^alpha, and redistributed so that every
+// new bin holds the same share.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_vegas_init(int D, double* __restrict__ edges, unsigned* zero) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *zero = 0u;
+  if (i >= D * (VEGAS_BINS + 1)) return;
+  edges[i] = (double)(i % (VEGAS_BINS + 1)) / VEGAS_BINS;
+}
+
+// the points of one iteration: D = 4 NF Born uniforms (RAMBO) + xi_tilde, y, phi
+template <int NF>
+__global__ __launch_bounds__(256) void k_vegas_points(VegasArgs a) {
+  constexpr int D = 4 * NF + 3;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const uint64_t e = a.first + (uint64_t)i;
+  double x[D + 1];
+  double wg = 1.0;
+#pragma unroll
+  for (int s = 0; s < (D + 1) / 2; ++s) {
+    double v[2];
+    uniform2(a.seed, a.stream, e, (uint32_t)s, v[0], v[1]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int d = 2 * s + c;
+      if (d >= D) break;
+      const double t = v[c] * VEGAS_BINS;
+      int b = (int)t;
+      if (b > VEGAS_BINS - 1) b = VEGAS_BINS - 1;
+      const double lo = a.edges[d * (VEGAS_BINS + 1) + b], wd = a.edges[d * (VEGAS_BINS + 1) + b + 1] - lo;
+      x[d] = lo + (t - b) * wd;
+      wg *= VEGAS_BINS * wd;
+      a.bins[(int64_t)d * a.n + i] = (uint8_t)b;
+    }
+  }
+  double u[NF][4];
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) u[k][m] = x[4 * k + m];
+  double p[NF][4], wb;
+  rambo_point<NF>(u, a.rs, a.mass, p, wb);
+  store_event<NF>(p, a.rs, a.mom, a.n, i);
+  a.xit[i] = x[4 * NF];
+  a.y[i] = 2.0 * x[4 * NF + 1] - 1.0;
+  a.phi[i] = 2.0 * M_PI * x[4 * NF + 2];
+  a.w[i] = wb * wg * (2.0 * 2.0 * M_PI);   // dy = 2 du, dphi = 2 pi du
+}
+
+// f = scale * w * sum over sectors of dsig; a non-finite sum (an exactly
+// singular point, measure zero) counts as zero and is counted
+__global__ __launch_bounds__(256) void k_vegas_f(int64_t n, int nsec, const double* __restrict__ dsig,
+                                                 const double* __restrict__ w, double scale, double* __restrict__ f,
+                                                 unsigned* __restrict__ dropped) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < nsec; ++k) s += dsig[(int64_t)k * n + i];
+  double v = scale * w[i] * s;
+  if (!isfinite(v)) {
+    v = 0.0;
+    atomicAdd(dropped, 1u);
+  }
+  f[i] = v;
+}
+
+// per-block sums of f^2 per (variable, bin), in a fixed order: block b takes a
+// contiguous share of the points in chunks of 256; for every chunk, thread t
+// owns the (variable, bin) pairs t, t + 256, ... and adds the chunk's points
+// of its bin in point order
+__global__ __launch_bounds__(256) void k_vegas_hist_partial(int64_t n, int D, const double* __restrict__ f,
+                                                            const uint8_t* __restrict__ bins,
+                                                            double* __restrict__ part) {
+  __shared__ double f2[256];
+  __shared__ uint8_t bb[VEGAS_MAX_DIM][256];
+  __shared__ double acc[VEGAS_MAX_DIM * VEGAS_BINS];
+  const int pairs = D * VEGAS_BINS;
+  for (int q = threadIdx.x; q < pairs; q += blockDim.x) acc[q] = 0.0;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+  for (int64_t c0 = lo; c0 < hi; c0 += 256) {
+    const int64_t i = c0 + threadIdx.x;
+    const int cnt = hi - c0 < 256 ? (int)(hi - c0) : 256;
+    __syncthreads();
+    if (i < hi) {
+      f2[threadIdx.x] = f[i] * f[i];
+      for (int d = 0; d < D; ++d) bb[d][threadIdx.x] = bins[(int64_t)d * n + i];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+      const int d = q / VEGAS_BINS, b = q % VEGAS_BINS;
+      double s = 0.0;
+      for (int j = 0; j < cnt; ++j)
+        if (bb[d][j] == b) s += f2[j];
+      acc[q] += s;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < pairs; q += blockDim.x) part[(int64_t)blockIdx.x * pairs + q] = acc[q];
+}
+
+// hist[q] = sum over blocks, in block order
+__global__ __launch_bounds__(256) void k_vegas_hist_final(int nblocks, int pairs, const double* __restrict__ part,
+                                                          double* __restrict__ hist) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= pairs) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * pairs + q];
+  hist[q] = s;
+}
+
+// new grid from the histogram: one thread per variable
+__global__ void k_vegas_refine(int D, double alpha, const double* __restrict__ hist, double* __restrict__ edges) {
+  const int d = threadIdx.x;
+  if (d >= D) return;
+  const int NB = VEGAS_BINS;
+  const double* h = hist + d * NB;
+  double* ed = edges + d * (NB + 1);
+  double sm[VEGAS_BINS], r[VEGAS_BINS], old[VEGAS_BINS + 1];
+  // smoothing with the neighbours
+  sm[0] = 0.5 * (h[0] + h[1]);
+  for (int b = 1; b < NB - 1; ++b) sm[b] = (h[b - 1] + h[b] + h[b + 1]) / 3.0;
+  sm[NB - 1] = 0.5 * (h[NB - 2] + h[NB - 1]);
+  double tot = 0.0;
+  for (int b = 0; b < NB; ++b) tot += sm[b];
+  if (!(tot > 0.0)) return;
+  double rsum = 0.0;
+  for (int b = 0; b < NB; ++b) {
+    const double a = sm[b] / tot;
+    r[b] = a <= 0.0 ? 0.0 : (a >= 1.0 ? 1.0 : pow((1.0 - a) / (-log(a)), alpha));
+    rsum += r[b];
+  }
+  if (!(rsum > 0.0)) return;
+  for (int k = 0; k <= NB; ++k) old[k] = ed[k];
+  const double share = rsum / NB;
+  int b = 0;
+  double acc = 0.0;   // r of the old bins before b
+  for (int k = 1; k < NB; ++k) {
+    const double target = k * share;
+    while (b < NB - 1 && acc + r[b] < target) {
+      acc += r[b];
+      ++b;
+    }
+    const double frac = r[b] > 0.0 ? (target - acc) / r[b] : 0.0;
+    ed[k] = old[b] + frac * (old[b + 1] - old[b]);
+  }
+  ed[0] = 0.0;
+  ed[NB] = 1.0;
+}
+
+hipError_t launch_vegas_init(int D, double* edges, unsigned* zero, hipStream_t st) {
+  hipLaunchKernelGGL(k_vegas_init, dim3((D * (VEGAS_BINS + 1) + 255) / 256), dim3(256), 0, st, D, edges, zero);
+  return hipGetLastError();
+}
+
+hipError_t launch_vegas_points(int nfin, const VegasArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+  switch (nfin) {
+    case 2: hipLaunchKernelGGL(k_vegas_points<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_vegas_points<3>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vegas_update(int64_t n, int D, int nsec, const double* dsig, const double* w, double scale,
+                               double* f, unsigned* dropped, const uint8_t* bins, double* part, double* hist,
+                               double* xs_part, double* acc, bool refine, double alpha, double* edges,
+                               hipStream_t st) {
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(k_vegas_f, dim3((unsigned)grid), dim3(256), 0, st, n, nsec, dsig, w, scale, f, dropped);
+  hipError_t e = launch_xs_sums(n, f, nullptr, 1.0, xs_part, acc, true, st);
+  if (e != hipSuccess || !refine) return e;
+  hipLaunchKernelGGL(k_vegas_hist_partial, dim3(VEGAS_HIST_BLOCKS), dim3(256), 0, st, n, D, (const double*)f, bins,
+                     part);
+  const int pairs = D * VEGAS_BINS;
+  hipLaunchKernelGGL(k_vegas_hist_final, dim3((pairs + 255) / 256), dim3(256), 0, st, VEGAS_HIST_BLOCKS, pairs,
+                     (const double*)part, hist);
+  hipLaunchKernelGGL(k_vegas_refine, dim3(1), dim3(64), 0, st, D, alpha, (const double*)hist, edges);
+  return hipGetLastError();
+}
+
 // Monte Carlo sums of f = scale * w * me2 over a chunk, in a fixed order:
 // block b reduces its contiguous share into part[b] = (sum f, sum f^2); one
 // block then adds the parts, in order, to acc.
@@ -202,7 +410,7 @@ __global__ __launch_bounds__(256) void k_xs_partial(int64_t n, const double* __r
   const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
   double a = 0.0, b = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const double f = scale * w[i] * me2[i];
+    const double f = scale * w[i] * (me2 ? me2[i] : 1.0);
     a += f;
     b += f * f;
   }

@@ -294,15 +294,15 @@ int fks_sectors(int real_proc, const FksSector** out, int max) {
 // nlo_integrate_subtracted with n points per iteration and niter iterations:
 // the FKS workspace, then Born momenta, weights, radiation variables, one
 // dsig and one W array per sector, f, bin indices, histogram partials, the
-// histogram, the grid, partial sums, per-iteration sums and a counter
+// grid, partial sums, per-iteration sums and a counter
 size_t int_ws_bytes(int real_proc, int64_t n, int niter) {
   const FksSector* secs[8];
   const int ns = fks_sectors(real_proc, secs, 8);
   if (!ns) return 0;
   const int nb = PROC_STATIC[secs[0]->born].npart;
   const int D = 4 * (nb - 2) + 3;
-  const size_t dbl = (size_t)n * (nb * 4 + 4 + 2 * ns + 1) + (size_t)VEGAS_HIST_BLOCKS * D * VEGAS_BINS +
-                     (size_t)D * VEGAS_BINS + (size_t)D * (VEGAS_BINS + 1) + XS_PART_DOUBLES + 2 * (size_t)niter + 64;
+  const size_t dbl = (size_t)n * (nb * 4 + 4 + 2 * ns + 1) + (size_t)(VEGAS_HIST_BLOCKS + VEGAS_HIST_SEG) * D * VEGAS_BINS +
+                     (size_t)D * (VEGAS_BINS + 1) + XS_PART_DOUBLES + 2 * (size_t)niter + 64;
   return fks_ws_bytes(real_proc, n) + 256 + dbl * sizeof(double) + (size_t)n * D + 256;
 }
 
@@ -943,8 +943,7 @@ nlo_status nlo_integrate_subtracted(nlo_ctx* ctx, int real_proc, double sqrt_s_b
   double* dsig = dp;           dp += (size_t)n * ns;
   double* wsc = dp;            dp += (size_t)n * ns;
   double* f = dp;              dp += n;
-  double* part = dp;           dp += (size_t)VEGAS_HIST_BLOCKS * D * VEGAS_BINS;
-  double* hist = dp;           dp += (size_t)D * VEGAS_BINS;
+  double* part = dp;           dp += (size_t)(VEGAS_HIST_BLOCKS + VEGAS_HIST_SEG) * D * VEGAS_BINS;
   double* edges = dp;          dp += (size_t)D * (VEGAS_BINS + 1);
   double* xs_part = dp;        dp += XS_PART_DOUBLES;
   double* acc = dp;            dp += 2 * (size_t)niter;
@@ -974,7 +973,7 @@ nlo_status nlo_integrate_subtracted(nlo_ctx* ctx, int real_proc, double sqrt_s_b
       e = launch_subtracted(ctx, secs[k], real_proc, n, n, mom, xit, yv, phi, nullptr, prec, &o, ctx->ws, s);
     }
     if (e == hipSuccess)
-      e = launch_vegas_update(n, D, ns, dsig, w, conv, f, dropped, bins, part, hist, xs_part, acc + 2 * it,
+      e = launch_vegas_update(n, D, ns, dsig, w, conv, f, dropped, bins, part, xs_part, acc + 2 * it,
                               it + 1 < niter, 1.5, edges, s);
   }
   if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));

@@ -317,22 +317,44 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_map(FksArgs a) {
     f64 = (a.mode == 1) || (a.mode == 2 && !(kappa >= a.thr));
     skip = a.compact && a.mask && !a.mask[1 * a.ld + e];
   }
-  // wave-aggregated positions in the four lists
+  // positions in the four lists (FP32, FP64, and the two of events that
+  // skip the real |M|^2): wave ballots, then one atomic per list and block
   const unsigned long long m32 = __ballot(act && !f64 && !skip), m64 = __ballot(act && f64 && !skip);
   const unsigned long long s32 = __ballot(act && !f64 && skip), s64 = __ballot(act && f64 && skip);
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long lower = lane ? (~0ull >> (64 - lane)) : 0ull;
-  unsigned b32 = 0, b64 = 0, c32 = 0, c64 = 0;
-  if (lane == 0) {
-    if (m32) b32 = atomicAdd(&a.cnt[0], (unsigned)__popcll(m32));
-    if (m64) b64 = atomicAdd(&a.cnt[1], (unsigned)__popcll(m64));
-    if (s32) c32 = atomicAdd(&a.cnt[2], (unsigned)__popcll(s32));
-    if (s64) c64 = atomicAdd(&a.cnt[3], (unsigned)__popcll(s64));
+  unsigned b32, b64, c32, c64;
+  if (a.mode == 1 && !a.compact) {
+    // every event in the FP64 list, in event order from the back: no atomics
+    b32 = c32 = c64 = 0u;
+    b64 = (unsigned)((int64_t)blockIdx.x * blockDim.x + wave * 64);
+    if (e == 0) a.cnt[1] = (unsigned)a.n;
+  } else {
+    __shared__ unsigned wc[NLO_MAX_BLOCK / 64][4], wb[NLO_MAX_BLOCK / 64][4];
+    const int nw = (int)(blockDim.x + 63) >> 6;
+    if (lane == 0) {
+      wc[wave][0] = (unsigned)__popcll(m32);
+      wc[wave][1] = (unsigned)__popcll(m64);
+      wc[wave][2] = (unsigned)__popcll(s32);
+      wc[wave][3] = (unsigned)__popcll(s64);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int l = threadIdx.x;
+      unsigned tot = 0u;
+      for (int w = 0; w < nw; ++w) tot += wc[w][l];
+      unsigned base = tot ? atomicAdd(&a.cnt[l], tot) : 0u;
+      for (int w = 0; w < nw; ++w) {
+        wb[w][l] = base;
+        base += wc[w][l];
+      }
+    }
+    __syncthreads();
+    b32 = wb[wave][0];
+    b64 = wb[wave][1];
+    c32 = wb[wave][2];
+    c64 = wb[wave][3];
   }
-  b32 = __shfl(b32, 0);
-  b64 = __shfl(b64, 0);
-  c32 = __shfl(c32, 0);
-  c64 = __shfl(c64, 0);
   if (!act) return;
   if (skip) {
     const int64_t pos = f64 ? a.n - 1 - (int64_t)(c64 + __popcll(s64 & lower)) : (int64_t)(c32 + __popcll(s32 & lower));

@@ -282,87 +282,115 @@ __global__ __launch_bounds__(256) void k_vegas_f(int64_t n, int nsec, const doub
 }
 
 // per-block sums of f^2 per (variable, bin), in a fixed order: block b takes a
-// contiguous share of the points in chunks of 256; for every chunk, thread t
-// owns the (variable, bin) pairs t, t + 256, ... and adds the chunk's points
-// of its bin in point order
+// contiguous share of the points.  Thread t serves variable d = t / 16 and
+// every 16th point of the share from t mod 16 on, adding each into its own
+// column of an LDS histogram in point order; at the end the 16 columns of a
+// variable are added in column order.  Rows are padded to 257 doubles so
+// that the column sums, one bin per lane, fall into different banks.
+constexpr int VEGAS_HIST_SUB = 256 / VEGAS_MAX_DIM;
 __global__ __launch_bounds__(256) void k_vegas_hist_partial(int64_t n, int D, const double* __restrict__ f,
                                                             const uint8_t* __restrict__ bins,
                                                             double* __restrict__ part) {
-  __shared__ double f2[256];
-  __shared__ uint8_t bb[VEGAS_MAX_DIM][256];
-  __shared__ double acc[VEGAS_MAX_DIM * VEGAS_BINS];
-  const int pairs = D * VEGAS_BINS;
-  for (int q = threadIdx.x; q < pairs; q += blockDim.x) acc[q] = 0.0;
+  constexpr int ROW = 257;
+  __shared__ double hist[VEGAS_BINS * ROW];
+  const int t = threadIdx.x, d = t / VEGAS_HIST_SUB, sub = t % VEGAS_HIST_SUB;
+  for (int b = 0; b < VEGAS_BINS; ++b) hist[b * ROW + t] = 0.0;
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
-  for (int64_t c0 = lo; c0 < hi; c0 += 256) {
-    const int64_t i = c0 + threadIdx.x;
-    const int cnt = hi - c0 < 256 ? (int)(hi - c0) : 256;
-    __syncthreads();
-    if (i < hi) {
-      f2[threadIdx.x] = f[i] * f[i];
-      for (int d = 0; d < D; ++d) bb[d][threadIdx.x] = bins[(int64_t)d * n + i];
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-      const int d = q / VEGAS_BINS, b = q % VEGAS_BINS;
-      double s = 0.0;
-      for (int j = 0; j < cnt; ++j)
-        if (bb[d][j] == b) s += f2[j];
-      acc[q] += s;
+  if (d < D) {
+    const uint8_t* bd = bins + (int64_t)d * n;
+#pragma unroll 4
+    for (int64_t j = lo + sub; j < hi; j += VEGAS_HIST_SUB) {
+      const double fj = f[j];
+      hist[bd[j] * ROW + t] += fj * fj;
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < pairs; q += blockDim.x) part[(int64_t)blockIdx.x * pairs + q] = acc[q];
+  const int pairs = D * VEGAS_BINS;
+  for (int q = t; q < pairs; q += 256) {
+    const int dq = q / VEGAS_BINS, b = q % VEGAS_BINS;
+    double acc = 0.0;
+    for (int c = 0; c < VEGAS_HIST_SUB; ++c) acc += hist[b * ROW + dq * VEGAS_HIST_SUB + c];
+    part[(int64_t)blockIdx.x * pairs + q] = acc;
+  }
 }
 
-// hist[q] = sum over blocks, in block order
-__global__ __launch_bounds__(256) void k_vegas_hist_final(int nblocks, int pairs, const double* __restrict__ part,
-                                                          double* __restrict__ hist) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= pairs) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * pairs + q];
-  hist[q] = s;
+// fold[s][q] = sum of part[b][q] over the VEGAS_HIST_BLOCKS / VEGAS_HIST_SEG
+// blocks b of segment s, in block order within four interleaved chains
+__global__ __launch_bounds__(256) void k_vegas_hist_fold(int pairs, const double* __restrict__ part,
+                                                         double* __restrict__ fold) {
+  constexpr int PER = VEGAS_HIST_BLOCKS / VEGAS_HIST_SEG;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= VEGAS_HIST_SEG * pairs) return;
+  const int seg = i / pairs, q = i % pairs;
+  const double* p = part + (int64_t)seg * PER * pairs + q;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < PER; ++k) a[k & 3] += p[(int64_t)k * pairs];
+  fold[i] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
-// new grid from the histogram: one thread per variable
-__global__ void k_vegas_refine(int D, double alpha, const double* __restrict__ hist, double* __restrict__ edges) {
-  const int d = threadIdx.x;
-  if (d >= D) return;
-  const int NB = VEGAS_BINS;
-  const double* h = hist + d * NB;
+// New grid of variable d = blockIdx.x from the folded histograms: lane b
+// adds bin b over the segments (in order), smooths it with its neighbours
+// and compresses it; lane 0 forms the running sums in bin order; lane k
+// places new edge k.
+__global__ __launch_bounds__(64) void k_vegas_refine(int D, double alpha, const double* __restrict__ fold,
+                                                     double* __restrict__ edges) {
+  constexpr int NB = VEGAS_BINS;
+  __shared__ double h[NB], sm[NB], r[NB], cum[NB + 1], old[NB + 1], tot_s[2];
+  const int d = blockIdx.x, b = threadIdx.x;
+  const int pairs = D * NB;
   double* ed = edges + d * (NB + 1);
-  double sm[VEGAS_BINS], r[VEGAS_BINS], old[VEGAS_BINS + 1];
-  // smoothing with the neighbours
-  sm[0] = 0.5 * (h[0] + h[1]);
-  for (int b = 1; b < NB - 1; ++b) sm[b] = (h[b - 1] + h[b] + h[b + 1]) / 3.0;
-  sm[NB - 1] = 0.5 * (h[NB - 2] + h[NB - 1]);
-  double tot = 0.0;
-  for (int b = 0; b < NB; ++b) tot += sm[b];
-  if (!(tot > 0.0)) return;
-  double rsum = 0.0;
-  for (int b = 0; b < NB; ++b) {
+  if (b < NB) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < VEGAS_HIST_SEG; ++k) a[k & 3] += fold[(int64_t)k * pairs + d * NB + b];
+    h[b] = (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  if (b <= NB) old[b] = ed[b];
+  __syncthreads();
+  // smoothing with the neighbours (two-point averages at the ends)
+  if (b < NB) {
+    sm[b] = b == 0 ? 0.5 * (h[0] + h[1])
+                   : (b == NB - 1 ? 0.5 * (h[NB - 2] + h[NB - 1]) : (h[b - 1] + h[b] + h[b + 1]) / 3.0);
+  }
+  __syncthreads();
+  if (b == 0) {
+    double t = 0.0;
+    for (int c = 0; c < NB; ++c) t += sm[c];
+    tot_s[0] = t;
+  }
+  __syncthreads();
+  const double tot = tot_s[0];
+  if (!(tot > 0.0)) return;                  // nothing to adapt to: keep the grid
+  if (b < NB) {
     const double a = sm[b] / tot;
     r[b] = a <= 0.0 ? 0.0 : (a >= 1.0 ? 1.0 : pow((1.0 - a) / (-log(a)), alpha));
-    rsum += r[b];
   }
-  if (!(rsum > 0.0)) return;
-  for (int k = 0; k <= NB; ++k) old[k] = ed[k];
-  const double share = rsum / NB;
-  int b = 0;
-  double acc = 0.0;   // r of the old bins before b
-  for (int k = 1; k < NB; ++k) {
-    const double target = k * share;
-    while (b < NB - 1 && acc + r[b] < target) {
-      acc += r[b];
-      ++b;
+  __syncthreads();
+  if (b == 0) {
+    double c = 0.0;
+    cum[0] = 0.0;
+    for (int q = 0; q < NB; ++q) {
+      c += r[q];
+      cum[q + 1] = c;
     }
-    const double frac = r[b] > 0.0 ? (target - acc) / r[b] : 0.0;
-    ed[k] = old[b] + frac * (old[b + 1] - old[b]);
+    tot_s[1] = c;
   }
-  ed[0] = 0.0;
-  ed[NB] = 1.0;
+  __syncthreads();
+  const double rsum = tot_s[1];
+  if (!(rsum > 0.0)) return;
+  // edge k: the first old bin q (at most NB - 1) whose running sum reaches
+  // k rsum / NB, entered by the fraction of its own r that is still missing
+  if (b >= 1 && b < NB) {
+    const double target = b * (rsum / NB);
+    int q = 0;
+    while (q < NB - 1 && cum[q + 1] < target) ++q;
+    const double frac = r[q] > 0.0 ? (target - cum[q]) / r[q] : 0.0;
+    ed[b] = old[q] + frac * (old[q + 1] - old[q]);
+  }
+  if (b == 0) ed[0] = 0.0;
+  if (b == NB) ed[NB] = 1.0;
 }
 
 hipError_t launch_vegas_init(int D, double* edges, unsigned* zero, hipStream_t st) {
@@ -381,9 +409,8 @@ hipError_t launch_vegas_points(int nfin, const VegasArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_vegas_update(int64_t n, int D, int nsec, const double* dsig, const double* w, double scale,
-                               double* f, unsigned* dropped, const uint8_t* bins, double* part, double* hist,
-                               double* xs_part, double* acc, bool refine, double alpha, double* edges,
-                               hipStream_t st) {
+                               double* f, unsigned* dropped, const uint8_t* bins, double* part, double* xs_part,
+                               double* acc, bool refine, double alpha, double* edges, hipStream_t st) {
   const int64_t grid = (n + 255) / 256;
   hipLaunchKernelGGL(k_vegas_f, dim3((unsigned)grid), dim3(256), 0, st, n, nsec, dsig, w, scale, f, dropped);
   hipError_t e = launch_xs_sums(n, f, nullptr, 1.0, xs_part, acc, true, st);
@@ -391,9 +418,10 @@ hipError_t launch_vegas_update(int64_t n, int D, int nsec, const double* dsig, c
   hipLaunchKernelGGL(k_vegas_hist_partial, dim3(VEGAS_HIST_BLOCKS), dim3(256), 0, st, n, D, (const double*)f, bins,
                      part);
   const int pairs = D * VEGAS_BINS;
-  hipLaunchKernelGGL(k_vegas_hist_final, dim3((pairs + 255) / 256), dim3(256), 0, st, VEGAS_HIST_BLOCKS, pairs,
-                     (const double*)part, hist);
-  hipLaunchKernelGGL(k_vegas_refine, dim3(1), dim3(64), 0, st, D, alpha, (const double*)hist, edges);
+  double* fold = part + (int64_t)VEGAS_HIST_BLOCKS * pairs;
+  hipLaunchKernelGGL(k_vegas_hist_fold, dim3((VEGAS_HIST_SEG * pairs + 255) / 256), dim3(256), 0, st, pairs,
+                     (const double*)part, fold);
+  hipLaunchKernelGGL(k_vegas_refine, dim3(D), dim3(64), 0, st, D, alpha, (const double*)fold, edges);
   return hipGetLastError();
 }
 

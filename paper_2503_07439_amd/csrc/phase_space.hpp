@@ -24,7 +24,8 @@ hipError_t launch_fks_variables(int64_t n, uint32_t seed, uint32_t stream, uint6
 // VEGAS adaptive integration over the Born RAMBO uniforms and xi_tilde, y, phi
 constexpr int VEGAS_BINS = 50;
 constexpr int VEGAS_MAX_DIM = 16;       // 4 per Born final-state particle (at most 3) + 3
-constexpr int VEGAS_HIST_BLOCKS = 256;
+constexpr int VEGAS_HIST_BLOCKS = 1024;  // blocks of the histogram pass
+constexpr int VEGAS_HIST_SEG = 32;       // their partial sums folded in 32 segments
 
 struct VegasArgs {
   int64_t n;
@@ -42,12 +43,11 @@ struct VegasArgs {
 hipError_t launch_vegas_init(int D, double* edges, unsigned* zero, hipStream_t st);
 hipError_t launch_vegas_points(int nfin, const VegasArgs& a, hipStream_t st);
 // f = scale w sum_s dsig[s]; (sum f, sum f^2) into acc; with refine, the
-// per-bin sums of f^2 (part: VEGAS_HIST_BLOCKS x D x VEGAS_BINS doubles,
-// hist: D x VEGAS_BINS) and the new grid
+// per-bin sums of f^2 (part: (VEGAS_HIST_BLOCKS + VEGAS_HIST_SEG) x D x
+// VEGAS_BINS doubles) and the new grid
 hipError_t launch_vegas_update(int64_t n, int D, int nsec, const double* dsig, const double* w, double scale,
-                               double* f, unsigned* dropped, const uint8_t* bins, double* part, double* hist,
-                               double* xs_part, double* acc, bool refine, double alpha, double* edges,
-                               hipStream_t st);
+                               double* f, unsigned* dropped, const uint8_t* bins, double* part, double* xs_part,
+                               double* acc, bool refine, double alpha, double* edges, hipStream_t st);
 
 // fixed-order sums (sum f, sum f^2) of f = scale * w * me2 over n events,
 // added to acc[0..1] (or replacing them when reset); part: 2 * 512 doubles;

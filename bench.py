@@ -232,7 +232,8 @@ def integrate_leg(ctx):
 def mix_leg(ctx, steps):
     """An uneven mix of Born, real and subtracted items (MIXED precision):
     one captured-graph launch of the whole mix against the same items issued
-    one call after another on the stream."""
+    one call after another on the stream, with the default launch
+    configurations and after autotuning every item on its own events."""
     import torch
     import paper_2503_07439_amd as nl
     from nlo_inputs.workloads import MIX_ITEMS, MIX_STREAM, events, fks_variables, mix_counts
@@ -263,35 +264,47 @@ def mix_leg(ctx, steps):
                                                          it.xi_tilde, it.y, it.phi, None, it.prec, it.fks_out, stream))
         items.append(it)
     ctx.reserve(int(counts.max()))     # the direct calls share the context workspace
-    plan = nl.nlo_batch_plan(ctx.ctx, items, 4)
 
-    def run_graph():
-        nl.nlo_batch_run(plan, stream)
+    def timed_pair():
+        """(graph ms, direct ms) with the context's current configurations"""
+        plan = nl.nlo_batch_plan(ctx.ctx, items, 4)
+        out = []
+        try:
+            for fn in (lambda: nl.nlo_batch_run(plan, stream), lambda: [c() for c in calls]):
+                for _ in range(2):
+                    fn()
+                torch.cuda.synchronize()
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record()
+                for _ in range(steps):
+                    fn()
+                t1.record()
+                torch.cuda.synchronize()
+                out.append(t0.elapsed_time(t1) / steps)
+        finally:
+            nl.nlo_plan_destroy(plan)
+        return out
 
-    def run_direct():
-        for c in calls:
-            c()
-
-    res = {}
-    try:
-        for name, fn in (("graph", run_graph), ("direct", run_direct)):
-            for _ in range(2):
-                fn()
-            torch.cuda.synchronize()
-            t0 = torch.cuda.Event(enable_timing=True)
-            t1 = torch.cuda.Event(enable_timing=True)
-            t0.record()
-            for _ in range(steps):
-                fn()
-            t1.record()
-            torch.cuda.synchronize()
-            res[name] = t0.elapsed_time(t1) / steps
-    finally:
-        nl.nlo_plan_destroy(plan)
+    default_graph, default_direct = timed_pair()
+    # autotune every item on its own events, then plan again
+    tuned = []
+    for k, ((kind, proc, pair, born), it) in enumerate(zip(MIX_ITEMS, items)):
+        if kind == "me2":
+            mom = keep[[i for i, x in enumerate(keep) if x.data_ptr() == it.mom][0]]
+            cfg, ns = ctx.autotune(proc, mom, "mixed")
+        else:
+            find = lambda ptr: keep[[i for i, x in enumerate(keep) if x.data_ptr() == ptr][0]]
+            cfg, ns = ctx.autotune_subtracted(proc, pair[0], pair[1], find(it.mom), find(it.xi_tilde), find(it.y),
+                                              find(it.phi), "mixed")
+        tuned.append({"item": k, "config": list(cfg), "ns_per_event": ns})
+    graph, direct = timed_pair()
     total = int(counts.sum())
     return {"items": [[k, p, list(q) if q else None, int(c)] for (k, p, q, _), c in zip(MIX_ITEMS, counts)],
-            "events": total, "precision": "mixed", "graph_ms": res["graph"], "direct_ms": res["direct"],
-            "graph_events_per_s": total / (res["graph"] * 1e-3), "graph_speedup": res["direct"] / res["graph"]}
+            "events": total, "precision": "mixed", "graph_ms": graph, "direct_ms": direct,
+            "graph_events_per_s": total / (graph * 1e-3), "graph_speedup": direct / graph,
+            "default_config_graph_ms": default_graph, "default_config_direct_ms": default_direct,
+            "autotuned": tuned}
 
 
 def mask_study(ctx, steps):

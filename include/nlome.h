@@ -104,6 +104,16 @@ typedef struct {
   int colour_mode;  /* 0 = automatic, 1 = vector ALU, 2 = matrix cores (FP32 family only) */
 } nlo_kernel_config;
 
+/* Launch configuration of one FKS sector's subtracted evaluation in one
+ * precision: the real-emission |M|^2 kernels (real_block threads per block,
+ * colour unit as in nlo_kernel_config) and the map and counterterm kernels
+ * (ct_block threads per block).  Defaults {256, 0, 256}. */
+typedef struct {
+  int real_block;   /* 64, 128, 192 or 256 */
+  int colour_mode;  /* 0 = automatic, 1 = vector ALU, 2 = matrix cores (FP32/MIXED only) */
+  int ct_block;     /* 64, 128, 192 or 256 */
+} nlo_fks_config;
+
 uint32_t nlo_abi_version(void);
 
 /* Create a context on params->device; *out receives it.  Allocates nothing on
@@ -154,9 +164,45 @@ nlo_status nlo_reserve(nlo_ctx* ctx, int64_t n);
  * given stream, keeps the fastest for this context and returns it in *best
  * (may be NULL) and its time per event in *ns_per_event (may be NULL).
  * Synchronises the stream; allocates nothing (FP16/BF16 use the context
- * workspace, which must hold n events: nlo_reserve). */
+ * workspace, which must hold n events: nlo_reserve).  With a tuning cache set
+ * (nlo_tuning_cache), the result is merged into it. */
 nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int64_t ld, const double* mom,
                         double* me2, void* hip_stream, nlo_kernel_config* best, double* ns_per_event);
+
+/* Per-sector launch configuration of nlo_subtracted (sector as there). */
+nlo_status nlo_set_fks_config(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, nlo_prec prec,
+                              const nlo_fks_config* cfg);
+nlo_status nlo_get_fks_config(const nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, nlo_prec prec,
+                              nlo_fks_config* cfg);
+
+/* Autotuner for one FKS sector's subtracted evaluation (the launch
+ * configuration of the paper's per-sector event loop, section "A data
+ * parallel algorithm"): times, with HIP events on the given stream, the real
+ * |M|^2 block size x colour unit (FP32/MIXED: vector ALU or matrix cores)
+ * with the default counterterm block, then the counterterm block with the
+ * winner, each by one warm-up and three timed nlo_subtracted calls on the
+ * caller's sample (Born momenta, radiation variables as nlo_subtracted; W
+ * scratch output of n doubles); keeps the fastest for this context, returns it
+ * in *best and its time per event in *ns_per_event (either may be NULL).
+ * Uses the context workspace (nlo_reserve(ctx, n)); synchronises the stream.
+ * With a tuning cache set (nlo_tuning_cache), the result is merged into it. */
+nlo_status nlo_autotune_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                                   const double* born_mom, const double* xi_tilde, const double* y,
+                                   const double* phi, nlo_prec prec, double* w_scratch, void* hip_stream,
+                                   nlo_fks_config* best, double* ns_per_event);
+
+/* Tuning cache: a JSON file of autotune results, each entry keyed by the
+ * device architecture (gcnArchName), its compute-unit count, the HIP runtime
+ * and driver versions and the library build (a hash of its sources).  This
+ * call reads path (a missing file is an empty cache), applies to the context
+ * every entry whose key matches the current device and build (*loaded, may be
+ * NULL, receives their number; entries of other keys are kept but ignored),
+ * and remembers path: every later nlo_autotune / nlo_autotune_subtracted on
+ * this context merges its result into the file (replacing the entry of the
+ * same key, process, sector and precision; written to a temporary file and
+ * renamed).  path NULL or "" stops the merging.  Host I/O only; a malformed
+ * file returns NLO_EINVAL and changes nothing. */
+nlo_status nlo_tuning_cache(nlo_ctx* ctx, const char* path, int* loaded);
 
 /* Squared matrix elements (the paper's Born and real equations):
  *   me2[e] = avg_factor * sum_{helicities} sum_{colours} |M(mom_e)|^2

@@ -11,7 +11,8 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_subtracted, nlo_subtracted_static, nlo_set_fks_threshold, nlo_fks_out, nlo_work_item, nlo_batch_plan,
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
                    nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
-                   nlo_me2_checked, nlo_reserve, nlo_colour_unit, nlo_integrate_subtracted)
+                   nlo_me2_checked, nlo_reserve, nlo_colour_unit, nlo_integrate_subtracted, nlo_fks_config,
+                   nlo_set_fks_config, nlo_get_fks_config, nlo_autotune_subtracted, nlo_tuning_cache)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -132,6 +133,34 @@ class Context:
             self.reserve(n)
         return nlo_autotune(self.ctx, proc_id(proc), PREC[prec], n, n, mom.data_ptr(), out.data_ptr(),
                             self._stream())
+
+    def autotune_subtracted(self, real, fks_i, fks_j, born_mom, xi_tilde, y, phi, prec="mixed"):
+        """Time the launch configurations of one FKS sector on this sample and
+        keep the fastest.  Returns ((real_block, colour_mode, ct_block), ns per
+        event)."""
+        import torch
+        n = born_mom.shape[2]
+        w = torch.empty(n, dtype=torch.float64, device=born_mom.device)
+        self.reserve(n)
+        return nlo_autotune_subtracted(self.ctx, proc_id(real), fks_i, fks_j, n, n, born_mom.data_ptr(),
+                                       xi_tilde.data_ptr(), y.data_ptr(), phi.data_ptr(), PREC[prec], w.data_ptr(),
+                                       self._stream())
+
+    def set_fks_config(self, real, fks_i, fks_j, prec, real_block, colour_mode, ct_block):
+        nlo_set_fks_config(self.ctx, proc_id(real), fks_i, fks_j, PREC[prec], real_block, colour_mode, ct_block)
+
+    def fks_config(self, real, fks_i, fks_j, prec):
+        """(real_block, colour_mode, ct_block) of one FKS sector and precision."""
+        return nlo_get_fks_config(self.ctx, proc_id(real), fks_i, fks_j, PREC[prec])
+
+    def kernel_config(self, proc, prec):
+        """(block, colour_mode) of one process and precision."""
+        return nlo_get_kernel_config(self.ctx, proc_id(proc), PREC[prec])
+
+    def tuning_cache(self, path):
+        """Apply the matching entries of the JSON tuning cache at path and merge
+        later autotune results into it; returns the number applied."""
+        return nlo_tuning_cache(self.ctx, path)
 
     def set_fks_threshold(self, thr):
         nlo_set_fks_threshold(self.ctx, thr)

@@ -25,6 +25,10 @@ class nlo_proc_info(ctypes.Structure):
                 ("gs_pow", ctypes.c_int), ("e_pow", ctypes.c_int)]
 
 
+class nlo_fks_config(ctypes.Structure):
+    _fields_ = [("real_block", ctypes.c_int), ("colour_mode", ctypes.c_int), ("ct_block", ctypes.c_int)]
+
+
 class nlo_kernel_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("colour_mode", ctypes.c_int)]
 
@@ -68,6 +72,14 @@ SIGNATURES = {
     "nlo_process_info": ([_VP, ctypes.c_int, ctypes.POINTER(nlo_proc_info)], ctypes.c_int),
     "nlo_set_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
     "nlo_get_kernel_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(nlo_kernel_config)], ctypes.c_int),
+    "nlo_set_fks_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(nlo_fks_config)], ctypes.c_int),
+    "nlo_get_fks_config": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(nlo_fks_config)], ctypes.c_int),
+    "nlo_autotune_subtracted": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP,
+                                 ctypes.c_int, _VP, _VP, ctypes.POINTER(nlo_fks_config),
+                                 ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "nlo_tuning_cache": ([_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "nlo_me2": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "nlo_me2_checked": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "nlo_reserve": ([_VP, _I64], ctypes.c_int),
@@ -224,6 +236,34 @@ def nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr):
     check(lib().nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr, ctypes.byref(best),
                              ctypes.byref(ns)))
     return (best.block, best.colour_mode), ns.value
+
+
+def nlo_set_fks_config(ctx, real_proc, fks_i, fks_j, prec, real_block, colour_mode, ct_block):
+    return check(lib().nlo_set_fks_config(ctx, real_proc, fks_i, fks_j, prec,
+                                          ctypes.byref(nlo_fks_config(real_block, colour_mode, ct_block))))
+
+
+def nlo_get_fks_config(ctx, real_proc, fks_i, fks_j, prec):
+    cfg = nlo_fks_config()
+    check(lib().nlo_get_fks_config(ctx, real_proc, fks_i, fks_j, prec, ctypes.byref(cfg)))
+    return cfg.real_block, cfg.colour_mode, cfg.ct_block
+
+
+def nlo_autotune_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, prec, w_ptr,
+                            stream_ptr):
+    """((real_block, colour_mode, ct_block), ns per event)"""
+    best = nlo_fks_config()
+    ns = ctypes.c_double()
+    check(lib().nlo_autotune_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, prec,
+                                        w_ptr, stream_ptr, ctypes.byref(best), ctypes.byref(ns)))
+    return (best.real_block, best.colour_mode, best.ct_block), ns.value
+
+
+def nlo_tuning_cache(ctx, path):
+    """Number of entries applied from the cache file at path (None: stop merging)."""
+    n = ctypes.c_int()
+    check(lib().nlo_tuning_cache(ctx, path.encode() if path else None, ctypes.byref(n)))
+    return n.value
 
 
 def nlo_uniforms(ctx, n, seed, stream, first, slot, out_ptr, stream_ptr):

@@ -79,13 +79,37 @@ def _deps(src):
     return deps
 
 
-def _compile(src, extra, verbose, force):
+def build_id():
+    """A hash of every source the library is built from (the key that ties a
+    tuning-cache entry to this build)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")) +
+                   glob.glob(os.path.join(CSRC, "generated", "*.hpp")))
+    files += [os.path.join(ROOT, "include", "nlome.h"), os.path.join(HERE, "build.py"), os.path.join(HERE, "codegen.py")]
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, extra, verbose, force, bid=None):
     obj = os.path.join(OBJ, os.path.splitext(os.path.basename(src))[0] + ".o")
+    extra = list(extra)
+    if bid is not None and os.path.basename(src) == "capi.hip":
+        extra.append('-DNLO_BUILD_ID="%s"' % bid)
+        stamp = os.path.join(OBJ, "capi.build_id")
+        if not os.path.exists(stamp) or open(stamp).read() != bid:
+            force = True
+            with open(stamp, "w") as f:
+                f.write(bid)
     if not force and os.path.exists(obj):
         t = os.path.getmtime(obj)
         if all(os.path.getmtime(d) <= t for d in _deps(src) if os.path.exists(d)):
             return obj
-    cmd = [_hipcc()] + HIPCC_FLAGS + list(extra) + unit_flags(os.path.basename(src)) + ["-c", "-o", obj, src]
+    cmd = [_hipcc()] + HIPCC_FLAGS + extra + unit_flags(os.path.basename(src)) + ["-c", "-o", obj, src]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr[-4000:]))
@@ -103,8 +127,9 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     srcs.sort(key=lambda p: 0 if p.endswith("tu_gg_ttgg_4.hip") else
               (1 if ("gg_ttgg" in p and "fks" not in p) else (2 if "gg_ttg" in p else 3)))
     jobs = jobs or min(16, os.cpu_count() or 8)
+    bid = build_id()
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra_flags, verbose, force), srcs))
+        objs = list(ex.map(lambda s: _compile(s, extra_flags, verbose, force, bid), srcs))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.run(cmd, check=True)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <string>
@@ -53,10 +54,16 @@ int auto_colour_mode(int pid, nlo_prec prec) {
 
 }  // namespace
 
+#ifndef NLO_BUILD_ID
+#define NLO_BUILD_ID "unversioned"
+#endif
+
 struct nlo_ctx {
   nlo_params params;
   std::mutex mu;
   nlo_kernel_config cfg[NPROC_][5];
+  nlo_fks_config fks_cfg[NFKS][5];   // per FKS sector (FKS_TABLE order) and precision
+  std::string tuning_path;           // JSON tuning cache that autotune results are merged into
   // MIXED routes an FKS event to FP64 when kappa = xi (1-y) (or xi (1-y^2)
   // for the beams) is below this: measured on the stress sets, FP32 keeps
   // |dW|/|W| below 1e-4 for every event with kappa >= 0.1
@@ -215,6 +222,8 @@ nlo_status nlo_create(nlo_ctx** out, const nlo_params* params) {
   c->params = *params;
   for (auto& row : c->cfg)
     for (auto& k : row) k = nlo_kernel_config{256, 0};
+  for (auto& row : c->fks_cfg)
+    for (auto& k : row) k = nlo_fks_config{256, 0, 256};
   *out = c;
   return NLO_OK;
 }
@@ -360,11 +369,11 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.jac = out->jac;
   a.status = out->status;
   a.real_out = out->real_mom;
-  const int block = 256;
+  const nlo_fks_config& fc = ctx->fks_cfg[sec - FKS_TABLE][prec];
+  const int block = fc.ct_block;
   hipError_t err = sec->map(a, block, s);
   // real |M|^2 per bucket: FP32 from the front, FP64 from the back
-  const nlo_kernel_config& kc = ctx->cfg[real_proc][prec];
-  LaunchArgs la{n, n, a.real, a.me2r, coupling_scale(real_proc, ctx->params), ctx->params.m_top, kc.block, s,
+  LaunchArgs la{n, n, a.real, a.me2r, coupling_scale(real_proc, ctx->params), ctx->params.m_top, fc.real_block, s,
                 a.cnt, 0};
   // the real |M|^2 takes the FKS pair's invariants from the radiation variables
   if (sec->j >= 0) {
@@ -377,7 +386,7 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
     la.ovp.b1 = sec->i;
   }
   la.ovv = a.pinv;
-  const bool mfma = (kc.colour_mode ? kc.colour_mode : auto_colour_mode(real_proc, prec)) == 2;
+  const bool mfma = (fc.colour_mode ? fc.colour_mode : auto_colour_mode(real_proc, prec)) == 2;
   if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
   if (err == hipSuccess && a.mode != 0) {
     la.which = 1;
@@ -405,6 +414,236 @@ struct nlo_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// tuning cache: a JSON object {"format": ..., "entries": [{...}, ...]} of flat
+// entries (string and number values), written and read here only
+// ---------------------------------------------------------------------------
+const char* const PREC_NAME[5] = {"fp64", "fp32", "fp16", "bf16", "mixed"};
+const char* const KEY_FIELDS[5] = {"arch", "cus", "runtime", "driver", "build"};
+
+struct TuneEntry {
+  std::vector<std::string> k, v;
+  std::vector<bool> str;   // value was a JSON string
+  const std::string* get(const char* key) const {
+    for (size_t i = 0; i < k.size(); ++i)
+      if (k[i] == key) return &v[i];
+    return nullptr;
+  }
+  void put(const char* key, const std::string& val, bool is_str) {
+    for (size_t i = 0; i < k.size(); ++i)
+      if (k[i] == key) {
+        v[i] = val;
+        str[i] = is_str;
+        return;
+      }
+    k.emplace_back(key);
+    v.push_back(val);
+    str.push_back(is_str);
+  }
+};
+
+// the identity of this device, runtime and build
+TuneEntry tuning_identity(int device) {
+  hipDeviceProp_t p{};
+  int rt = 0, drv = 0;
+  TuneEntry e;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) p.gcnArchName[0] = 0;
+  (void)hipRuntimeGetVersion(&rt);
+  (void)hipDriverGetVersion(&drv);
+  e.put("arch", p.gcnArchName, true);
+  e.put("cus", std::to_string(p.multiProcessorCount), false);
+  e.put("runtime", std::to_string(rt), false);
+  e.put("driver", std::to_string(drv), false);
+  e.put("build", NLO_BUILD_ID, true);
+  return e;
+}
+
+bool same_fields(const TuneEntry& a, const TuneEntry& b, const char* const* keys, int nk) {
+  for (int i = 0; i < nk; ++i) {
+    const std::string *x = a.get(keys[i]), *y = b.get(keys[i]);
+    if (!x || !y || *x != *y) return false;
+  }
+  return true;
+}
+
+bool parse_tuning(const std::string& t, std::vector<TuneEntry>& out) {
+  size_t i = t.find("\"entries\"");
+  if (i == std::string::npos) return false;
+  i = t.find('[', i);
+  if (i == std::string::npos) return false;
+  ++i;
+  auto ws = [&]() { while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\r' || t[i] == '\t' || t[i] == ',')) ++i; };
+  auto str = [&](std::string& o) {
+    if (i >= t.size() || t[i] != '"') return false;
+    ++i;
+    o.clear();
+    while (i < t.size() && t[i] != '"') {
+      if (t[i] == '\\' && i + 1 < t.size()) ++i;
+      o += t[i++];
+    }
+    if (i >= t.size()) return false;
+    ++i;
+    return true;
+  };
+  for (;;) {
+    ws();
+    if (i >= t.size()) return false;
+    if (t[i] == ']') return true;
+    if (t[i] != '{') return false;
+    ++i;
+    TuneEntry e;
+    for (;;) {
+      ws();
+      if (i >= t.size()) return false;
+      if (t[i] == '}') {
+        ++i;
+        break;
+      }
+      std::string key, val;
+      if (!str(key)) return false;
+      ws();
+      if (i >= t.size() || t[i] != ':') return false;
+      ++i;
+      while (i < t.size() && t[i] == ' ') ++i;
+      if (i < t.size() && t[i] == '"') {
+        if (!str(val)) return false;
+        e.put(key.c_str(), val, true);
+      } else {
+        const size_t b = i;
+        while (i < t.size() && t[i] != ',' && t[i] != '}' && t[i] != ' ' && t[i] != '\n') ++i;
+        val = t.substr(b, i - b);
+        char* end = nullptr;
+        (void)std::strtod(val.c_str(), &end);
+        if (val.empty() || end != val.c_str() + val.size()) return false;
+        e.put(key.c_str(), val, false);
+      }
+    }
+    out.push_back(std::move(e));
+  }
+}
+
+std::string format_tuning(const std::vector<TuneEntry>& es) {
+  std::string o = "{\"format\": \"nlome-tuning-1\",\n \"entries\": [\n";
+  for (size_t n = 0; n < es.size(); ++n) {
+    o += "  {";
+    for (size_t i = 0; i < es[n].k.size(); ++i) {
+      if (i) o += ", ";
+      o += "\"" + es[n].k[i] + "\": ";
+      if (es[n].str[i]) {
+        o += "\"";
+        for (char c : es[n].v[i]) {
+          if (c == '"' || c == '\\') o += '\\';
+          o += c;
+        }
+        o += "\"";
+      } else {
+        o += es[n].v[i];
+      }
+    }
+    o += n + 1 < es.size() ? "},\n" : "}\n";
+  }
+  return o + " ]}\n";
+}
+
+// read a cache file: missing = empty; false when it does not parse
+bool read_tuning(const std::string& path, std::vector<TuneEntry>& out) {
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return true;
+  std::string t;
+  char buf[4096];
+  size_t r;
+  while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, r);
+  std::fclose(f);
+  if (t.find_first_not_of(" \n\r\t") == std::string::npos) return true;
+  return parse_tuning(t, out);
+}
+
+int proc_by_name(const std::string& name) {
+  for (int p = 0; p < NPROC_; ++p)
+    if (name == PROC_STATIC[p].name) return p;
+  return -1;
+}
+
+int prec_by_name(const std::string& name) {
+  for (int p = 0; p < 5; ++p)
+    if (name == PREC_NAME[p]) return p;
+  return -1;
+}
+
+bool valid_block(long b) { return b >= 64 && b <= NLO_MAX_BLOCK && b % 64 == 0; }
+
+// apply one entry of this device's key to the context; false if it names
+// nothing this build has or holds an invalid configuration
+bool apply_entry(nlo_ctx* ctx, const TuneEntry& e) {
+  const std::string *kind = e.get("kind"), *proc = e.get("proc"), *prec = e.get("prec");
+  if (!kind || !proc || !prec) return false;
+  const int pid = proc_by_name(*proc), pr = prec_by_name(*prec);
+  if (pid < 0 || pr < 0) return false;
+  auto num = [&](const char* k, long& v) {
+    const std::string* x = e.get(k);
+    if (!x) return false;
+    v = std::strtol(x->c_str(), nullptr, 10);
+    return true;
+  };
+  long cm = 0;
+  if (!num("colour_mode", cm) || cm < 0 || cm > 2 || (cm == 2 && pr != NLO_FP32 && pr != NLO_MIXED)) return false;
+  if (*kind == "me2") {
+    long b = 0;
+    if (!num("block", b) || !valid_block(b)) return false;
+    ctx->cfg[pid][pr] = nlo_kernel_config{(int)b, (int)cm};
+    return true;
+  }
+  if (*kind == "subtracted") {
+    long fi = 0, fj = 0, rb = 0, cb = 0;
+    if (!num("i", fi) || !num("j", fj) || !num("real_block", rb) || !num("ct_block", cb)) return false;
+    if (!valid_block(rb) || !valid_block(cb)) return false;
+    for (int k = 0; k < NFKS; ++k)
+      if (FKS_TABLE[k].real == pid && FKS_TABLE[k].i == fi && FKS_TABLE[k].j == fj) {
+        ctx->fks_cfg[k][pr] = nlo_fks_config{(int)rb, (int)cm, (int)cb};
+        return true;
+      }
+  }
+  return false;
+}
+
+// merge one result into the context's cache file (no-op without one)
+nlo_status merge_tuning(const nlo_ctx* ctx, TuneEntry e, const char* fn) {
+  if (ctx->tuning_path.empty()) return NLO_OK;
+  std::vector<TuneEntry> es;
+  if (!read_tuning(ctx->tuning_path, es)) return fail(NLO_EINVAL, "%s: tuning cache %s does not parse", fn,
+                                                      ctx->tuning_path.c_str());
+  const TuneEntry id = tuning_identity(ctx->params.device);
+  TuneEntry full = id;
+  for (size_t i = 0; i < e.k.size(); ++i) full.put(e.k[i].c_str(), e.v[i], e.str[i]);
+  static const char* const ident[10] = {"arch", "cus", "runtime", "driver", "build", "kind", "proc", "prec", "i", "j"};
+  bool replaced = false;
+  for (TuneEntry& x : es)
+    if (same_fields(x, full, ident, 8) && (x.get("i") == nullptr) == (full.get("i") == nullptr) &&
+        (!full.get("i") || same_fields(x, full, ident + 8, 2))) {
+      x = full;
+      replaced = true;
+    }
+  if (!replaced) es.push_back(full);
+  const std::string tmp = ctx->tuning_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(NLO_EINVAL, "%s: cannot write %s", fn, tmp.c_str());
+  const std::string text = format_tuning(es);
+  const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+  if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), ctx->tuning_path.c_str()) != 0)
+    return fail(NLO_EINVAL, "%s: cannot write %s", fn, ctx->tuning_path.c_str());
+  return NLO_OK;
+}
+
+std::string fmt_double(double v) {
+  char b[64];
+  std::snprintf(b, sizeof b, "%.6g", v);
+  return b;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -638,8 +877,153 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
   (void)hipEventDestroy(e1);
   ctx->cfg[proc_id][prec] = result == NLO_OK ? win : saved;
   if (result != NLO_OK) return result;
+  const double ns = (double)win_ms * 1e6 / 3.0 / (double)n;
   if (best) *best = win;
-  if (ns_per_event) *ns_per_event = (double)win_ms * 1e6 / 3.0 / (double)n;
+  if (ns_per_event) *ns_per_event = ns;
+  TuneEntry e;
+  e.put("kind", "me2", true);
+  e.put("proc", PROC_STATIC[proc_id].name, true);
+  e.put("prec", PREC_NAME[prec], true);
+  e.put("block", std::to_string(win.block), false);
+  e.put("colour_mode", std::to_string(win.colour_mode), false);
+  e.put("ns_per_event", fmt_double(ns), false);
+  return merge_tuning(ctx, e, "nlo_autotune");
+}
+
+nlo_status nlo_set_fks_config(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, nlo_prec prec,
+                              const nlo_fks_config* cfg) {
+  const char* fn = "nlo_set_fks_config";
+  nlo_status st = check_ctx(ctx, real_proc, fn);
+  if (st) return st;
+  if (!cfg) return fail(NLO_EINVAL, "%s: cfg is NULL", fn);
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "%s: precision %d not supported (FP64, FP32, MIXED)", fn, (int)prec);
+  int k = 0;
+  while (k < NFKS && !(FKS_TABLE[k].real == real_proc && FKS_TABLE[k].i == fks_i && FKS_TABLE[k].j == fks_j)) ++k;
+  if (k == NFKS) return fail(NLO_EUNSUPPORTED, "%s: no FKS sector (%d, %d) for %s", fn, fks_i, fks_j,
+                             PROC_STATIC[real_proc].name);
+  if (!valid_block(cfg->real_block) || !valid_block(cfg->ct_block))
+    return fail(NLO_EINVAL, "%s: blocks must be multiples of 64 in [64, %d]", fn, NLO_MAX_BLOCK);
+  if (cfg->colour_mode < 0 || cfg->colour_mode > 2 || (cfg->colour_mode == 2 && prec == NLO_FP64))
+    return fail(NLO_EINVAL, "%s: bad colour_mode %d for this precision", fn, cfg->colour_mode);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->fks_cfg[k][prec] = *cfg;
+  return NLO_OK;
+}
+
+nlo_status nlo_get_fks_config(const nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, nlo_prec prec,
+                              nlo_fks_config* cfg) {
+  const char* fn = "nlo_get_fks_config";
+  nlo_status st = check_ctx(ctx, real_proc, fn);
+  if (st) return st;
+  if (!cfg) return fail(NLO_EINVAL, "%s: cfg is NULL", fn);
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "%s: precision %d not supported (FP64, FP32, MIXED)", fn, (int)prec);
+  for (int k = 0; k < NFKS; ++k)
+    if (FKS_TABLE[k].real == real_proc && FKS_TABLE[k].i == fks_i && FKS_TABLE[k].j == fks_j) {
+      *cfg = ctx->fks_cfg[k][prec];
+      return NLO_OK;
+    }
+  return fail(NLO_EUNSUPPORTED, "%s: no FKS sector (%d, %d) for %s", fn, fks_i, fks_j, PROC_STATIC[real_proc].name);
+}
+
+nlo_status nlo_autotune_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                                   const double* born_mom, const double* xi_tilde, const double* y,
+                                   const double* phi, nlo_prec prec, double* w_scratch, void* hip_stream,
+                                   nlo_fks_config* best, double* ns_per_event) {
+  const char* fn = "nlo_autotune_subtracted";
+  nlo_fks_out out{};
+  out.W = w_scratch;
+  const FksSector* sec = nullptr;
+  nlo_status st = check_subtracted(ctx, real_proc, fks_i, fks_j, n, ld, born_mom, xi_tilde, y, phi, prec, &out, &sec,
+                                   fn);
+  if (st) return st;
+  if (n <= 0) return fail(NLO_EINVAL, "%s: need n > 0", fn);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  st = check_ws(ctx, fks_ws_bytes(real_proc, n), n, fn);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(NLO_EDEVICE, "%s: event", fn);
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(NLO_EDEVICE, "%s: event", fn);
+  }
+  nlo_fks_config& cur = ctx->fks_cfg[sec - FKS_TABLE][prec];
+  const nlo_fks_config saved = cur;
+  nlo_fks_config win = saved;
+  float win_ms = -1.0f;
+  nlo_status result = NLO_OK;
+  // one warm-up and three timed calls of the configuration in cur
+  auto time_cur = [&]() {
+    float ms = -1.0f;
+    for (int rep = 0; rep < 4 && result == NLO_OK; ++rep) {
+      if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) result = fail(NLO_EDEVICE, "%s: record", fn);
+      if (result == NLO_OK) {
+        hipError_t err = launch_subtracted(ctx, sec, real_proc, n, ld, born_mom, xi_tilde, y, phi, nullptr, prec,
+                                           &out, ctx->ws, s);
+        if (err != hipSuccess) result = fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(err));
+      }
+    }
+    if (result == NLO_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      result = fail(NLO_EDEVICE, "%s: timing failed", fn);
+    if (result == NLO_OK && (win_ms < 0.0f || ms < win_ms)) {
+      win_ms = ms;
+      win = cur;
+    }
+  };
+  const bool fp32 = prec != NLO_FP64;
+  for (int rb = 64; rb <= NLO_MAX_BLOCK && result == NLO_OK; rb += 64)
+    for (int m = 1; m <= (fp32 ? 2 : 1) && result == NLO_OK; ++m) {
+      cur = nlo_fks_config{rb, m, saved.ct_block};
+      time_cur();
+    }
+  const nlo_fks_config real_win = win;
+  for (int cb = 64; cb <= NLO_MAX_BLOCK && result == NLO_OK; cb += 64) {
+    if (cb == real_win.ct_block) continue;
+    cur = nlo_fks_config{real_win.real_block, real_win.colour_mode, cb};
+    time_cur();
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cur = result == NLO_OK ? win : saved;
+  if (result != NLO_OK) return result;
+  const double ns = (double)win_ms * 1e6 / 3.0 / (double)n;
+  if (best) *best = win;
+  if (ns_per_event) *ns_per_event = ns;
+  TuneEntry e;
+  e.put("kind", "subtracted", true);
+  e.put("proc", PROC_STATIC[real_proc].name, true);
+  e.put("i", std::to_string(fks_i), false);
+  e.put("j", std::to_string(fks_j), false);
+  e.put("prec", PREC_NAME[prec], true);
+  e.put("real_block", std::to_string(win.real_block), false);
+  e.put("colour_mode", std::to_string(win.colour_mode), false);
+  e.put("ct_block", std::to_string(win.ct_block), false);
+  e.put("ns_per_event", fmt_double(ns), false);
+  return merge_tuning(ctx, e, fn);
+}
+
+nlo_status nlo_tuning_cache(nlo_ctx* ctx, const char* path, int* loaded) {
+  const char* fn = "nlo_tuning_cache";
+  if (!ctx) return fail(NLO_EINVAL, "%s: ctx is NULL", fn);
+  if (loaded) *loaded = 0;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (!path || !*path) {
+    ctx->tuning_path.clear();
+    return NLO_OK;
+  }
+  std::vector<TuneEntry> es;
+  if (!read_tuning(path, es)) return fail(NLO_EINVAL, "%s: %s does not parse as a tuning cache", fn, path);
+  const TuneEntry id = tuning_identity(ctx->params.device);
+  int n = 0;
+  for (const TuneEntry& e : es)
+    if (same_fields(e, id, KEY_FIELDS, 5) && apply_entry(ctx, e)) ++n;
+  ctx->tuning_path = path;
+  if (loaded) *loaded = n;
   return NLO_OK;
 }
 

@@ -144,3 +144,120 @@ def test_autotune_keeps_results(orc):
             assert np.all(r < (1e-11 if prec == "fp64" else 1e-3))
     finally:
         ctx.close()
+
+
+def _oracle_w_bound(orc, proc, pair, mom, xt, y, phi, idx, prec):
+    """binary128 W on the sampled events and the per-event bound of the
+    parity tests: |dW| <= 1e-12 (|W| + D) in FP64; MIXED adds 1e-3 |W| for
+    its FP32-routed events"""
+    r = orc.fks(proc, pair[0], pair[1], np.ascontiguousarray(mom[:, :, idx]), xt[idx], y[idx], phi[idx], kind="quad")
+    kap = r["xi"] * (1 - r["y"]) * ((1 + r["y"]) if pair[1] < 0 else 1.0)
+    D = sum(np.abs(r[k]) for k in ("g_R", "g_S", "g_C", "g_Cm", "g_SC", "g_SCm")) / kap
+    bound = 1e-12 * (np.abs(r["W"]) + D) + (1e-3 * np.abs(r["W"]) if prec == "mixed" else 0.0)
+    return r["W"], bound
+
+
+def test_autotuned_mix_against_oracle(orc):
+    """Every item of the mix autotuned on its own events (block size and
+    colour unit; per-sector real and counterterm blocks), planned into one
+    graph: the graph equals the tuned direct calls bit for bit, and a strided
+    sample of every item matches the oracle (|M|^2: FP64 1e-11, MIXED 1e-5,
+    FP16 median 2e-3; W: against binary128 within the parity tests' bound)."""
+    import torch
+    import paper_2503_07439_amd as nl
+    ctx = nl.Context()
+    items, bufs, direct, counts = _mix(402)
+    try:
+        tuned = []
+        for kind, proc, args, prec, out in direct:
+            if kind == "me2":
+                tuned.append(ctx.autotune(proc, args, prec)[0])
+            else:
+                pair, mom, xt, y, phi = args
+                tuned.append(ctx.autotune_subtracted(proc, pair[0], pair[1], mom, xt, y, phi, prec)[0])
+        print("tuned configurations", tuned, flush=True)
+        ref = []
+        for kind, proc, args, prec, out in direct:
+            if kind == "me2":
+                ref.append(ctx.me2(proc, args, prec).clone())
+            else:
+                pair, mom, xt, y, phi = args
+                ref.append(ctx.subtracted(proc, pair[0], pair[1], mom, xt, y, phi, prec=prec)["W"].clone())
+        ctx.reserve(int(counts.max()))
+        plan = nl.nlo_batch_plan(ctx.ctx, items, 4)
+        try:
+            nl.nlo_batch_run(plan, torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+        finally:
+            nl.nlo_plan_destroy(plan)
+        for k, ((kind, proc, args, prec, out), r) in enumerate(zip(direct, ref)):
+            got = (out if kind == "me2" else out[0]).cpu().numpy()
+            assert np.array_equal(np.nan_to_num(got), np.nan_to_num(r.cpu().numpy())), (k, proc)
+            n = got.size
+            idx = np.unique(np.linspace(0, n - 1, min(n, 64 if kind == "sub" else 128)).astype(np.int64))
+            if kind == "me2":
+                mom = args.cpu().numpy()
+                rel = np.abs(got[idx] / orc.me2(proc, np.ascontiguousarray(mom[:, :, idx])) - 1)
+                print("item %d %s %s: median %.2e max %.2e" % (k, proc, prec, np.median(rel), rel.max()), flush=True)
+                if prec == "fp64":
+                    assert np.all(rel < 1e-11)
+                elif prec == "mixed":
+                    assert np.all(rel < 1e-5)
+                else:
+                    assert np.median(rel) < 2e-3
+            else:
+                pair, mom, xt, y, phi = (a.cpu().numpy() if hasattr(a, "cpu") else a for a in args)
+                w, bound = _oracle_w_bound(orc, proc, pair, mom, xt, y, phi, idx, prec)
+                dw = np.abs(got[idx] - w)
+                print("item %d %s %s W: max |dW|/bound %.2e" % (k, proc, prec, np.max(dw / bound)), flush=True)
+                assert np.all(dw <= bound)
+    finally:
+        ctx.close()
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    """Autotune results merge into a JSON cache keyed by device, runtime and
+    build; a new context applies exactly the entries of its own key; a
+    malformed file is rejected and changes nothing."""
+    import json
+    import torch
+    import paper_2503_07439_amd as nl
+    path = str(tmp_path / "tuning.json")
+    a, b = nl.Context(), nl.Context()
+    try:
+        assert a.tuning_cache(path) == 0                       # no file yet: empty cache
+        m = torch.from_numpy(events("gg_tt", 1 << 14, (400.0, 2000.0), stream=420)[0]).cuda()
+        cfg_me2, _ = a.autotune("gg_tt", m, "mixed")
+        mom, _ = events("ee_uu", 1 << 12, 1000.0, stream=421)
+        xt, y, phi = (torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in fks_variables(1 << 12, stream=421))
+        cfg_fks, _ = a.autotune_subtracted("ee_uug", 4, 2, torch.from_numpy(mom).cuda(), xt, y, phi, "fp64")
+        doc = json.load(open(path))
+        assert doc["format"] == "nlome-tuning-1" and len(doc["entries"]) == 2
+        e_me2 = [e for e in doc["entries"] if e["kind"] == "me2"][0]
+        e_fks = [e for e in doc["entries"] if e["kind"] == "subtracted"][0]
+        for e in (e_me2, e_fks):
+            assert e["arch"].startswith("gfx950") and e["cus"] > 0 and e["runtime"] > 0 and len(e["build"]) == 16
+        assert (e_me2["proc"], e_me2["prec"], e_me2["block"], e_me2["colour_mode"]) == ("gg_tt", "mixed", *cfg_me2)
+        assert (e_fks["proc"], e_fks["i"], e_fks["j"], e_fks["prec"]) == ("ee_uug", 4, 2, "fp64")
+        assert (e_fks["real_block"], e_fks["colour_mode"], e_fks["ct_block"]) == cfg_fks
+        # tuning again replaces the entry of the same key
+        a.autotune("gg_tt", m, "mixed")
+        assert len(json.load(open(path))["entries"]) == 2
+        # a foreign key is kept in the file but not applied
+        doc["entries"].append(dict(e_me2, arch="gfx000", block=64, proc="gg_ttg"))
+        json.dump(doc, open(path, "w"))
+        b.set_kernel_config("gg_tt", "mixed", 64, 1)
+        assert b.tuning_cache(path) == 2
+        assert b.kernel_config("gg_tt", "mixed") == tuple(cfg_me2)
+        assert b.fks_config("ee_uug", 4, 2, "fp64") == tuple(cfg_fks)
+        assert b.kernel_config("gg_ttg", "mixed") == (256, 0)
+        # a malformed file: error, nothing applied
+        bad = str(tmp_path / "bad.json")
+        open(bad, "w").write('{"format": "nlome-tuning-1", "entries": [{"kind": "me2", "block": }]}')
+        with pytest.raises(nl.NloError) as e:
+            b.tuning_cache(bad)
+        assert e.value.status == 1
+        assert b.kernel_config("gg_tt", "mixed") == tuple(cfg_me2)
+    finally:
+        a.close()
+        b.close()

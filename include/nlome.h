@@ -273,7 +273,10 @@ typedef struct {
  *              phi its azimuth about that axis.
  *   mask:      device [4][ld] bytes for B, R, S, C (non-zero = passes its cuts)
  *              or NULL (all pass).  A failed cut zeroes its term after
- *              evaluation; the soft-collinear terms need both S and C.
+ *              evaluation; the soft-collinear terms need both S and C.  A C
+ *              byte with bit 1 set gives the beams' two collinear ends
+ *              separately: bit 2 the y = +1 end (g_C, g_SC), bit 3 the
+ *              y = -1 end (g_Cm, g_SCm) (nlo_fks_cut_masks writes these).
  *   prec:      NLO_FP64, NLO_FP32 (real amplitudes in float, kinematics and
  *              assembly in double) or NLO_MIXED (float unless the event is
  *              near a singular limit, see nlo_set_fks_threshold).
@@ -382,6 +385,57 @@ nlo_status nlo_phase_space(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uin
  * initial_state, a random sign of y (slot 66).  Outputs: device [n] each. */
 nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
                              int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream);
+
+/* ---- cuts: the passCuts / passAnyCuts predicates of the paper's Algorithm 2
+ * (the paper defines no cuts; these are infrared safe, so that the
+ * subtraction still cancels) ----
+ * Jets are the final-state massless coloured partons clustered by the
+ * anti-kT algorithm with radius jet_r in (rapidity, azimuth), four-momentum
+ * recombination; a parton exactly along the beam (pT = 0) is not clustered.
+ * An event passes when at least njet_min jets have pT >= jet_ptmin and
+ * |y| <= jet_ymax, every top quark has pT >= top_ptmin and |y| <= top_ymax,
+ * and every charged lepton pT >= lep_ptmin and |y| <= lep_ymax (GeV; use 0
+ * and a large number to switch a cut off). */
+typedef struct {
+  double jet_r;
+  double jet_ptmin, jet_ymax;
+  int njet_min;
+  double top_ptmin, top_ymax;
+  double lep_ptmin, lep_ymax;
+} nlo_cuts;
+
+/* pass: device uint8 [n], 1 where event e of mom (layout above, process
+ * proc_id) passes the cuts, else 0. */
+nlo_status nlo_cut_mask(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, const nlo_cuts* cuts,
+                        uint8_t* pass, void* hip_stream);
+
+/* The mask argument of nlo_subtracted for one FKS sector, every term at its
+ * own kinematics (Algorithm 2: passCuts(a, p_a)): B and S at the Born point
+ * as given (the soft limit adds a zero-energy parton, which is not
+ * clustered); R at the real point of the FKS map; C at the map's collinear
+ * end: for a final-state emitter the y = 1 point, whose collinear pair the jet
+ * algorithm merges back into the Born jet (C = B); for the beams the y = +1
+ * and y = -1 points separately, encoded as 2 | 4 (y = +1 passes) | 8 (y = -1
+ * passes), which nlo_subtracted reads per end.  mask: device [4][ld] bytes. */
+nlo_status nlo_fks_cut_masks(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                             const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                             const nlo_cuts* cuts, uint8_t* mask, void* hip_stream);
+
+/* Algorithm 2's "regenerate until a cut passes" loop as stream compaction:
+ * RAMBO candidates of proc_id (exactly as nlo_phase_space: candidate c is
+ * event first + c of (seed, stream)) are generated and cut in chunks of up to
+ * 2^20, and the passing ones written, in candidate order, to mom (layout
+ * above, [npart][4][ld]) and weight ([n], or NULL) until n have passed.
+ * *trials (host) receives the number of candidates used, i.e. one past the
+ * index of the n-th passing one, so that a Monte Carlo estimate over the cut
+ * region is (1/trials) sum over the n outputs.  Candidates are generated twice
+ * (count, then scatter) instead of stored; a block's count and its position
+ * among the passing candidates come from fixed-order scans, so the output is
+ * the same for any chunking.  Synchronises the stream once per chunk.  Fails
+ * with NLO_EINVAL when 2^26 candidates in a row pass nothing. */
+nlo_status nlo_generate_passing(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uint32_t seed, uint32_t stream,
+                                uint64_t first, double sqrt_s_lo, double sqrt_s_hi, const nlo_cuts* cuts,
+                                double* mom, double* weight, uint64_t* trials, void* hip_stream);
 
 /* Partonic cross section of proc_id at fixed sqrt(s_hat) by plain Monte Carlo
  * integration (the paper's section "Monte-Carlo integration": the mean of the

@@ -79,17 +79,23 @@ def anti_kt(partons, R, tie):
     objs = [np.asarray(p, dtype=float) for p in partons if pt(p) > 0.0]
     jets = []
     while objs:
-        # the smallest of d_iB = 1/pT_i^2 and d_ij = min(1/pT_i^2, 1/pT_j^2) dR_ij^2 / R^2
-        best, bi, bj = None, -1, -1
+        # the smallest of d_iB = 1/pT_i^2 and d_ij = min(1/pT_i^2, 1/pT_j^2) dR_ij^2 / R^2,
+        # the first one in list order on an exact tie
+        cand = []
         for i, a in enumerate(objs):
-            d = 1.0 / pt(a) ** 2
-            if best is None or tie.lt(d, best):
-                best, bi, bj = d, i, -1
+            cand.append((1.0 / pt(a) ** 2, i, -1))
             for j in range(i + 1, len(objs)):
                 b = objs[j]
-                d = min(1.0 / pt(a) ** 2, 1.0 / pt(b) ** 2) * delta_r2(a, b) / (R * R)
-                if tie.lt(d, best):
-                    best, bi, bj = d, i, j
+                cand.append((min(1.0 / pt(a) ** 2, 1.0 / pt(b) ** 2) * delta_r2(a, b) / (R * R), i, j))
+        best, bi, bj = cand[0]
+        for d, i, j in cand[1:]:
+            if d < best:
+                best, bi, bj = d, i, j
+        # a near tie decides the outcome unless both distances are beam
+        # distances (the minimal beam distances become jets in either order)
+        for d, i, j in cand:
+            if (i, j) != (bi, bj) and not (j < 0 and bj < 0):
+                tie.lt(d, best)
         if bj < 0:
             jets.append(objs.pop(bi))
         else:

@@ -12,7 +12,8 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_batch_run, nlo_plan_destroy, NLO_ITEM_ME2, NLO_ITEM_SUBTRACTED, nlo_autotune,
                    nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
                    nlo_me2_checked, nlo_reserve, nlo_colour_unit, nlo_integrate_subtracted, nlo_fks_config,
-                   nlo_set_fks_config, nlo_get_fks_config, nlo_autotune_subtracted, nlo_tuning_cache)
+                   nlo_set_fks_config, nlo_get_fks_config, nlo_autotune_subtracted, nlo_tuning_cache, nlo_cuts,
+                   make_cuts, nlo_cut_mask, nlo_fks_cut_masks, nlo_generate_passing)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -156,6 +157,36 @@ class Context:
     def kernel_config(self, proc, prec):
         """(block, colour_mode) of one process and precision."""
         return nlo_get_kernel_config(self.ctx, proc_id(proc), PREC[prec])
+
+    def cut_mask(self, proc, mom, cuts):
+        """uint8 CUDA [n]: 1 where an event passes the cuts (dict of nlo_cuts fields)"""
+        import torch
+        n = mom.shape[2]
+        out = torch.empty(n, dtype=torch.uint8, device=mom.device)
+        nlo_cut_mask(self.ctx, proc_id(proc), n, n, mom.data_ptr(), make_cuts(cuts), out.data_ptr(), self._stream())
+        return out
+
+    def fks_cut_masks(self, real, fks_i, fks_j, born_mom, xi_tilde, y, phi, cuts):
+        """uint8 CUDA [4][n]: the B, R, S, C masks of nlo_subtracted from the cuts"""
+        import torch
+        n = born_mom.shape[2]
+        out = torch.empty((4, n), dtype=torch.uint8, device=born_mom.device)
+        nlo_fks_cut_masks(self.ctx, proc_id(real), fks_i, fks_j, n, n, born_mom.data_ptr(), xi_tilde.data_ptr(),
+                          y.data_ptr(), phi.data_ptr(), make_cuts(cuts), out.data_ptr(), self._stream())
+        return out
+
+    def generate_passing(self, proc, n, sqrt_s, stream, cuts, first=0, seed=7439):
+        """n RAMBO points that pass the cuts, in candidate order: (mom CUDA
+        [npart][4][n], weight [n], number of candidates used)"""
+        import torch
+        lo, hi = sqrt_s if isinstance(sqrt_s, tuple) else (sqrt_s, sqrt_s)
+        npart = self.info(proc).npart
+        mom = torch.empty((npart, 4, n), dtype=torch.float64, device="cuda")
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        self.reserve(1)
+        t = nlo_generate_passing(self.ctx, proc_id(proc), n, n, seed, stream, first, float(lo), float(hi),
+                                 make_cuts(cuts), mom.data_ptr(), w.data_ptr(), self._stream())
+        return mom, w, t
 
     def tuning_cache(self, path):
         """Apply the matching entries of the JSON tuning cache at path and merge

@@ -25,6 +25,20 @@ class nlo_proc_info(ctypes.Structure):
                 ("gs_pow", ctypes.c_int), ("e_pow", ctypes.c_int)]
 
 
+class nlo_cuts(ctypes.Structure):
+    _fields_ = [("jet_r", ctypes.c_double), ("jet_ptmin", ctypes.c_double), ("jet_ymax", ctypes.c_double),
+                ("njet_min", ctypes.c_int), ("top_ptmin", ctypes.c_double), ("top_ymax", ctypes.c_double),
+                ("lep_ptmin", ctypes.c_double), ("lep_ymax", ctypes.c_double)]
+
+
+def make_cuts(d):
+    """nlo_cuts from a dict with the field names (missing cuts are off)"""
+    c = nlo_cuts(0.4, 0.0, 1e300, 0, 0.0, 1e300, 0.0, 1e300)
+    for k, v in d.items():
+        setattr(c, k, v)
+    return c
+
+
 class nlo_fks_config(ctypes.Structure):
     _fields_ = [("real_block", ctypes.c_int), ("colour_mode", ctypes.c_int), ("ct_block", ctypes.c_int)]
 
@@ -80,6 +94,12 @@ SIGNATURES = {
                                  ctypes.c_int, _VP, _VP, ctypes.POINTER(nlo_fks_config),
                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "nlo_tuning_cache": ([_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "nlo_cut_mask": ([_VP, ctypes.c_int, _I64, _I64, _VP, ctypes.POINTER(nlo_cuts), _VP, _VP], ctypes.c_int),
+    "nlo_fks_cut_masks": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP,
+                           ctypes.POINTER(nlo_cuts), _VP, _VP], ctypes.c_int),
+    "nlo_generate_passing": ([_VP, ctypes.c_int, _I64, _I64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                              ctypes.c_double, ctypes.c_double, ctypes.POINTER(nlo_cuts), _VP, _VP,
+                              ctypes.POINTER(ctypes.c_uint64), _VP], ctypes.c_int),
     "nlo_me2": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "nlo_me2_checked": ([_VP, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "nlo_reserve": ([_VP, _I64], ctypes.c_int),
@@ -264,6 +284,24 @@ def nlo_tuning_cache(ctx, path):
     n = ctypes.c_int()
     check(lib().nlo_tuning_cache(ctx, path.encode() if path else None, ctypes.byref(n)))
     return n.value
+
+
+def nlo_cut_mask(ctx, proc_id, n, ld, mom_ptr, cuts, pass_ptr, stream_ptr):
+    return check(lib().nlo_cut_mask(ctx, proc_id, n, ld, mom_ptr, ctypes.byref(cuts), pass_ptr, stream_ptr))
+
+
+def nlo_fks_cut_masks(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, cuts, mask_ptr,
+                      stream_ptr):
+    return check(lib().nlo_fks_cut_masks(ctx, real_proc, fks_i, fks_j, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr,
+                                         ctypes.byref(cuts), mask_ptr, stream_ptr))
+
+
+def nlo_generate_passing(ctx, proc_id, n, ld, seed, stream, first, rs_lo, rs_hi, cuts, mom_ptr, w_ptr, stream_ptr):
+    """number of candidates used"""
+    t = ctypes.c_uint64()
+    check(lib().nlo_generate_passing(ctx, proc_id, n, ld, seed, stream, first, rs_lo, rs_hi, ctypes.byref(cuts),
+                                     mom_ptr, w_ptr, ctypes.byref(t), stream_ptr))
+    return t.value
 
 
 def nlo_uniforms(ctx, n, seed, stream, first, slot, out_ptr, stream_ptr):

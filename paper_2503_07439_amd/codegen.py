@@ -623,6 +623,9 @@ def _crational(x):
 # ---------------------------------------------------------------------------
 # process list
 # ---------------------------------------------------------------------------
+LEPTONS = ("e-", "e+", "mu-", "mu+")
+
+
 def process_list():
     return [
         Process("ee_mumu", ["e-", "e+"], ["mu-", "mu+"], {"a"}, 0.25),
@@ -1056,6 +1059,8 @@ def emit_process(p):
     L.append("  static constexpr const char* NAME = \"%s\";" % nm)
     L.append("  static constexpr unsigned TOP_LEGS = 0x%x;   // bit k: leg k is a top quark"
              % sum(1 << k for k, x in enumerate(list(p.incoming) + list(p.outgoing)) if x in ("t", "t~")))
+    L.append("  static constexpr unsigned LEP_LEGS = 0x%x;   // bit k: leg k is a charged lepton"
+             % sum(1 << k for k, x in enumerate(list(p.incoming) + list(p.outgoing)) if x in LEPTONS))
     L.append("  __device__ static int good(int i) { return %s_good[i]; }" % nm)
     # per-event data
     L.append("  template <class T> struct Pre {")
@@ -1332,9 +1337,10 @@ def generate(out_dir):
     for p in procs:
         gs, ee = p.coupling_powers()
         tops = sum(1 << k for k, x in enumerate(list(p.incoming) + list(p.outgoing)) if x in ("t", "t~"))
-        index.append('  {"%s", %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %.17g, %.17g, %du},' % (
+        leps = sum(1 << k for k, x in enumerate(list(p.incoming) + list(p.outgoing)) if x in LEPTONS)
+        index.append('  {"%s", %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %.17g, %.17g, %du, %du},' % (
             p.name, p.npart, len(p.incoming), len(p.flows), 1 << p.npart, len(p.good_helicities()), p.ndiagrams,
-            len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee, p.avg, p.ident, tops))
+            len(p.amps), len([n for n in p.nodes if n.kind != "ext"]), gs, ee, p.avg, p.ident, tops, leps))
     index.append("};")
     index.append("static const me2_launcher ME2_LAUNCH[NPROC][NVAR] = {")
     for p in procs:
@@ -1346,6 +1352,7 @@ def generate(out_dir):
     index.append("  const char* name; int real, born, bornm, i, j;")
     index.append("  hipError_t (*map)(const FksArgs&, int, hipStream_t);")
     index.append("  hipError_t (*born_fn[2])(const FksArgs&, int, int, hipStream_t);   // [0] double, [1] float")
+    index.append("  hipError_t (*cuts)(const FksCutArgs&, hipStream_t);")
     index.append("};")
     decl, rows = [], []
     pid = {p.name: k for k, p in enumerate(procs)}
@@ -1359,6 +1366,7 @@ def generate(out_dir):
             body = ['#include "../fks.hpp"', '#include "%s.hpp"' % name, "namespace nlo {"]
             if v == 0:
                 body.append("hipError_t %s_map(const FksArgs& a, int block, hipStream_t st) { return launch_fks_map<%s>(a, block, st); }" % (name, name))
+                body.append("hipError_t %s_cuts(const FksCutArgs& a, hipStream_t st) { return launch_fks_cuts<%s>(a, st); }" % (name, name))
             body.append("hipError_t %s_born%d(const FksArgs& a, int which, int block, hipStream_t st) { return launch_fks_born<%s, %s>(a, which, block, st); }" % (name, v, name, T))
             body.append("}  // namespace nlo")
             path = os.path.join(out_dir, "tu_%s_%d.hip" % (name, v))
@@ -1367,8 +1375,9 @@ def generate(out_dir):
         decl.append("hipError_t %s_map(const FksArgs&, int, hipStream_t);" % name)
         decl.append("hipError_t %s_born0(const FksArgs&, int, int, hipStream_t);" % name)
         decl.append("hipError_t %s_born1(const FksArgs&, int, int, hipStream_t);" % name)
-        rows.append('  {"%s", %d, %d, %d, %d, %d, %s_map, {%s_born0, %s_born1}},' % (
-            name, pid[real], pid[born], pid[bornm or born], i, j, name, name, name))
+        decl.append("hipError_t %s_cuts(const FksCutArgs&, hipStream_t);" % name)
+        rows.append('  {"%s", %d, %d, %d, %d, %d, %s_map, {%s_born0, %s_born1}, %s_cuts},' % (
+            name, pid[real], pid[born], pid[bornm or born], i, j, name, name, name, name))
     index.extend(decl)
     index.append("constexpr int NFKS = %d;" % len(FKS_SECTORS))
     index.append("static const FksSector FKS_TABLE[NFKS] = {")

@@ -317,6 +317,29 @@ size_t int_ws_bytes(int real_proc, int64_t n, int niter) {
 
 constexpr int INT_MAX_ITER = 64;
 
+// nlo_generate_passing: block counts and offsets of one chunk, its total and
+// the trial count
+size_t gen_ws_bytes() { return 2 * (size_t)(GEN_CHUNK / 256) * sizeof(unsigned) + 256; }
+
+// final-state leg classes of a process for the cuts
+CutLegs legs_of(int pid) {
+  const ProcStatic& P = PROC_STATIC[pid];
+  const int nf = P.npart - P.nin;
+  const unsigned all = (1u << nf) - 1u;
+  const unsigned top = (P.top_legs >> P.nin) & all, lep = (P.lep_legs >> P.nin) & all;
+  return CutLegs{all & ~top & ~lep, top, lep};
+}
+
+nlo_status check_cuts(const nlo_cuts* c, const char* fn) {
+  if (!c) return fail(NLO_EINVAL, "%s: cuts is NULL", fn);
+  const double v[7] = {c->jet_r, c->jet_ptmin, c->jet_ymax, c->top_ptmin, c->top_ymax, c->lep_ptmin, c->lep_ymax};
+  for (double x : v)
+    if (std::isnan(x)) return fail(NLO_EINVAL, "%s: a cut is NaN", fn);
+  if (!(c->jet_r > 0.0)) return fail(NLO_EINVAL, "%s: jet_r must be positive", fn);
+  if (c->njet_min < 0) return fail(NLO_EINVAL, "%s: njet_min < 0", fn);
+  return NLO_OK;
+}
+
 // workspace that serves every evaluation call of up to n events: the largest
 // FKS sector, a half-width |M|^2 launch, a cross-section chunk and an
 // integration of up to min(n, 2^20) points per iteration
@@ -325,7 +348,7 @@ size_t ws_bytes_for(int64_t n) {
   for (const FksSector& f : FKS_TABLE) b = std::max(b, fks_ws_bytes(f.real, n));
   for (int p = 0; p < NPROC_; ++p) b = std::max(b, xs_ws_bytes(PROC_STATIC[p].npart, std::min(n, XS_CHUNK)));
   for (const FksSector& f : FKS_TABLE) b = std::max(b, int_ws_bytes(f.real, std::min(n, XS_CHUNK), INT_MAX_ITER));
-  return b;
+  return std::max(b, gen_ws_bytes());
 }
 
 // the launch sequence of one FKS sector on stream s with workspace ws
@@ -1390,6 +1413,139 @@ nlo_status nlo_integrate_subtracted(nlo_ctx* ctx, int real_proc, double sqrt_s_b
   if (error_pb) *error_pb = sw > 0.0 ? 1.0 / std::sqrt(sw) : 0.0;
   if (chi2_dof) *chi2_dof = niter - nadapt > 1 ? chi / (niter - nadapt - 1) : 0.0;
   if (nd) return fail(NLO_EDEVICE, "%s: %u points gave a non-finite integrand", fn, nd);
+  return NLO_OK;
+}
+
+nlo_status nlo_cut_mask(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, const double* mom, const nlo_cuts* cuts,
+                        uint8_t* pass, void* hip_stream) {
+  const char* fn = "nlo_cut_mask";
+  nlo_status st = check_ctx(ctx, proc_id, fn);
+  if (st) return st;
+  st = check_cuts(cuts, fn);
+  if (st) return st;
+  if (n < 0 || ld < n) return fail(NLO_EINVAL, "%s: need 0 <= n <= ld", fn);
+  if (n == 0) return NLO_OK;
+  if (!mom || !pass) return fail(NLO_EINVAL, "%s: NULL device pointer", fn);
+  const ProcStatic& P = PROC_STATIC[proc_id];
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  hipError_t e = launch_cut_mask(P.npart - P.nin, n, ld, P.nin, mom, legs_of(proc_id), *cuts, pass,
+                                 (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  return NLO_OK;
+}
+
+nlo_status nlo_fks_cut_masks(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
+                             const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
+                             const nlo_cuts* cuts, uint8_t* mask, void* hip_stream) {
+  const char* fn = "nlo_fks_cut_masks";
+  nlo_status st = check_ctx(ctx, real_proc, fn);
+  if (st) return st;
+  st = check_cuts(cuts, fn);
+  if (st) return st;
+  const FksSector* sec = nullptr;
+  for (const FksSector& f : FKS_TABLE)
+    if (f.real == real_proc && f.i == fks_i && f.j == fks_j) sec = &f;
+  if (!sec) return fail(NLO_EUNSUPPORTED, "%s: no FKS sector (%d, %d) for %s", fn, fks_i, fks_j,
+                        PROC_STATIC[real_proc].name);
+  if (n < 0 || ld < n) return fail(NLO_EINVAL, "%s: need 0 <= n <= ld", fn);
+  if (n == 0) return NLO_OK;
+  if (!born_mom || !xi_tilde || !y || !phi || !mask) return fail(NLO_EINVAL, "%s: NULL device pointer", fn);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  FksCutArgs a{};
+  a.n = n;
+  a.ld = ld;
+  a.born = born_mom;
+  a.xit = xi_tilde;
+  a.y = y;
+  a.phi = phi;
+  a.mt = ctx->params.m_top;
+  a.cuts = *cuts;
+  a.mask = mask;
+  hipError_t e = sec->cuts(a, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  return NLO_OK;
+}
+
+nlo_status nlo_generate_passing(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uint32_t seed, uint32_t stream,
+                                uint64_t first, double sqrt_s_lo, double sqrt_s_hi, const nlo_cuts* cuts,
+                                double* mom, double* weight, uint64_t* trials, void* hip_stream) {
+  const char* fn = "nlo_generate_passing";
+  nlo_status st = check_ctx(ctx, proc_id, fn);
+  if (st) return st;
+  st = check_cuts(cuts, fn);
+  if (st) return st;
+  if (n < 0 || ld < n || n > 0x7fffffffLL) return fail(NLO_EINVAL, "%s: need 0 <= n <= ld, n < 2^31", fn);
+  if (!trials) return fail(NLO_EINVAL, "%s: trials is NULL", fn);
+  *trials = 0;
+  if (n == 0) return NLO_OK;
+  if (!mom) return fail(NLO_EINVAL, "%s: mom is NULL", fn);
+  const ProcStatic& P = PROC_STATIC[proc_id];
+  const int nf = P.npart - P.nin;
+  if (P.nin != 2 || nf < 2 || nf > 4) return fail(NLO_EUNSUPPORTED, "%s: %s not supported", fn, P.name);
+  GenArgs a{};
+  double msum = 0.0;
+  for (int k = 0; k < nf; ++k) {
+    a.mass[k] = (P.top_legs >> (k + 2)) & 1u ? ctx->params.m_top : 0.0;
+    msum += a.mass[k];
+  }
+  if (!(sqrt_s_lo > msum) || !(sqrt_s_hi >= sqrt_s_lo) || !std::isfinite(sqrt_s_hi))
+    return fail(NLO_EINVAL, "%s: need %g < sqrt_s_lo <= sqrt_s_hi < inf", fn, msum);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  st = check_ws(ctx, gen_ws_bytes(), 1, fn);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  unsigned* base = static_cast<unsigned*>(ctx->ws);
+  a.bcount = base;
+  a.boff = base + GEN_CHUNK / 256;
+  uintptr_t c = reinterpret_cast<uintptr_t>(a.boff + GEN_CHUNK / 256);
+  c = (c + 63) & ~uintptr_t(63);
+  a.total = reinterpret_cast<unsigned*>(c);
+  a.trials = reinterpret_cast<uint64_t*>(c + 64);
+  a.n = n;
+  a.ld = ld;
+  a.seed = seed;
+  a.stream = stream;
+  a.first0 = first;
+  a.rs_lo = sqrt_s_lo;
+  a.rs_hi = sqrt_s_hi;
+  a.legs = legs_of(proc_id);
+  a.cuts = *cuts;
+  a.mom = mom;
+  a.weight = weight;
+  uint64_t cand = first, dry = 0;
+  int64_t have = 0;
+  while (have < n) {
+    // as many candidates as the acceptance so far suggests, at least 2^16
+    int64_t m = GEN_CHUNK;
+    if (have > 0) {
+      const double acc = (double)have / (double)(cand - first);
+      m = std::min<int64_t>(GEN_CHUNK, std::max<int64_t>(65536, (int64_t)(1.2 * (double)(n - have) / acc) + 1));
+    } else if (cand == first) {
+      m = std::min<int64_t>(GEN_CHUNK, std::max<int64_t>(65536, 2 * n));
+    }
+    a.m = m;
+    a.have = have;
+    a.first = cand;
+    hipError_t e = launch_generate_chunk(nf, a, s);
+    unsigned tot = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&tot, a.total, sizeof tot, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
+    have += tot;
+    cand += (uint64_t)m;
+    dry = tot ? 0 : dry + (uint64_t)m;
+    if (dry >= ((uint64_t)1 << 26))
+      return fail(NLO_EINVAL, "%s: no candidate passed the cuts in %llu in a row", fn, (unsigned long long)dry);
+  }
+  hipError_t e = hipMemcpyAsync(trials, a.trials, sizeof *trials, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
   return NLO_OK;
 }
 

@@ -28,6 +28,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include "cuts.hpp"
 #include "helas.hpp"
 #include "launch.hpp"
 
@@ -409,13 +410,19 @@ __device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e
   uint8_t st = (which & 1) ? 2 : 0;
   double Bo = B;
   if (a.mask) {
-    const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e], mC = a.mask[3 * a.ld + e];
+    const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e];
+    // C byte: non-zero = passes; with bit 1 set, bits 2 and 3 give the y = +1
+    // and y = -1 ends of the beams separately
+    const uint8_t mC = a.mask[3 * a.ld + e];
+    const bool cp = (mC & 2) ? (mC & 4) != 0 : mC != 0, cm = (mC & 2) ? (mC & 8) != 0 : mC != 0;
     if (!mB) Bo = 0.0;
     if (!mR) gR = 0.0;
     if (!mS) gS = 0.0;
-    if (!mC) { gC = 0.0; gCm = 0.0; }
-    if (!mS || !mC) { gSC = 0.0; gSCm = 0.0; }
-    if (!(mB && mR && mS && mC)) st |= 4;
+    if (!cp) gC = 0.0;
+    if (!cm) gCm = 0.0;
+    if (!mS || !cp) gSC = 0.0;
+    if (!mS || !cm) gSCm = 0.0;
+    if (!(mB && mR && mS && cp && (S::J >= 0 || cm))) st |= 4;
   }
   double W;
   if constexpr (S::J >= 0) {
@@ -637,6 +644,76 @@ static __global__ __launch_bounds__(1024) void k_sum_fixed(int64_t n, const doub
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = part[0];
+}
+
+// ---------------------------------------------------------------------------
+// cut masks of an FKS sector: every term at its own kinematics
+// ---------------------------------------------------------------------------
+struct FksCutArgs {
+  int64_t n, ld;
+  const double* born;              // [NB][4][ld]
+  const double *xit, *y, *phi;     // [n]
+  double mt;
+  nlo_cuts cuts;
+  uint8_t* mask;                   // [4][ld]: B, R, S, C
+};
+
+template <class P, int NF>
+__device__ __forceinline__ CutLegs cut_legs_of() {
+  constexpr unsigned all = (1u << NF) - 1u;
+  const unsigned top = (P::TOP_LEGS >> 2) & all, lep = (P::LEP_LEGS >> 2) & all;
+  return CutLegs{all & ~top & ~lep, top, lep};
+}
+
+// B and S at the Born point as given (the soft limit adds a zero-energy
+// parton, which is not clustered); R at the real point of the map; C at the
+// map's collinear end(s): a final-state emitter's y = 1 point has i and j
+// collinear, which the jet algorithm merges back into the Born jet (C = B);
+// for the beams the y = +1 and y = -1 points are evaluated and encoded as
+// 2 | 4 (y = +1 passes) | 8 (y = -1 passes).
+template <class S>
+__global__ __launch_bounds__(256) void k_fks_cuts(FksCutArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n) return;
+  constexpr int NBF = S::NB - 2, NRF = S::NR - 2;
+  double kb[S::NB][4], fb[NBF][4], fr[NRF][4], kr[S::NR][4];
+#pragma unroll
+  for (int k = 0; k < S::NB; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) kb[k][m] = a.born[(k * 4 + m) * a.ld + e];
+#pragma unroll
+  for (int k = 0; k < NBF; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) fb[k][m] = kb[k + 2][m];
+  const bool pb = cut_pass<NBF>(fb, cut_legs_of<typename S::Born, NBF>(), a.cuts);
+  fks_project_born<S>(kb, a.mt);
+  const CutLegs lr = cut_legs_of<typename S::Real, NRF>();
+  auto real_pass = [&](double y) {
+    FksKin K;
+    fks_map<S>(kb, a.xit[e], y, a.phi[e], kr, K);
+#pragma unroll
+    for (int k = 0; k < NRF; ++k)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) fr[k][m] = kr[k + 2][m];
+    return cut_pass<NRF>(fr, lr, a.cuts);
+  };
+  const bool pr = real_pass(a.y[e]);
+  uint8_t c;
+  if constexpr (S::J >= 0) {
+    c = pb;
+  } else {
+    c = (uint8_t)(2u | (real_pass(1.0) ? 4u : 0u) | (real_pass(-1.0) ? 8u : 0u));
+  }
+  a.mask[0 * a.ld + e] = pb;
+  a.mask[1 * a.ld + e] = pr;
+  a.mask[2 * a.ld + e] = pb;
+  a.mask[3 * a.ld + e] = c;
+}
+
+template <class S>
+hipError_t launch_fks_cuts(const FksCutArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fks_cuts<S>), dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 template <class S>

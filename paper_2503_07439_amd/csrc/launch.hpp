@@ -45,6 +45,7 @@ struct ProcStatic {
   int npart, nin, nflow, nhel, ngood, ndiag, nterm, ncur, gs_pow, e_pow;
   double avg, ident;
   unsigned top_legs;   // bit k set: leg k is a top quark (mass m_t), else massless
+  unsigned lep_legs;   // bit k set: leg k is a charged lepton
 };
 
 typedef hipError_t (*me2_launcher)(const LaunchArgs&);

@@ -18,6 +18,7 @@
 // final states.  One event per lane, all in FP64.
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include "cuts.hpp"
 #include "phase_space.hpp"
 
 namespace nlo {
@@ -170,24 +171,126 @@ __device__ __forceinline__ void store_event(const double (&p)[NF][4], double rs,
     for (int m = 0; m < 4; ++m) mom[((k + 2) * 4 + m) * ld + i] = p[k][m];
 }
 
+// the batch recipe's point of event e: sqrt(s_hat) from slot 64, particle k
+// from slots 2k and 2k + 1
+template <int NF>
+__device__ __forceinline__ void recipe_point(uint32_t seed, uint32_t stream, uint64_t e, double rs_lo, double rs_hi,
+                                             const double* mass, double (&p)[NF][4], double& w, double& rs) {
+  double u0, u1;
+  uniform2(seed, stream, e, 64, u0, u1);
+  rs = rs_lo + (rs_hi - rs_lo) * u0;
+  double u[NF][4];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    uniform2(seed, stream, e, 2 * k, u[k][0], u[k][1]);
+    uniform2(seed, stream, e, 2 * k + 1, u[k][2], u[k][3]);
+  }
+  rambo_point<NF>(u, rs, mass, p, w);
+}
+
 template <int NF>
 __global__ __launch_bounds__(256) void k_rambo(PsArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const uint64_t e = a.first + (uint64_t)i;
-  double u0, u1;
-  uniform2(a.seed, a.stream, e, 64, u0, u1);
-  const double rs = a.rs_lo + (a.rs_hi - a.rs_lo) * u0;
-  double u[NF][4];
-#pragma unroll
-  for (int k = 0; k < NF; ++k) {
-    uniform2(a.seed, a.stream, e, 2 * k, u[k][0], u[k][1]);
-    uniform2(a.seed, a.stream, e, 2 * k + 1, u[k][2], u[k][3]);
-  }
-  double p[NF][4], w;
-  rambo_point<NF>(u, rs, a.mass, p, w);
+  double p[NF][4], w, rs;
+  recipe_point<NF>(a.seed, a.stream, a.first + (uint64_t)i, a.rs_lo, a.rs_hi, a.mass, p, w, rs);
   store_event<NF>(p, rs, a.mom, a.ld, i);
   if (a.weight) a.weight[i] = w;
+}
+
+// ---------------------------------------------------------------------------
+// cuts (cuts.hpp) on batches, and Algorithm 2's regenerate-until-pass loop as
+// stream compaction
+// ---------------------------------------------------------------------------
+template <int NF>
+__global__ __launch_bounds__(256) void k_cut_mask(int64_t n, int64_t ld, int nin, const double* __restrict__ mom,
+                                                  CutLegs legs, nlo_cuts cuts, uint8_t* __restrict__ pass) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double fin[NF][4];
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) fin[k][m] = mom[((nin + k) * 4 + m) * ld + e];
+  pass[e] = cut_pass<NF>(fin, legs, cuts) ? 1 : 0;
+}
+
+// passing candidates of this block's 256 (wave ballots, waves in order):
+// returns the candidate's rank among them, or -1 if it fails
+__device__ __forceinline__ int block_rank(bool ok, unsigned* total) {
+  __shared__ unsigned wcnt[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(ok);
+  if (lane == 0) wcnt[wave] = (unsigned)__popcll(m);
+  __syncthreads();
+  unsigned before = 0u;
+  for (int w = 0; w < wave; ++w) before += wcnt[w];
+  if (total) *total = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+  const unsigned long long lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+  return ok ? (int)(before + (unsigned)__popcll(m & lower)) : -1;
+}
+
+// pass 1: how many of each block's 256 candidates pass
+template <int NF>
+__global__ __launch_bounds__(256) void k_gen_count(GenArgs a) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool ok = false;
+  if (c < a.m) {
+    double p[NF][4], w, rs;
+    recipe_point<NF>(a.seed, a.stream, a.first + (uint64_t)c, a.rs_lo, a.rs_hi, a.mass, p, w, rs);
+    ok = cut_pass<NF>(p, a.legs, a.cuts);
+  }
+  unsigned tot;
+  (void)block_rank(ok, &tot);
+  if (threadIdx.x == 0) a.bcount[blockIdx.x] = tot;
+}
+
+// exclusive scan of the block counts in block order (one block of 256
+// threads: each thread owns a contiguous run of blocks), and the total
+__global__ __launch_bounds__(256) void k_gen_scan(int nblocks, const unsigned* __restrict__ bcount,
+                                                  unsigned* __restrict__ boff, unsigned* __restrict__ total) {
+  __shared__ unsigned part[256];
+  const int t = threadIdx.x, per = (nblocks + 255) / 256;
+  const int lo = t * per, hi = lo + per < nblocks ? lo + per : nblocks;
+  unsigned s = 0u;
+  for (int b = lo; b < hi; ++b) s += bcount[b];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    unsigned run = 0u;
+    for (int k = 0; k < 256; ++k) {
+      const unsigned v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  unsigned run = part[t];
+  for (int b = lo; b < hi; ++b) {
+    boff[b] = run;
+    run += bcount[b];
+  }
+}
+
+// pass 2: regenerate, and write the passing candidates at their ranks (those
+// below the target); the n-th passing candidate records the trial count
+template <int NF>
+__global__ __launch_bounds__(256) void k_gen_scatter(GenArgs a) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool ok = false;
+  double p[NF][4], w = 0.0, rs = 0.0;
+  if (c < a.m) {
+    recipe_point<NF>(a.seed, a.stream, a.first + (uint64_t)c, a.rs_lo, a.rs_hi, a.mass, p, w, rs);
+    ok = cut_pass<NF>(p, a.legs, a.cuts);
+  }
+  const int r = block_rank(ok, nullptr);
+  if (r < 0) return;
+  const int64_t rank = a.have + (int64_t)a.boff[blockIdx.x] + r;
+  if (rank >= a.n) return;
+  store_event<NF>(p, rs, a.mom, a.ld, rank);
+  if (a.weight) a.weight[rank] = w;
+  if (rank == a.n - 1) *a.trials = a.first + (uint64_t)c + 1 - a.first0;
 }
 
 // FKS radiation variables: xi_tilde and 1 - |y| log-uniform in [1e-6, 1],
@@ -503,6 +606,36 @@ hipError_t launch_rambo(int nfin, const PsArgs& a, hipStream_t st) {
     case 3: hipLaunchKernelGGL(k_rambo<3>, grid, block, 0, st, a); break;
     case 4: hipLaunchKernelGGL(k_rambo<4>, grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cut_mask(int nfin, int64_t n, int64_t ld, int nin, const double* mom, const CutLegs& legs,
+                           const nlo_cuts& cuts, uint8_t* pass, hipStream_t st) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (nfin) {
+    case 2: hipLaunchKernelGGL(k_cut_mask<2>, grid, block, 0, st, n, ld, nin, mom, legs, cuts, pass); break;
+    case 3: hipLaunchKernelGGL(k_cut_mask<3>, grid, block, 0, st, n, ld, nin, mom, legs, cuts, pass); break;
+    case 4: hipLaunchKernelGGL(k_cut_mask<4>, grid, block, 0, st, n, ld, nin, mom, legs, cuts, pass); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_generate_chunk(int nfin, const GenArgs& a, hipStream_t st) {
+  const unsigned nb = (unsigned)((a.m + 255) / 256);
+  const dim3 grid(nb), block(256);
+  switch (nfin) {
+    case 2: hipLaunchKernelGGL(k_gen_count<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_gen_count<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_gen_count<4>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_gen_scan, dim3(1), dim3(256), 0, st, (int)nb, (const unsigned*)a.bcount, a.boff, a.total);
+  switch (nfin) {
+    case 2: hipLaunchKernelGGL(k_gen_scatter<2>, grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_gen_scatter<3>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_gen_scatter<4>, grid, block, 0, st, a); break;
   }
   return hipGetLastError();
 }

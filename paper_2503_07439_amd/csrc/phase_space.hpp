@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "cuts.hpp"
+
 namespace nlo {
 
 struct PsArgs {
@@ -15,8 +17,30 @@ struct PsArgs {
   double* weight;            // [n] RAMBO weight, or null
 };
 
+// Algorithm 2's regenerate-until-pass loop, one chunk of m candidates:
+// candidates first .. first + m - 1 of the batch recipe; the passing ones get
+// ranks have, have + 1, ... in candidate order, and those below n are written
+// to mom/weight at their rank; the candidate of rank n - 1 writes
+// *trials = its counter + 1 - first0; *total = this chunk's passing count
+constexpr int64_t GEN_CHUNK = (int64_t)1 << 20;
+struct GenArgs {
+  int64_t n, ld, m, have;
+  uint32_t seed, stream;
+  uint64_t first, first0;
+  double rs_lo, rs_hi;
+  double mass[8];
+  CutLegs legs;
+  nlo_cuts cuts;
+  unsigned *bcount, *boff, *total;   // [m / 256], [m / 256], [1]
+  uint64_t* trials;
+  double *mom, *weight;
+};
+
 hipError_t launch_uniforms(int64_t n, uint32_t seed, uint32_t stream, uint64_t first, uint32_t slot, double* out,
                            hipStream_t st);
+hipError_t launch_cut_mask(int nfin, int64_t n, int64_t ld, int nin, const double* mom, const CutLegs& legs,
+                           const nlo_cuts& cuts, uint8_t* pass, hipStream_t st);
+hipError_t launch_generate_chunk(int nfin, const GenArgs& a, hipStream_t st);
 hipError_t launch_rambo(int nfin, const PsArgs& a, hipStream_t st);
 hipError_t launch_fks_variables(int64_t n, uint32_t seed, uint32_t stream, uint64_t first, int initial_state,
                                 double* xit, double* y, double* phi, hipStream_t st);

@@ -226,6 +226,16 @@ def integrate_leg(ctx):
                          "ms_per_iteration": dt * 1e3 / niter, "points_per_s": n * niter / dt,
                          "sigma_pb": sig, "error_pb": err, "chi2_dof": chi,
                          "first_iteration_error_pb": its[0][1], "last_iteration_error_pb": its[-1][1]})
+            if real == "ee_uug":
+                # the complete NLO correction from device pieces: the Born-proportional
+                # virtual + integrated counterterms and this subtracted real emission
+                mom, w = ctx.phase_space("ee_uu", n, rs, 331)
+                b, vi = ctx.virtual_integrated("ee_uu", mom, prec)
+                alpha = 1.0 / 132.507
+                sig_b = 3 * (2.0 / 3.0) ** 2 * 4 * math.pi * alpha ** 2 / (3 * rs * rs) * 0.3893793721e9
+                rows[-1]["nlo_k_factor_minus_1"] = float((w * vi).sum() / (w * b).sum()) + sig / sig_b
+                rows[-1]["nlo_k_factor_error"] = err / sig_b
+                rows[-1]["alpha_s_over_pi"] = 0.118 / math.pi
     return rows
 
 

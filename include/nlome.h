@@ -386,6 +386,26 @@ nlo_status nlo_phase_space(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uin
 nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
                              int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream);
 
+/* Born and the finite part of virtual + integrated counterterms, per event
+ * (the paper's NLO section: the virtual correction and the FKS counterterms
+ * added back, integrated in d = 4 - 2 eps dimensions, where their poles
+ * cancel).  For a Born with exactly two massless coloured partons (e+e- ->
+ * u ubar, the Born of the sectors (4,2) and (4,3) of e+e- -> u ubar g) every
+ * piece is proportional to the Born: with the subtraction of nlo_subtracted
+ * (always subtract, xi_c = 1, delta = 2, these sector functions) the
+ * counterterms integrate to (alpha_s C_F / 2 pi) c_Gamma (4 pi mu^2 / s)^eps
+ * [2/eps^2 + 3/eps + 13 - 5 pi^2 / 3] B and the one-loop quark form factor to
+ * [-2/eps^2 - 3/eps - 8 + pi^2] B, so
+ *   vi[e] = B (alpha_s C_F / 2 pi) (5 - 2 pi^2 / 3),   B = born[e] (as nlo_me2),
+ * independent of the renormalisation scale.  With the subtracted real
+ * emission integrated (nlo_integrate_subtracted) the total is
+ * sigma_B (1 + alpha_s / pi).  prec: FP64, FP32 or MIXED (of the Born).
+ * Other Borns: NLO_EUNSUPPORTED (their integrated soft counterterms need
+ * colour-linked Borns with massive eikonal integrals, and beam collinear
+ * remnants need parton densities). */
+nlo_status nlo_virtual_integrated(nlo_ctx* ctx, int born_proc, int64_t n, int64_t ld, const double* mom,
+                                  nlo_prec prec, double* born, double* vi, void* hip_stream);
+
 /* ---- cuts: the passCuts / passAnyCuts predicates of the paper's Algorithm 2
  * (the paper defines no cuts; these are infrared safe, so that the
  * subtraction still cancels) ----

@@ -13,7 +13,7 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
                    nlo_me2_checked, nlo_reserve, nlo_colour_unit, nlo_integrate_subtracted, nlo_fks_config,
                    nlo_set_fks_config, nlo_get_fks_config, nlo_autotune_subtracted, nlo_tuning_cache, nlo_cuts,
-                   make_cuts, nlo_cut_mask, nlo_fks_cut_masks, nlo_generate_passing)
+                   make_cuts, nlo_cut_mask, nlo_fks_cut_masks, nlo_generate_passing, nlo_virtual_integrated)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -157,6 +157,16 @@ class Context:
     def kernel_config(self, proc, prec):
         """(block, colour_mode) of one process and precision."""
         return nlo_get_kernel_config(self.ctx, proc_id(proc), PREC[prec])
+
+    def virtual_integrated(self, born_proc, mom, prec="fp64"):
+        """(Born |M|^2, finite virtual + integrated counterterms) per event, CUDA [n] each"""
+        import torch
+        n = mom.shape[2]
+        b = torch.empty(n, dtype=torch.float64, device=mom.device)
+        vi = torch.empty(n, dtype=torch.float64, device=mom.device)
+        nlo_virtual_integrated(self.ctx, proc_id(born_proc), n, n, mom.data_ptr(), PREC[prec], b.data_ptr(),
+                               vi.data_ptr(), self._stream())
+        return b, vi
 
     def cut_mask(self, proc, mom, cuts):
         """uint8 CUDA [n]: 1 where an event passes the cuts (dict of nlo_cuts fields)"""

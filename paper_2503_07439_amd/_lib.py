@@ -94,6 +94,7 @@ SIGNATURES = {
                                  ctypes.c_int, _VP, _VP, ctypes.POINTER(nlo_fks_config),
                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "nlo_tuning_cache": ([_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "nlo_virtual_integrated": ([_VP, ctypes.c_int, _I64, _I64, _VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
     "nlo_cut_mask": ([_VP, ctypes.c_int, _I64, _I64, _VP, ctypes.POINTER(nlo_cuts), _VP, _VP], ctypes.c_int),
     "nlo_fks_cut_masks": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP,
                            ctypes.POINTER(nlo_cuts), _VP, _VP], ctypes.c_int),
@@ -284,6 +285,10 @@ def nlo_tuning_cache(ctx, path):
     n = ctypes.c_int()
     check(lib().nlo_tuning_cache(ctx, path.encode() if path else None, ctypes.byref(n)))
     return n.value
+
+
+def nlo_virtual_integrated(ctx, born_proc, n, ld, mom_ptr, prec, born_ptr, vi_ptr, stream_ptr):
+    return check(lib().nlo_virtual_integrated(ctx, born_proc, n, ld, mom_ptr, prec, born_ptr, vi_ptr, stream_ptr))
 
 
 def nlo_cut_mask(ctx, proc_id, n, ld, mom_ptr, cuts, pass_ptr, stream_ptr):

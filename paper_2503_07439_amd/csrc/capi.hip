@@ -1549,4 +1549,30 @@ nlo_status nlo_generate_passing(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld
   return NLO_OK;
 }
 
+nlo_status nlo_virtual_integrated(nlo_ctx* ctx, int born_proc, int64_t n, int64_t ld, const double* mom,
+                                  nlo_prec prec, double* born, double* vi, void* hip_stream) {
+  const char* fn = "nlo_virtual_integrated";
+  nlo_status st = check_ctx(ctx, born_proc, fn);
+  if (st) return st;
+  if (std::strcmp(PROC_STATIC[born_proc].name, "ee_uu") != 0)
+    return fail(NLO_EUNSUPPORTED, "%s: %s: only a Born with two massless coloured partons (ee_uu)", fn,
+                PROC_STATIC[born_proc].name);
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "%s: precision %d not supported (FP64, FP32, MIXED)", fn, (int)prec);
+  if (n < 0 || ld < n) return fail(NLO_EINVAL, "%s: need 0 <= n <= ld", fn);
+  if (n == 0) return NLO_OK;
+  if (!mom || !born || !vi) return fail(NLO_EINVAL, "%s: NULL device pointer", fn);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  st = launch_me2(ctx, born_proc, n, ld, mom, born, prec, s);
+  if (st) return st;
+  const double cf = 4.0 / 3.0;
+  const double c = ctx->params.alpha_s * cf / (2.0 * M_PI) * (5.0 - 2.0 * M_PI * M_PI / 3.0);
+  hipError_t e = launch_scale(n, born, c, vi, s);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  return NLO_OK;
+}
+
 }  // extern "C"

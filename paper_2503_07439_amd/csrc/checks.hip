@@ -44,4 +44,15 @@ hipError_t launch_mark_list(int64_t n, const unsigned* cnt, const unsigned* list
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_scale(int64_t n, const double* __restrict__ in, double c,
+                                               double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = c * in[e];
+}
+
+hipError_t launch_scale(int64_t n, const double* in, double c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, in, c, out);
+  return hipGetLastError();
+}
+
 }  // namespace nlo

@@ -57,8 +57,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true", help="skip the other |M|^2 configurations and gg->ttgg")
     ap.add_argument("--no-fks", action="store_true", help="skip the subtracted-weight legs")
     ap.add_argument("--no-integrate", action="store_true", help="skip the device integration leg")
-    ap.add_argument("--mask-study", action="store_true",
-                    help="also time branch-free against compact cut masks on the 2^18 gg->ttgg (4,5) FKS set")
+    ap.add_argument("--no-mask-study", action="store_true", help="skip the cut-mask study")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -320,39 +319,71 @@ def mix_leg(ctx, steps):
 def mask_study(ctx, steps):
     """Wasted compute of branch-free cut masks (every term evaluated, failed
     ones zeroed) against compact masks (events failing the R cut skip the
-    real |M|^2), for several pass fractions of the R cut (other cuts pass)."""
+    real |M|^2, events failing every Born-level cut skip the Born amplitudes)
+    and against the cut-class buffer (16 calls of 2^14 events each, too few
+    to fill the chip on their own; a real and a counterterm queue, each
+    evaluated when it holds 2^16 events), for several pass fractions of the R
+    cut and of the S and C cuts together."""
     import torch
     from nlo_inputs.philox import uniforms
     from nlo_inputs.workloads import events, fks_variables
-    n = 1 << 18
+    n, piece = 1 << 18, 1 << 14
     mom, _ = events("gg_ttg", n, (400.0, 2000.0), stream=42)
     xt, y, phi = fks_variables(n, stream=42)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     M, X, Y, P = t(mom), t(xt), t(y), t(phi)
-    u = uniforms(7439, 43, np.arange(n, dtype=np.uint64), 0)[:, 0]
+    slots = t(np.arange(n, dtype=np.uint32))
+    u = uniforms(7439, 43, np.arange(n, dtype=np.uint64), 0)
+    w = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ctx.reserve(n)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
     rows = []
-    for frac in (1.0, 0.5, 0.25):
-        mask = np.ones((4, n), dtype=np.uint8)
-        mask[1] = (u < frac).astype(np.uint8)
+    for r_pass, ct_pass in ((1.0, 1.0), (0.5, 1.0), (0.25, 1.0), (0.5, 0.5), (1.0, 0.25)):
+        mask = np.zeros((4, n), dtype=np.uint8)
+        mask[0] = 1
+        mask[1] = (u[:, 0] < r_pass).astype(np.uint8)
+        mask[2] = mask[3] = (u[:, 1] < ct_pass).astype(np.uint8)
         tm = t(mask)
         ms = {}
         for mode in (False, True):
             ctx.set_fks_mask_mode(mode)
-            fn = lambda: ctx.subtracted("gg_ttgg", 4, 5, M, X, Y, P, prec="mixed", mask=tm)
-            fn()
-            torch.cuda.synchronize()
-            t0 = torch.cuda.Event(enable_timing=True)
-            t1 = torch.cuda.Event(enable_timing=True)
-            t0.record()
-            for _ in range(steps):
-                fn()
-            t1.record()
-            torch.cuda.synchronize()
-            ms["compact" if mode else "branch_free"] = t0.elapsed_time(t1) / steps
+            ms["compact" if mode else "branch_free"] = timed(
+                lambda: ctx.subtracted("gg_ttgg", 4, 5, M, X, Y, P, prec="mixed", mask=tm))
+        # the same 16 small calls one after another, compact, without buffering
+        pieces = [(M[:, :, k:k + piece].contiguous(), X[k:k + piece], Y[k:k + piece], P[k:k + piece],
+                   tm[:, k:k + piece].contiguous()) for k in range(0, n, piece)]
+        ms["per_call"] = timed(lambda: [ctx.subtracted("gg_ttgg", 4, 5, a, b, c, d, prec="mixed", mask=e)
+                                        for a, b, c, d, e in pieces])
         ctx.set_fks_mask_mode(False)
-        rows.append({"r_pass": frac, "branch_free_ms": ms["branch_free"], "compact_ms": ms["compact"],
-                     "wasted_fraction": 1 - ms["compact"] / ms["branch_free"]})
-    return {"sector": "gg_ttgg (4,5)", "events": n, "precision": "mixed", "rows": rows}
+        buf = ctx.fks_buffer("gg_ttgg", 4, 5, "mixed", 4 * piece, w)
+
+        def buffered():
+            for k in range(0, n, piece):
+                sl = slice(k, k + piece)
+                buf.push(M[:, :, sl].contiguous(), X[sl], Y[sl], P[sl], tm[:, sl].contiguous(), slots[sl])
+            buf.flush()
+
+        try:
+            ms["buffered"] = timed(buffered)
+        finally:
+            buf.close()
+        rows.append({"r_pass": r_pass, "ct_pass": ct_pass, "branch_free_ms": ms["branch_free"],
+                     "compact_ms": ms["compact"], "buffered_16_calls_ms": ms["buffered"],
+                     "compact_16_calls_ms": ms["per_call"],
+                     "wasted_fraction_branch_free": 1 - ms["compact"] / ms["branch_free"]})
+    return {"sector": "gg_ttgg (4,5)", "events": n, "precision": "mixed", "buffer_pieces": n // piece, "rows": rows}
 
 
 def measured_traffic(kernel, n):
@@ -565,7 +596,7 @@ def main():
         # single-issue vector FP32 rate is the attainable ceiling
         roofline["frac_of_unpacked_fp32_peak"] = achieved / PEAK["fp64"]
 
-    study = mask_study(ctx, 3) if args.mask_study else None
+    study = None if args.no_mask_study else mask_study(ctx, 2)
 
     others = None
     if not args.no_configs:

@@ -294,9 +294,10 @@ typedef struct {
  *   0 (default): branch-free, as in the paper's Algorithm 2 -- every term is
  *      evaluated at every point and failed cuts zero it afterwards;
  *   1: compact -- events whose R cut fails are set aside by the map kernel
- *      and skip the real |M|^2 evaluation (the paper's "smarter" variant that
- *      evaluates only points passing a cut; its other terms are evaluated as
- *      before).  Results are bit for bit those of mode 0. */
+ *      and skip the real |M|^2 evaluation, and events none of whose B, S and
+ *      C cuts passes skip the Born amplitudes (the paper's "smarter" variant
+ *      that evaluates only points passing a cut).  Results are bit for bit
+ *      those of mode 0. */
 nlo_status nlo_set_fks_mask_mode(nlo_ctx* ctx, int mode);
 
 nlo_status nlo_subtracted(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, int64_t n, int64_t ld,
@@ -385,6 +386,34 @@ nlo_status nlo_phase_space(nlo_ctx* ctx, int proc_id, int64_t n, int64_t ld, uin
  * initial_state, a random sign of y (slot 66).  Outputs: device [n] each. */
 nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t stream, uint64_t first,
                              int initial_state, double* xi_tilde, double* y, double* phi, void* hip_stream);
+
+/* Buffered FKS evaluation: the paper's "smarter" alternative to branch-free
+ * masking (end of section "A data parallel algorithm") -- points are stored
+ * per cut class and evaluated once enough of them pass, across calls.  Two
+ * class queues per buffer: the real emission (events whose R cut passes) and
+ * the counterterms (events whose S cut or either collinear cut passes).  A
+ * queue is evaluated (its own terms only: the real |M|^2 without Born
+ * amplitudes, or the Born-level counterterms without the real |M|^2) when it
+ * holds at least `threshold` events, and by nlo_fks_buffer_flush; each
+ * evaluation adds its contribution to W to w_out[slot] (device float64,
+ * caller-owned, zeroed by the caller; one slot per event), so that after the
+ * flush w_out[slot] = W of nlo_subtracted with the same masks (up to the
+ * rounding of the two-part sum, within 1e-12 of D in FP64).  Each slot
+ * receives at most one contribution per queue, added in stream order, so the
+ * result does not depend on how events were pushed.  create allocates the
+ * queues and their own FKS workspace (2 threshold events); push and flush
+ * allocate nothing and synchronise the stream once per pushed piece (to read
+ * the queue sizes).  One buffer serves one stream at a time. */
+typedef struct nlo_fks_buffer nlo_fks_buffer;
+nlo_status nlo_fks_buffer_create(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, nlo_prec prec,
+                                 int64_t threshold, double* w_out, nlo_fks_buffer** out);
+/* born_mom, xi_tilde, y, phi, mask: as nlo_subtracted (mask may be NULL: all
+ * pass); slot: device uint32 [n], the w_out index of each event */
+nlo_status nlo_fks_buffer_push(nlo_fks_buffer* buf, int64_t n, int64_t ld, const double* born_mom,
+                               const double* xi_tilde, const double* y, const double* phi, const uint8_t* mask,
+                               const uint32_t* slot, void* hip_stream);
+nlo_status nlo_fks_buffer_flush(nlo_fks_buffer* buf, void* hip_stream);
+nlo_status nlo_fks_buffer_destroy(nlo_fks_buffer* buf);
 
 /* Born and the finite part of virtual + integrated counterterms, per event
  * (the paper's NLO section: the virtual correction and the FKS counterterms

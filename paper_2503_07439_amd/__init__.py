@@ -13,7 +13,8 @@ from ._lib import (NLO_FP64, NLO_FP32, NLO_FP16, NLO_BF16, NLO_MIXED, PREC, NloE
                    nlo_uniforms, nlo_phase_space, nlo_fks_variables, nlo_cross_section, nlo_set_fks_mask_mode,
                    nlo_me2_checked, nlo_reserve, nlo_colour_unit, nlo_integrate_subtracted, nlo_fks_config,
                    nlo_set_fks_config, nlo_get_fks_config, nlo_autotune_subtracted, nlo_tuning_cache, nlo_cuts,
-                   make_cuts, nlo_cut_mask, nlo_fks_cut_masks, nlo_generate_passing, nlo_virtual_integrated)
+                   make_cuts, nlo_cut_mask, nlo_fks_cut_masks, nlo_generate_passing, nlo_virtual_integrated,
+                   nlo_fks_buffer_create, nlo_fks_buffer_push, nlo_fks_buffer_flush, nlo_fks_buffer_destroy)
 
 PROCESSES = ["ee_mumu", "ee_uu", "ee_uug", "gg_tt", "uu_tt", "gg_ttg", "uu_ttg", "ug_ttu", "gg_ttgg"]
 
@@ -157,6 +158,32 @@ class Context:
     def kernel_config(self, proc, prec):
         """(block, colour_mode) of one process and precision."""
         return nlo_get_kernel_config(self.ctx, proc_id(proc), PREC[prec])
+
+    def fks_buffer(self, real, fks_i, fks_j, prec, threshold, w_out):
+        """A buffered evaluator of one FKS sector adding W contributions to
+        w_out (float64 CUDA, zeroed by the caller): .push(born, xt, y, phi,
+        mask, slot), .flush(), .close()."""
+        ctx = self
+
+        class _Buf:
+            def __init__(self):
+                self.b = nlo_fks_buffer_create(ctx.ctx, proc_id(real), fks_i, fks_j, PREC[prec], threshold,
+                                               w_out.data_ptr())
+
+            def push(self, born, xt, y, phi, mask, slot):
+                n = born.shape[2]
+                nlo_fks_buffer_push(self.b, n, n, born.data_ptr(), xt.data_ptr(), y.data_ptr(), phi.data_ptr(),
+                                    mask.data_ptr() if mask is not None else None, slot.data_ptr(), ctx._stream())
+
+            def flush(self):
+                nlo_fks_buffer_flush(self.b, ctx._stream())
+
+            def close(self):
+                if self.b:
+                    nlo_fks_buffer_destroy(self.b)
+                    self.b = None
+
+        return _Buf()
 
     def virtual_integrated(self, born_proc, mom, prec="fp64"):
         """(Born |M|^2, finite virtual + integrated counterterms) per event, CUDA [n] each"""

@@ -94,6 +94,11 @@ SIGNATURES = {
                                  ctypes.c_int, _VP, _VP, ctypes.POINTER(nlo_fks_config),
                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "nlo_tuning_cache": ([_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "nlo_fks_buffer_create": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _VP,
+                               ctypes.POINTER(_VP)], ctypes.c_int),
+    "nlo_fks_buffer_push": ([_VP, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "nlo_fks_buffer_flush": ([_VP, _VP], ctypes.c_int),
+    "nlo_fks_buffer_destroy": ([_VP], ctypes.c_int),
     "nlo_virtual_integrated": ([_VP, ctypes.c_int, _I64, _I64, _VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
     "nlo_cut_mask": ([_VP, ctypes.c_int, _I64, _I64, _VP, ctypes.POINTER(nlo_cuts), _VP, _VP], ctypes.c_int),
     "nlo_fks_cut_masks": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I64, _I64, _VP, _VP, _VP, _VP,
@@ -285,6 +290,25 @@ def nlo_tuning_cache(ctx, path):
     n = ctypes.c_int()
     check(lib().nlo_tuning_cache(ctx, path.encode() if path else None, ctypes.byref(n)))
     return n.value
+
+
+def nlo_fks_buffer_create(ctx, real_proc, fks_i, fks_j, prec, threshold, w_ptr):
+    b = _VP()
+    check(lib().nlo_fks_buffer_create(ctx, real_proc, fks_i, fks_j, prec, threshold, w_ptr, ctypes.byref(b)))
+    return b
+
+
+def nlo_fks_buffer_push(buf, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, mask_ptr, slot_ptr, stream_ptr):
+    return check(lib().nlo_fks_buffer_push(buf, n, ld, born_ptr, xit_ptr, y_ptr, phi_ptr, mask_ptr, slot_ptr,
+                                           stream_ptr))
+
+
+def nlo_fks_buffer_flush(buf, stream_ptr):
+    return check(lib().nlo_fks_buffer_flush(buf, stream_ptr))
+
+
+def nlo_fks_buffer_destroy(buf):
+    return check(lib().nlo_fks_buffer_destroy(buf))
 
 
 def nlo_virtual_integrated(ctx, born_proc, n, ld, mom_ptr, prec, born_ptr, vi_ptr, stream_ptr):

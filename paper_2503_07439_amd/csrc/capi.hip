@@ -354,7 +354,8 @@ size_t ws_bytes_for(int64_t n) {
 // the launch sequence of one FKS sector on stream s with workspace ws
 hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_proc, int64_t n, int64_t ld,
                              const double* born_mom, const double* xi_tilde, const double* y, const double* phi,
-                             const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* ws, hipStream_t s) {
+                             const uint8_t* mask, nlo_prec prec, const nlo_fks_out* out, void* ws, hipStream_t s,
+                             bool force_compact = false) {
   const int nr = PROC_STATIC[real_proc].npart;
   char* base = static_cast<char*>(ws);
   FksArgs a{};
@@ -372,7 +373,7 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.skip_inv = a.inv + n;
   uintptr_t c = reinterpret_cast<uintptr_t>(a.skip_inv + n);
   a.cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
-  a.compact = (ctx->fks_compact && mask) ? 1 : 0;
+  a.compact = ((ctx->fks_compact || force_compact) && mask) ? 1 : 0;
   a.thr = ctx->fks_thr;
   a.mode = prec == NLO_FP64 ? 1 : (prec == NLO_FP32 ? 0 : 2);
   a.scale_b = coupling_scale(sec->born, ctx->params);
@@ -1572,6 +1573,169 @@ nlo_status nlo_virtual_integrated(nlo_ctx* ctx, int born_proc, int64_t n, int64_
   const double c = ctx->params.alpha_s * cf / (2.0 * M_PI) * (5.0 - 2.0 * M_PI * M_PI / 3.0);
   hipError_t e = launch_scale(n, born, c, vi, s);
   if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  return NLO_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// buffered FKS evaluation: cut-class queues that fill across calls
+// ---------------------------------------------------------------------------
+struct nlo_fks_buffer {
+  nlo_ctx* ctx = nullptr;
+  const FksSector* sec = nullptr;
+  int real = 0;
+  nlo_prec prec = NLO_FP64;
+  int64_t threshold = 0, cap = 0;
+  double* w_out = nullptr;
+  FksQueue q[2] = {};
+  unsigned* cnt = nullptr;
+  int64_t host_cnt[2] = {0, 0};
+  double* wq = nullptr;     // W of one queue evaluation [cap]
+  void* ws = nullptr;       // FKS workspace for cap events
+  void* block = nullptr;    // the one device allocation holding all of the above
+};
+
+namespace {
+
+// evaluate queue c (its events' own terms only) and add the results to their slots
+nlo_status buffer_eval(nlo_fks_buffer* b, int c, hipStream_t s, const char* fn) {
+  const int64_t m = b->host_cnt[c];
+  if (m == 0) return NLO_OK;
+  nlo_fks_out o{};
+  o.W = b->wq;
+  hipError_t e = launch_subtracted(b->ctx, b->sec, b->real, m, b->cap, b->q[c].born, b->q[c].xit, b->q[c].y,
+                                   b->q[c].phi, b->q[c].mask, b->prec, &o, b->ws, s, true);
+  if (e == hipSuccess) e = launch_queue_scatter(m, b->q[c].slot, b->wq, b->w_out, s);
+  if (e == hipSuccess) e = launch_queue_reset(b->cnt, c, s);
+  if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
+  b->host_cnt[c] = 0;
+  return NLO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nlo_status nlo_fks_buffer_create(nlo_ctx* ctx, int real_proc, int fks_i, int fks_j, nlo_prec prec,
+                                 int64_t threshold, double* w_out, nlo_fks_buffer** out) {
+  const char* fn = "nlo_fks_buffer_create";
+  if (!out) return fail(NLO_EINVAL, "%s: out is NULL", fn);
+  *out = nullptr;
+  nlo_status st = check_ctx(ctx, real_proc, fn);
+  if (st) return st;
+  const FksSector* sec = nullptr;
+  for (const FksSector& f : FKS_TABLE)
+    if (f.real == real_proc && f.i == fks_i && f.j == fks_j) sec = &f;
+  if (!sec) return fail(NLO_EUNSUPPORTED, "%s: no FKS sector (%d, %d) for %s", fn, fks_i, fks_j,
+                        PROC_STATIC[real_proc].name);
+  if (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)
+    return fail(NLO_EUNSUPPORTED, "%s: precision %d not supported (FP64, FP32, MIXED)", fn, (int)prec);
+  if (threshold < 1 || threshold > ((int64_t)1 << 24)) return fail(NLO_EINVAL, "%s: threshold in [1, 2^24]", fn);
+  if (!w_out) return fail(NLO_EINVAL, "%s: w_out is NULL", fn);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  st = use_device(ctx, fn);
+  if (st) return st;
+  nlo_fks_buffer* b = new (std::nothrow) nlo_fks_buffer;
+  if (!b) return fail(NLO_ENOMEM, "%s: out of host memory", fn);
+  b->ctx = ctx;
+  b->sec = sec;
+  b->real = real_proc;
+  b->prec = prec;
+  b->threshold = threshold;
+  b->cap = 2 * threshold;
+  b->w_out = w_out;
+  const int nb = PROC_STATIC[sec->born].npart;
+  const size_t cap = (size_t)b->cap;
+  const size_t per_q = cap * (nb * 4 + 3) * sizeof(double) + cap * sizeof(unsigned) + 4 * cap + 256;
+  const size_t ws_b = (fks_ws_bytes(real_proc, b->cap) + 255) & ~size_t(255);
+  const size_t total = 2 * per_q + cap * sizeof(double) + 256 + ws_b + 256;
+  if (hipMalloc(&b->block, total) != hipSuccess) {
+    delete b;
+    return fail(NLO_ENOMEM, "%s: device allocation of %zu bytes failed", fn, total);
+  }
+  char* p = static_cast<char*>(b->block);
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  for (int c = 0; c < 2; ++c) {
+    b->q[c].born = reinterpret_cast<double*>(take(cap * nb * 4 * sizeof(double)));
+    b->q[c].xit = reinterpret_cast<double*>(take(cap * sizeof(double)));
+    b->q[c].y = reinterpret_cast<double*>(take(cap * sizeof(double)));
+    b->q[c].phi = reinterpret_cast<double*>(take(cap * sizeof(double)));
+    b->q[c].slot = reinterpret_cast<unsigned*>(take(cap * sizeof(unsigned)));
+    b->q[c].mask = reinterpret_cast<uint8_t*>(take(4 * cap));
+  }
+  b->wq = reinterpret_cast<double*>(take(cap * sizeof(double)));
+  b->cnt = reinterpret_cast<unsigned*>(take(256));
+  b->ws = take(ws_b);
+  hipError_t e = launch_queue_reset(b->cnt, 0, nullptr);
+  if (e == hipSuccess) e = launch_queue_reset(b->cnt, 1, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    (void)hipFree(b->block);
+    delete b;
+    return fail(NLO_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
+  }
+  *out = b;
+  return NLO_OK;
+}
+
+nlo_status nlo_fks_buffer_push(nlo_fks_buffer* b, int64_t n, int64_t ld, const double* born_mom,
+                               const double* xi_tilde, const double* y, const double* phi, const uint8_t* mask,
+                               const uint32_t* slot, void* hip_stream) {
+  const char* fn = "nlo_fks_buffer_push";
+  if (!b) return fail(NLO_EINVAL, "%s: buffer is NULL", fn);
+  if (n < 0 || ld < n) return fail(NLO_EINVAL, "%s: need 0 <= n <= ld", fn);
+  if (n == 0) return NLO_OK;
+  if (!born_mom || !xi_tilde || !y || !phi || !slot) return fail(NLO_EINVAL, "%s: NULL device pointer", fn);
+  std::lock_guard<std::mutex> g(b->ctx->mu);
+  nlo_status st = use_device(b->ctx, fn);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nb = PROC_STATIC[b->sec->born].npart;
+  int64_t off = 0;
+  while (off < n) {
+    const int64_t room = b->cap - std::max(b->host_cnt[0], b->host_cnt[1]);
+    if (room < b->threshold) {        // cannot happen after the evaluations below; kept as a guard
+      for (int c = 0; c < 2; ++c)
+        if ((st = buffer_eval(b, c, s, fn))) return st;
+      continue;
+    }
+    const int64_t m = std::min(n - off, room);
+    // inputs of events off .. off + m - 1: pointers shifted by off, same leading dimension
+    hipError_t e = launch_queue_push(m, ld, nb, born_mom + off, xi_tilde + off, y + off, phi + off,
+                                     mask ? mask + off : nullptr, slot + off, b->q[0], b->q[1], b->cap, b->cnt, s);
+    unsigned h[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, b->cnt, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(NLO_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
+    b->host_cnt[0] = h[0];
+    b->host_cnt[1] = h[1];
+    for (int c = 0; c < 2; ++c)
+      if (b->host_cnt[c] >= b->threshold && (st = buffer_eval(b, c, s, fn))) return st;
+    off += m;
+  }
+  return NLO_OK;
+}
+
+nlo_status nlo_fks_buffer_flush(nlo_fks_buffer* b, void* hip_stream) {
+  const char* fn = "nlo_fks_buffer_flush";
+  if (!b) return fail(NLO_EINVAL, "%s: buffer is NULL", fn);
+  std::lock_guard<std::mutex> g(b->ctx->mu);
+  nlo_status st = use_device(b->ctx, fn);
+  if (st) return st;
+  for (int c = 0; c < 2; ++c)
+    if ((st = buffer_eval(b, c, (hipStream_t)hip_stream, fn))) return st;
+  return NLO_OK;
+}
+
+nlo_status nlo_fks_buffer_destroy(nlo_fks_buffer* b) {
+  if (!b) return NLO_OK;
+  if (b->block) (void)hipFree(b->block);
+  delete b;
   return NLO_OK;
 }
 

@@ -530,6 +530,20 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     fks_quark_isr<S, T>(a, which, pos, e, kb, K, S_real);
     return;
   } else {
+  // compact mode: an event none of whose Born-level terms (B, S, C) passes
+  // its cut skips the Born amplitudes; the masks would zero them anyway, so
+  // the outputs are those of the branch-free evaluation bit for bit
+  if (a.compact && a.mask) {
+    const uint8_t mC = a.mask[3 * a.ld + e];
+    const bool cany = (mC & 2) ? (mC & 12) != 0 : mC != 0;
+    if (!a.mask[0 * a.ld + e] && !a.mask[2 * a.ld + e] && !cany) {
+      const double me2r = skipped ? 0.0 : a.me2r[pos];
+      const double gR = S::J >= 0 ? K.xi * K.xi * (1.0 - K.y) * me2r * S_real
+                                  : K.xi * K.xi * (1.0 - K.y) * (1.0 + K.y) * me2r * S_real;
+      fks_store<S>(a, which, e, 0.0, gR, 0.0, 0.0, 0.0, 0.0, 0.0, K);
+      return;
+    }
+  }
 
   // Born: |M|^2 and the helicity-summed density Re(J_u J_v^*) of the flow
   // vector, over the nested schedule of the |M|^2 kernels.  Both sums are

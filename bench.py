@@ -107,9 +107,11 @@ def device_batch(ctx, proc, n, rs, stream):
 def kernel_name(ctx, proc, prec):
     if prec in ("fp16", "bf16"):
         return "k_me2_pair<%s, %s>" % (proc, "f16x2" if prec == "fp16" else "bf16x2")
+    sched = ctx.kernel_config(proc, prec)[2]
     if prec == "fp64":
-        return "k_me2_valu<%s, double>" % proc
-    return "k_me2_mfma<%s>" % proc if ctx.colour_unit(proc, prec) == "mfma" else "k_me2_valu<%s, float>" % proc
+        return "k_me2_valu<%s, double, %d>" % (proc, sched)
+    return "k_me2_mfma<%s>" % proc if ctx.colour_unit(proc, prec) == "mfma" else "k_me2_valu<%s, float, %d>" % (
+        proc, sched)
 
 
 def flops_per_event(proc):
@@ -575,7 +577,7 @@ def main():
         ms_o = timed(ctx, proc, mom, out, "mixed", max(3, args.steps // 4), 1)
         ctx.set_kernel_config(proc, "mixed", 256, 0)
         other = {"colour_unit": other_unit, "kernel": "k_me2_mfma<%s>" % proc if other_unit == "mfma" else
-                 "k_me2_valu<%s, float>" % proc, "ms_per_step": ms_o, "events_per_s": n / (ms_o * 1e-3)}
+                 "k_me2_valu<%s, float, 0>" % proc, "ms_per_step": ms_o, "events_per_s": n / (ms_o * 1e-3)}
         print("other colour unit: %.3f ms per step" % ms_o, file=sys.stderr, flush=True)
 
     # algorithmic flops per event: exact count of the generated source of the

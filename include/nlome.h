@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define NLO_ABI_VERSION 1u
+#define NLO_ABI_VERSION 2u
 
 typedef struct nlo_ctx nlo_ctx;   /* opaque, library-owned */
 
@@ -96,12 +96,18 @@ typedef struct {
   double avg_factor;     /* initial spin x colour average, applied by nlo_me2 */
   double ident_factor;   /* identical final-state factor, NOT applied */
   int gs_pow, e_pow;     /* |M|^2 is proportional to g_s^(2 gs_pow) e^(2 e_pow) */
+  int nschedules;        /* helicity schedules of the FP64/FP32 kernels (1 or 2) */
 } nlo_proc_info;
 
 /* Kernel launch configuration of one (process, precision) pair. */
 typedef struct {
   int block;        /* threads per block: 64, 128, 192 or 256 */
   int colour_mode;  /* 0 = automatic, 1 = vector ALU, 2 = matrix cores (FP32 family only) */
+  int schedule;     /* helicity schedule of the vector-ALU FP64/FP32 kernels: 0 = the
+                       generator's choice for the precision, 1 = the alternative lazy
+                       depth (one sub-current level more or less evaluated inside the
+                       deepest loop: fewer live registers or fewer flops), where the
+                       process has one (nlo_process_info: nschedules = 2) */
 } nlo_kernel_config;
 
 /* Launch configuration of one FKS sector's subtracted evaluation in one
@@ -157,9 +163,10 @@ nlo_status nlo_colour_unit(const nlo_ctx* ctx, int proc_id, nlo_prec prec, int* 
 nlo_status nlo_reserve(nlo_ctx* ctx, int64_t n);
 
 /* Autotuner: times every launch configuration of (proc_id, prec) -- block of
- * 64/128/192/256 threads (FP16/BF16 blocks cover two events per thread)
- * and, for FP32/MIXED, the colour contraction on the
- * vector ALU or the matrix cores -- on the caller's sample batch (device
+ * 64/128/192/256 threads (FP16/BF16 blocks cover two events per thread),
+ * for FP64/FP32/MIXED both helicity schedules where the process has two, and
+ * for FP32/MIXED the colour contraction on the vector ALU or the matrix cores
+ * (the matrix-core kernel with schedule 0) -- on the caller's sample batch (device
  * momenta, n events, scratch output me2 of n doubles) with HIP events on the
  * given stream, keeps the fastest for this context and returns it in *best
  * (may be NULL) and its time per event in *ns_per_event (may be NULL).

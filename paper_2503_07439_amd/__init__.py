@@ -127,7 +127,7 @@ class Context:
 
     def autotune(self, proc, mom, prec="mixed"):
         """Time every launch configuration on this sample and keep the fastest.
-        Returns ((block, colour_mode), ns per event)."""
+        Returns ((block, colour_mode, schedule), ns per event)."""
         import torch
         n = mom.shape[2]
         out = torch.empty(n, dtype=torch.float64, device=mom.device)
@@ -156,7 +156,7 @@ class Context:
         return nlo_get_fks_config(self.ctx, proc_id(real), fks_i, fks_j, PREC[prec])
 
     def kernel_config(self, proc, prec):
-        """(block, colour_mode) of one process and precision."""
+        """(block, colour_mode, schedule) of one process and precision."""
         return nlo_get_kernel_config(self.ctx, proc_id(proc), PREC[prec])
 
     def fks_buffer(self, real, fks_i, fks_j, prec, threshold, w_out):
@@ -238,8 +238,8 @@ class Context:
         True: events failing the R cut skip the real |M|^2."""
         nlo_set_fks_mask_mode(self.ctx, 1 if compact else 0)
 
-    def set_kernel_config(self, proc, prec, block, colour_mode=0):
-        nlo_set_kernel_config(self.ctx, proc_id(proc), PREC[prec], block, colour_mode)
+    def set_kernel_config(self, proc, prec, block, colour_mode=0, schedule=0):
+        nlo_set_kernel_config(self.ctx, proc_id(proc), PREC[prec], block, colour_mode, schedule)
 
     SEED = 7439
 

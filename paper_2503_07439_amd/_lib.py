@@ -22,7 +22,7 @@ class nlo_proc_info(ctypes.Structure):
                 ("ncolour", ctypes.c_int), ("nhel", ctypes.c_int), ("ngood_hel", ctypes.c_int),
                 ("ndiagrams", ctypes.c_int), ("nterms", ctypes.c_int), ("ncurrents", ctypes.c_int),
                 ("avg_factor", ctypes.c_double), ("ident_factor", ctypes.c_double),
-                ("gs_pow", ctypes.c_int), ("e_pow", ctypes.c_int)]
+                ("gs_pow", ctypes.c_int), ("e_pow", ctypes.c_int), ("nschedules", ctypes.c_int)]
 
 
 class nlo_cuts(ctypes.Structure):
@@ -44,7 +44,7 @@ class nlo_fks_config(ctypes.Structure):
 
 
 class nlo_kernel_config(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int), ("colour_mode", ctypes.c_int)]
+    _fields_ = [("block", ctypes.c_int), ("colour_mode", ctypes.c_int), ("schedule", ctypes.c_int)]
 
 
 class nlo_fks_out(ctypes.Structure):
@@ -187,15 +187,15 @@ def nlo_process_info(ctx, proc_id):
     return info
 
 
-def nlo_set_kernel_config(ctx, proc_id, prec, block, colour_mode=0):
-    cfg = nlo_kernel_config(block, colour_mode)
+def nlo_set_kernel_config(ctx, proc_id, prec, block, colour_mode=0, schedule=0):
+    cfg = nlo_kernel_config(block, colour_mode, schedule)
     return check(lib().nlo_set_kernel_config(ctx, proc_id, prec, ctypes.byref(cfg)))
 
 
 def nlo_get_kernel_config(ctx, proc_id, prec):
     cfg = nlo_kernel_config()
     check(lib().nlo_get_kernel_config(ctx, proc_id, prec, ctypes.byref(cfg)))
-    return cfg.block, cfg.colour_mode
+    return cfg.block, cfg.colour_mode, cfg.schedule
 
 
 def nlo_me2(ctx, proc_id, n, ld, mom_ptr, me2_ptr, prec, stream_ptr):
@@ -261,7 +261,7 @@ def nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr):
     ns = ctypes.c_double()
     check(lib().nlo_autotune(ctx, proc_id, prec, n, ld, mom_ptr, me2_ptr, stream_ptr, ctypes.byref(best),
                              ctypes.byref(ns)))
-    return (best.block, best.colour_mode), ns.value
+    return (best.block, best.colour_mode, best.schedule), ns.value
 
 
 def nlo_set_fks_config(ctx, real_proc, fks_i, fks_j, prec, real_block, colour_mode, ct_block):

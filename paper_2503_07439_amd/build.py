@@ -26,7 +26,8 @@ HIPCC_FLAGS = [
 # every other unit together.
 UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-O1",)}
 
-# |M|^2 units in FP64, FP32 and with MFMA colour (tu_<process>_<0|1|2>.hip):
+# |M|^2 units in FP64, FP32 and with MFMA colour (tu_<process>_<0|1|2>.hip,
+# and 5, 6 for the alternative helicity schedule in FP64 and FP32):
 # external polarisation vectors have a zero time component and a real z
 # component, and massless spinors have a zero chiral half.  Under strict IEEE
 # rules the compiler must keep every product with those zeros (x * 0 is NaN
@@ -40,7 +41,9 @@ ME2_FAST_FLAGS = {"0": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed
                   "1": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"),
                   "2": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"),
                   "3": ("-fno-honor-nans", "-fno-signed-zeros"),
-                  "4": ("-fno-honor-nans", "-fno-signed-zeros")}
+                  "4": ("-fno-honor-nans", "-fno-signed-zeros"),
+                  "5": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"),
+                  "6": ("-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros")}
 
 
 def unit_flags(base):
@@ -124,7 +127,7 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     os.makedirs(OBJ, exist_ok=True)
     srcs = [os.path.join(CSRC, "capi.hip"), os.path.join(CSRC, "phase_space.hip"), os.path.join(CSRC, "checks.hip")] + list(tus)
     # the largest process first so the long poles start early
-    srcs.sort(key=lambda p: 0 if p.endswith("tu_gg_ttgg_4.hip") else
+    srcs.sort(key=lambda p: 0 if p.endswith(("tu_gg_ttgg_4.hip", "tu_gg_ttgg_5.hip", "tu_gg_ttgg_6.hip")) else
               (1 if ("gg_ttgg" in p and "fks" not in p) else (2 if "gg_ttg" in p else 3)))
     jobs = jobs or min(16, os.cpu_count() or 8)
     bid = build_id()

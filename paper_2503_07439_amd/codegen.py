@@ -829,6 +829,9 @@ JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
 JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 0}
 # stop the compiler from hoisting those lazily emitted sub-currents back out
 KEEP_LAZY_IN_LOOP = True
+# processes that also get the other lazy depth as a run-time schedule
+# variant (kernel configuration `schedule` = 1), for the autotuner
+SCHEDULE_ALTS = ("gg_ttg", "gg_ttgg")
 
 
 def _node_call(n, mslot, dslot, den="s.den"):
@@ -1204,6 +1207,22 @@ def emit_process(p):
     L.append("  }")
     j_def = JIT_EXTRA_LEVELS.get(p.name, 0)
     j_f64 = JIT_EXTRA_LEVELS_FP64.get(p.name, j_def)
+    if p.name in SCHEDULE_ALTS:
+        # both lazy depths under their own names; schedule 0 takes each
+        # precision's default depth, schedule 1 the other one
+        L.extend(emit_nested(p, mslot, dslot, N, nin, 0, "helicity_sum_lazy0"))
+        L.extend(emit_nested(p, mslot, dslot, N, nin, 1, "helicity_sum_lazy1"))
+        L.append("  static constexpr int NSCHED = 2;")
+        L.append("  template <int SCHED, class T, class F> NLO_HD static void helicity_sum_sched(const Pre<T>& s, T mt, "
+                 "F&& body) {")
+        L.append("    constexpr int def = std::is_same<T, double>::value ? %d : %d;" % (j_f64, j_def))
+        L.append("    if constexpr ((SCHED == 0 ? def : 1 - def) == 0) helicity_sum_lazy0(s, mt, body);")
+        L.append("    else helicity_sum_lazy1(s, mt, body);")
+        L.append("  }")
+    else:
+        L.append("  static constexpr int NSCHED = 1;")
+        L.append("  template <int SCHED, class T, class F> NLO_HD static void helicity_sum_sched(const Pre<T>& s, T mt, "
+                 "F&& body) { helicity_sum(s, mt, body); }")
     if j_f64 == j_def:
         L.extend(emit_nested(p, mslot, dslot, N, nin))
     else:
@@ -1242,7 +1261,8 @@ def emit_process(p):
     return "\n".join(L)
 
 
-VARIANTS = ("VAR_F64", "VAR_F32", "VAR_MFMA", "VAR_F16", "VAR_BF16")
+VARIANTS = ("VAR_F64", "VAR_F32", "VAR_MFMA", "VAR_F16", "VAR_BF16", "VAR_F64_ALT", "VAR_F32_ALT")
+ALT_VARIANTS = (5, 6)   # compiled only for SCHEDULE_ALTS; elsewhere the table repeats variants 0 and 1
 
 
 def _write_if_changed(path, src):
@@ -1317,13 +1337,15 @@ def generate(out_dir):
     for p in procs:
         p.enumerate()
         p.colour()
-        incs = ['#include "../helas.hpp"'] + (['#include "../opaque.hpp"'] if JIT_EXTRA_LEVELS.get(p.name, 0) else [])
-        if JIT_EXTRA_LEVELS_FP64.get(p.name, JIT_EXTRA_LEVELS.get(p.name, 0)) != JIT_EXTRA_LEVELS.get(p.name, 0):
-            incs.append("#include <type_traits>")
+        incs = ["#include <type_traits>", '#include "../helas.hpp"']
+        if JIT_EXTRA_LEVELS.get(p.name, 0) or p.name in SCHEDULE_ALTS:
+            incs.append('#include "../opaque.hpp"')
         hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once"] + incs +
                          ["namespace nlo {", emit_process(p), "}  // namespace nlo", ""])
         _write_if_changed(os.path.join(out_dir, p.name + ".hpp"), hdr)
         for v, var in enumerate(VARIANTS):
+            if v in ALT_VARIANTS and p.name not in SCHEDULE_ALTS:
+                continue
             tu = "\n".join(["// GENERATED by codegen.py -- do not edit.", '#include "../kernels.hpp"',
                              '#include "%s.hpp"' % p.name, "namespace nlo {",
                              "hipError_t me2_%s_%d(const LaunchArgs& a) { return launch_me2<%s, %s>(a); }"
@@ -1344,7 +1366,8 @@ def generate(out_dir):
     index.append("};")
     index.append("static const me2_launcher ME2_LAUNCH[NPROC][NVAR] = {")
     for p in procs:
-        index.append("  {%s}," % ", ".join("me2_%s_%d" % (p.name, v) for v in range(len(VARIANTS))))
+        index.append("  {%s}," % ", ".join("me2_%s_%d" % (p.name, v if (v not in ALT_VARIANTS or p.name in SCHEDULE_ALTS)
+                                                             else v - 5) for v in range(len(VARIANTS))))
     index.append("};")
     # FKS sectors
     byname = {p.name: p for p in procs}

@@ -95,6 +95,7 @@ nlo_proc_info info_of(int pid) {
   r.ident_factor = P.ident;
   r.gs_pow = P.gs_pow;
   r.e_pow = P.e_pow;
+  r.nschedules = ME2_LAUNCH[pid][VAR_F64_ALT] != ME2_LAUNCH[pid][VAR_F64] ? 2 : 1;
   return r;
 }
 
@@ -116,14 +117,14 @@ nlo_status launch_me2(nlo_ctx* ctx, int pid, int64_t n, int64_t ld, const double
   const nlo_kernel_config& kc = ctx->cfg[pid][prec];
   int var;
   if (prec == NLO_FP64) {
-    var = VAR_F64;
+    var = kc.schedule ? VAR_F64_ALT : VAR_F64;
   } else if (prec == NLO_FP16) {
     var = VAR_F16;
   } else if (prec == NLO_BF16) {
     var = VAR_BF16;
   } else {
     const int mode = kc.colour_mode ? kc.colour_mode : auto_colour_mode(pid, prec);
-    var = (mode == 2) ? VAR_MFMA : VAR_F32;
+    var = (mode == 2) ? VAR_MFMA : (kc.schedule ? VAR_F32_ALT : VAR_F32);
   }
   LaunchArgs a{n, ld, mom, out, coupling_scale(pid, ctx->params), ctx->params.m_top, kc.block, st};
   if (half_prec(prec)) {
@@ -221,7 +222,7 @@ nlo_status nlo_create(nlo_ctx** out, const nlo_params* params) {
   if (!c) return fail(NLO_ENOMEM, "nlo_create: out of host memory");
   c->params = *params;
   for (auto& row : c->cfg)
-    for (auto& k : row) k = nlo_kernel_config{256, 0};
+    for (auto& k : row) k = nlo_kernel_config{256, 0, 0};
   for (auto& row : c->fks_cfg)
     for (auto& k : row) k = nlo_fks_config{256, 0, 256};
   *out = c;
@@ -615,9 +616,11 @@ bool apply_entry(nlo_ctx* ctx, const TuneEntry& e) {
   long cm = 0;
   if (!num("colour_mode", cm) || cm < 0 || cm > 2 || (cm == 2 && pr != NLO_FP32 && pr != NLO_MIXED)) return false;
   if (*kind == "me2") {
-    long b = 0;
+    long b = 0, sc = 0;
     if (!num("block", b) || !valid_block(b)) return false;
-    ctx->cfg[pid][pr] = nlo_kernel_config{(int)b, (int)cm};
+    if (e.get("schedule") && (!num("schedule", sc) || sc < 0 || sc > 1)) return false;
+    if (sc == 1 && (ME2_LAUNCH[pid][VAR_F64_ALT] == ME2_LAUNCH[pid][VAR_F64] || cm == 2)) return false;
+    ctx->cfg[pid][pr] = nlo_kernel_config{(int)b, (int)cm, (int)sc};
     return true;
   }
   if (*kind == "subtracted") {
@@ -740,6 +743,12 @@ nlo_status nlo_set_kernel_config(nlo_ctx* ctx, int proc_id, nlo_prec prec, const
   if (cfg->colour_mode < 0 || cfg->colour_mode > 2) return fail(NLO_EINVAL, "nlo_set_kernel_config: bad colour_mode");
   if (cfg->colour_mode == 2 && prec != NLO_FP32 && prec != NLO_MIXED)
     return fail(NLO_EUNSUPPORTED, "nlo_set_kernel_config: matrix-core colour contraction is FP32 only");
+  if (cfg->schedule < 0 || cfg->schedule > 1) return fail(NLO_EINVAL, "nlo_set_kernel_config: bad schedule");
+  if (cfg->schedule == 1 && ME2_LAUNCH[proc_id][VAR_F64_ALT] == ME2_LAUNCH[proc_id][VAR_F64])
+    return fail(NLO_EUNSUPPORTED, "nlo_set_kernel_config: %s has one helicity schedule", PROC_STATIC[proc_id].name);
+  if (cfg->schedule == 1 && (cfg->colour_mode == 2 || (prec != NLO_FP64 && prec != NLO_FP32 && prec != NLO_MIXED)))
+    return fail(NLO_EUNSUPPORTED, "nlo_set_kernel_config: the alternative schedule is for the vector-ALU FP64/FP32 "
+                "kernels");
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->cfg[proc_id][prec] = *cfg;
   return NLO_OK;
@@ -873,12 +882,16 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
   nlo_kernel_config win = saved;
   float win_ms = -1.0f;
   nlo_status result = NLO_OK;
-  const int modes_fp32[2] = {1, 2};
   const bool fp32 = prec == NLO_FP32 || prec == NLO_MIXED;
-  const int nmodes = fp32 ? 2 : 1;
+  const bool alt = ME2_LAUNCH[proc_id][VAR_F64_ALT] != ME2_LAUNCH[proc_id][VAR_F64] && !half_prec(prec);
+  // (colour unit, schedule) pairs: vector ALU with each schedule, the matrix cores with schedule 0
+  int cand[3][2], ncand = 0;
+  cand[ncand][0] = 1, cand[ncand][1] = 0, ++ncand;
+  if (alt) cand[ncand][0] = 1, cand[ncand][1] = 1, ++ncand;
+  if (fp32) cand[ncand][0] = 2, cand[ncand][1] = 0, ++ncand;
   for (int block = 64; block <= NLO_MAX_BLOCK && result == NLO_OK; block += 64) {
-    for (int m = 0; m < nmodes && result == NLO_OK; ++m) {
-      ctx->cfg[proc_id][prec] = nlo_kernel_config{block, fp32 ? modes_fp32[m] : 1};
+    for (int m = 0; m < ncand && result == NLO_OK; ++m) {
+      ctx->cfg[proc_id][prec] = nlo_kernel_config{block, cand[m][0], cand[m][1]};
       // one warm-up, then three timed launches
       for (int rep = 0; rep < 4 && result == NLO_OK; ++rep) {
         if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) result = fail(NLO_EDEVICE, "nlo_autotune: record");
@@ -910,6 +923,7 @@ nlo_status nlo_autotune(nlo_ctx* ctx, int proc_id, nlo_prec prec, int64_t n, int
   e.put("prec", PREC_NAME[prec], true);
   e.put("block", std::to_string(win.block), false);
   e.put("colour_mode", std::to_string(win.colour_mode), false);
+  e.put("schedule", std::to_string(win.schedule), false);
   e.put("ns_per_event", fmt_double(ns), false);
   return merge_tuning(ctx, e, "nlo_autotune");
 }

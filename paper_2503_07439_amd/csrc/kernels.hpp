@@ -57,7 +57,7 @@ __device__ __forceinline__ PairOv pair_ov(const PairOv& ovp, const double* __res
   return ov;
 }
 
-template <class P, class T>
+template <class P, class T, int SCHED = 0>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
                                                   const unsigned* cnt, int which, const unsigned* list,
@@ -78,7 +78,9 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t l
   typename P::template Pre<T> s;
   P::prologue(p, s, mt, pair_ov(ovp, ovv, ld, e));
   double acc = 0.0;
-  P::helicity_sum(s, T(mt), [&](const cx<T> (&J)[P::NFLOW]) { acc += (double)P::colour_sum(J); });
+  P::template helicity_sum_sched<SCHED>(s, T(mt), [&](const cx<T> (&J)[P::NFLOW]) {
+    acc += (double)P::colour_sum(J);
+  });
   out[e] = acc * (P::HEL_SYM * scale);   // the sum covers one of each pair (h, -h)
 }
 
@@ -320,12 +322,14 @@ static __global__ void k_fb_zero(unsigned* c) {
 template <class P, int VARIANT>
 hipError_t launch_me2(const LaunchArgs& a) {
   const int64_t grid = (a.n + a.block - 1) / a.block;
-  if constexpr (VARIANT == VAR_F64) {
-    hipLaunchKernelGGL((k_me2_valu<P, double>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr, a.ovp, a.ovv);
-  } else if constexpr (VARIANT == VAR_F32) {
-    hipLaunchKernelGGL((k_me2_valu<P, float>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld, a.mom,
-                       a.out, a.scale, a.mt, a.cnt, a.which, a.list, a.ovp, a.ovv);
+  if constexpr (VARIANT == VAR_F64 || VARIANT == VAR_F64_ALT) {
+    constexpr int SCHED = VARIANT == VAR_F64_ALT ? 1 : 0;
+    hipLaunchKernelGGL((k_me2_valu<P, double, SCHED>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld,
+                       a.mom, a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr, a.ovp, a.ovv);
+  } else if constexpr (VARIANT == VAR_F32 || VARIANT == VAR_F32_ALT) {
+    constexpr int SCHED = VARIANT == VAR_F32_ALT ? 1 : 0;
+    hipLaunchKernelGGL((k_me2_valu<P, float, SCHED>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld,
+                       a.mom, a.out, a.scale, a.mt, a.cnt, a.which, a.list, a.ovp, a.ovv);
   } else if constexpr (VARIANT == VAR_F16 || VARIANT == VAR_BF16) {
     // half-width pass over all events, then FP32 over the listed ones
     using V2 = typename std::conditional<VARIANT == VAR_F16, f16x2, bf16x2>::type;

@@ -11,8 +11,10 @@ namespace nlo {
 
 // kernel variants of one process: FP64 vector ALU, FP32 vector ALU, FP32 with
 // the colour contraction on the matrix cores, FP16 and BF16 amplitudes on
-// packed pairs of events
-enum { VAR_F64 = 0, VAR_F32 = 1, VAR_MFMA = 2, VAR_F16 = 3, VAR_BF16 = 4, NVAR = 5 };
+// packed pairs of events, and FP64 / FP32 with the alternative helicity
+// schedule (the other lazy depth; processes without one repeat 0 and 1)
+enum { VAR_F64 = 0, VAR_F32 = 1, VAR_MFMA = 2, VAR_F16 = 3, VAR_BF16 = 4, VAR_F64_ALT = 5, VAR_F32_ALT = 6,
+       NVAR = 7 };
 
 struct LaunchArgs {
   int64_t n, ld;

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_process_table():
     import paper_2503_07439_amd as nl
-    assert nl.nlo_abi_version() == 1
+    assert nl.nlo_abi_version() == 2
     assert nl.nlo_num_processes() == len(nl.PROCESSES)
 
 

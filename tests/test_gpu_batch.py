@@ -135,9 +135,11 @@ def test_autotune_keeps_results(orc):
         mom, _ = events("gg_ttg", 1 << 14, (400.0, 2000.0), stream=410)
         m = torch.from_numpy(mom).cuda()
         for prec in ("fp64", "mixed"):
-            (block, mode), ns = ctx.autotune("gg_ttg", m, prec)
-            assert block in (64, 128, 192, 256) and mode in (1, 2) and ns > 0
-            assert nl.nlo_get_kernel_config(ctx.ctx, nl.proc_id("gg_ttg"), nl.PREC[prec]) == (block, mode)
+            (block, mode, sched), ns = ctx.autotune("gg_ttg", m, prec)
+            print("gg_ttg %s tuned: block %d, colour unit %d, schedule %d, %.3f ns/event" % (prec, block, mode, sched, ns),
+                  flush=True)
+            assert block in (64, 128, 192, 256) and mode in (1, 2) and sched in (0, 1) and ns > 0
+            assert nl.nlo_get_kernel_config(ctx.ctx, nl.proc_id("gg_ttg"), nl.PREC[prec]) == (block, mode, sched)
             out = ctx.me2("gg_ttg", m, prec)
             torch.cuda.synchronize()
             r = np.abs(out.cpu().numpy()[:256] / orc.me2("gg_ttg", mom[:, :, :256]) - 1)
@@ -237,7 +239,8 @@ def test_tuning_cache_roundtrip(tmp_path):
         e_fks = [e for e in doc["entries"] if e["kind"] == "subtracted"][0]
         for e in (e_me2, e_fks):
             assert e["arch"].startswith("gfx950") and e["cus"] > 0 and e["runtime"] > 0 and len(e["build"]) == 16
-        assert (e_me2["proc"], e_me2["prec"], e_me2["block"], e_me2["colour_mode"]) == ("gg_tt", "mixed", *cfg_me2)
+        assert (e_me2["proc"], e_me2["prec"], e_me2["block"], e_me2["colour_mode"], e_me2["schedule"]) == (
+            "gg_tt", "mixed", *cfg_me2)
         assert (e_fks["proc"], e_fks["i"], e_fks["j"], e_fks["prec"]) == ("ee_uug", 4, 2, "fp64")
         assert (e_fks["real_block"], e_fks["colour_mode"], e_fks["ct_block"]) == cfg_fks
         # tuning again replaces the entry of the same key
@@ -250,7 +253,7 @@ def test_tuning_cache_roundtrip(tmp_path):
         assert b.tuning_cache(path) == 2
         assert b.kernel_config("gg_tt", "mixed") == tuple(cfg_me2)
         assert b.fks_config("ee_uug", 4, 2, "fp64") == tuple(cfg_fks)
-        assert b.kernel_config("gg_ttg", "mixed") == (256, 0)
+        assert b.kernel_config("gg_ttg", "mixed") == (256, 0, 0)
         # a malformed file: error, nothing applied
         bad = str(tmp_path / "bad.json")
         open(bad, "w").write('{"format": "nlome-tuning-1", "entries": [{"kind": "me2", "block": }]}')

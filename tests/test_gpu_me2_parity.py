@@ -87,6 +87,34 @@ def test_fp32_parity(gpu, orc, proc, prec, mode):
     assert np.all(r <= 1e-5)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("proc", ["gg_ttg", "gg_ttgg"])
+def test_alternative_schedule_parity(gpu, orc, proc, prec):
+    """The alternative helicity schedule (the other lazy depth) against the
+    oracle, to the bars of the default one."""
+    import paper_2503_07439_amd as nl
+    assert gpu.info(proc).nschedules == 2
+    n = 1000 if proc != "gg_ttgg" else 333
+    mom, _ = events(proc, n, _rs(proc), stream=105)
+    ref = orc.me2(proc, mom)
+    gpu.set_kernel_config(proc, prec, 256, 1, 1)
+    try:
+        import torch
+        m = torch.from_numpy(np.ascontiguousarray(mom)).cuda()
+        got = gpu.me2(proc, m, prec).cpu().numpy()
+    finally:
+        gpu.set_kernel_config(proc, prec, 256, 0, 0)
+    r = np.abs(got / ref - 1)
+    print(proc, prec, "schedule 1: median %.2e max %.2e" % (np.median(r), r.max()), flush=True)
+    if prec == "fp64":
+        assert np.median(r) <= 1e-14 and np.all(r <= 1e-13 + 2e-15 * _cond(mom))
+    else:
+        assert np.median(r) <= 1e-6 and np.all(r <= 1e-5)
+    with pytest.raises(nl.NloError) as e:
+        gpu.set_kernel_config("gg_tt", prec, 256, 1, 1)        # one schedule only
+    assert e.value.status == 5
+
+
 @pytest.mark.parametrize("block", [64, 128, 192])
 def test_launch_shapes_bitwise_fp64(gpu, block):
     """FP64 results do not depend on the launch shape (bitwise)."""

@@ -172,16 +172,18 @@ FKS_SETS = [("ee_uug", 4, 2, "ee_uu", 1000.0, 1 << 16), ("gg_ttg", 4, -1, "gg_tt
 
 
 def fks_leg(ctx, steps):
-    """The subtracted weight on the FKS stress sets: MIXED against FP64 time,
-    the fraction MIXED routes to FP64, the fraction whose W its precision does
-    not resolve to 1e-3 (status bit 3), and MIXED's error against FP64 on every
-    event.  Returns the rows and the inputs/outputs for the oracle sample."""
+    """The subtracted weight on the FKS stress sets (radiation variables
+    log-uniform towards the limits) and on the same Born points with flat
+    radiation variables: MIXED against FP64 time, the fraction MIXED routes to
+    FP64, the fraction whose W its precision does not resolve to 1e-3 (status
+    bit 3), and MIXED's error against FP64 on every event.  Returns the rows
+    and the stress sets' inputs/outputs for the oracle sample."""
     import torch
     from nlo_inputs.workloads import events, fks_variables
     rows, keep = [], []
-    for real, i, j, born, rs, n in FKS_SETS:
+    for (real, i, j, born, rs, n), spread in [(s, "log") for s in FKS_SETS] + [(s, "flat") for s in FKS_SETS]:
         mom_np, _ = events(born, n, rs, stream=42)
-        xt_np, y_np, phi_np = fks_variables(n, stream=42, initial_state=j < 0)
+        xt_np, y_np, phi_np = fks_variables(n, stream=42, initial_state=j < 0, spread=spread)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         M, X, Y, P = t(mom_np), t(xt_np), t(y_np), t(phi_np)
         ctx.reserve(n)
@@ -194,6 +196,7 @@ def fks_leg(ctx, steps):
         st = out["mixed"]["status"]
         rel = np.abs(out["mixed"]["W"] / out["fp64"]["W"] - 1)
         rows.append({"sector": "%s (%d,%s)" % (real, i, j if j >= 0 else "beams"), "events": n,
+                     "radiation_variables": {"log": "log-uniform stress set", "flat": "flat"}[spread],
                      "ms_mixed": ms["mixed"], "ms_fp64": ms["fp64"], "ms_fp32": ms["fp32"],
                      "mixed_speedup_vs_fp64": ms["fp64"] / ms["mixed"],
                      "routed_to_fp64": float(((st & 2) != 0).mean()),
@@ -201,7 +204,8 @@ def fks_leg(ctx, steps):
                      "unresolved_fp64": float(((out["fp64"]["status"] & 8) != 0).mean()),
                      "mixed_rel_err_vs_gpu_fp64": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
                                                    "p99_9": float(np.quantile(rel, 0.999)), "max": float(rel.max())}})
-        keep.append((real, i, j, mom_np, xt_np, y_np, phi_np, out))
+        if spread == "log":
+            keep.append((real, i, j, mom_np, xt_np, y_np, phi_np, out))
         del M, X, Y, P
     return rows, keep
 

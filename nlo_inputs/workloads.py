@@ -67,15 +67,24 @@ def events(proc, n, sqrt_s, seed=SEED, stream=0, first=0, m_top=M_TOP):
     return mom, w
 
 
-def fks_variables(n, seed=SEED, stream=0, first=0, initial_state=False):
+def fks_variables(n, seed=SEED, stream=0, first=0, initial_state=False, spread="log"):
     """FKS radiation variables (xi_tilde, y, phi) with xi_tilde and 1-|y|
-    log-uniform in [1e-6, 1] and phi uniform in [0, 2pi).  For an initial-state
-    sector y takes a random sign."""
+    log-uniform in [1e-6, 1] (spread "log", the stress sets that crowd the
+    soft and collinear limits; y >= 0), or xi_tilde and y uniform in (0, 1)
+    and (-1, 1) (spread "flat", plain sampling of the radiation phase space),
+    and phi uniform in [0, 2pi).  For an initial-state sector y takes a random
+    sign."""
     ev = np.arange(first, first + n, dtype=np.uint64)
     u1 = uniforms(seed, stream, ev, 65)
     u2 = uniforms(seed, stream, ev, 66)
-    xi_t = 10.0 ** (-6.0 * u1[:, 0])
-    omy = 10.0 ** (-6.0 * u1[:, 1])
+    if spread == "log":
+        xi_t = 10.0 ** (-6.0 * u1[:, 0])
+        omy = 10.0 ** (-6.0 * u1[:, 1])
+    elif spread == "flat":
+        xi_t = 1.0 - u1[:, 0]
+        omy = (1.0 if initial_state else 2.0) * (1.0 - u1[:, 1])
+    else:
+        raise ValueError("spread must be 'log' or 'flat'")
     y = 1.0 - omy
     if initial_state:
         y = np.where(u2[:, 1] < 0.5, y, -y)

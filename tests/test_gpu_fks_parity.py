@@ -53,19 +53,19 @@ def gpu():
     ctx.close()
 
 
-def _inputs(sector, n, stream):
+def _inputs(sector, n, stream, spread="log"):
     real, i, j, born, rs = sector
     mom, _ = events(born, n, rs, stream=stream)
-    xt, y, phi = fks_variables(n, stream=stream, initial_state=(j < 0))
+    xt, y, phi = fks_variables(n, stream=stream, initial_state=(j < 0), spread=spread)
     return mom, xt, y, phi
 
 
-def _ref(orc, sector, n, stream):
-    """binary128 oracle on the sector's stress inputs (cached per module)"""
-    key = (sector, n, stream)
+def _ref(orc, sector, n, stream, spread="log"):
+    """binary128 oracle on the sector's inputs (cached per module)"""
+    key = (sector, n, stream, spread)
     if key not in _REF:
         real, i, j = sector[:3]
-        mom, xt, y, phi = _inputs(sector, n, stream)
+        mom, xt, y, phi = _inputs(sector, n, stream, spread)
         _REF[key] = orc.fks(real, i, j, mom, xt, y, phi, want_real=True, kind="quad")
     return _REF[key]
 
@@ -151,6 +151,36 @@ def test_fks_mixed_parity(gpu, orc, sector):
     dsum = abs(got["w_sum"][0] - ref["W"].sum())
     print("   sum W relative error %.2e (of sum|W|)" % (dsum / np.abs(ref["W"]).sum()), flush=True)
     assert dsum <= bound.sum()
+    assert not np.any(got["status"] & 1)
+
+
+@pytest.mark.parametrize("sector", [SECTORS[0], SECTORS[2], SECTORS[4], SECTORS[6]], ids=lambda s: "%s_%d_%d" % s[:3])
+def test_fks_mixed_parity_flat(gpu, orc, sector):
+    """MIXED on radiation variables drawn flat over the radiation phase space,
+    where most events sit away from the limits and run in FP32: the same
+    bounds as on the stress sets (1e-3 |W| where FP32 resolves W, 1e-3 D where
+    it does not, the FP64 bound on the events routed to FP64)."""
+    real, i, j = sector[:3]
+    n = _n(sector)
+    mom, xt, y, phi = _inputs(sector, n, 205, "flat")
+    ref = _ref(orc, sector, n, 205, "flat")
+    got = _gpu_run(gpu, sector, mom, xt, y, phi, "mixed", want_sum=True)
+    D = _terms(ref) / _kappa(ref, j)
+    dW = np.abs(got["W"] - ref["W"])
+    rel = dW / np.abs(ref["W"])
+    routed = (got["status"] & 2) != 0
+    unres = (got["status"] & 8) != 0
+    kap = got["xi"] * ((1 - y) if j >= 0 else (1 - y) * (1 + y))
+    near = np.abs(kap / THR - 1) < 1e-12
+    assert np.array_equal(routed[~near], kap[~near] < THR)
+    print(real, i, j, "flat mixed: routed %.3f, FP32 |dW|/|W| max %.2e, |dW|/D max %.2e, unresolved %.3f" % (
+        routed.mean(), rel[~routed & ~unres].max(), (dW / D)[~routed].max(), unres.mean()), flush=True)
+    assert routed.mean() < 0.5                  # most of a flat set runs in FP32
+    fp32_bound = np.where(unres, 1e-3 * D, 1e-3 * np.abs(ref["W"]))
+    bound = np.where(routed, 1e-12 * (np.abs(ref["W"]) + D), fp32_bound)
+    assert np.all(dW <= bound)
+    assert np.all(rel[~unres] <= 1e-3)
+    assert abs(got["w_sum"][0] - ref["W"].sum()) <= bound.sum()
     assert not np.any(got["status"] & 1)
 
 

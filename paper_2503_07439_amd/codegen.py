@@ -829,16 +829,29 @@ JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
 JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 0}
 # stop the compiler from hoisting those lazily emitted sub-currents back out
 KEEP_LAZY_IN_LOOP = True
+# processes whose helicity loops read the internal momenta through the
+# optimisation barrier at every use.  The momenta are the same for every
+# helicity, so loop-invariant code motion would otherwise hoist every
+# momentum-only factor of the vertices (Pslash's components, the momentum
+# differences of the three-gluon vertex) out of all the loops and keep them
+# live across the whole helicity sum.
+OPAQUE_MOMENTA = ("gg_ttgg",)
 # processes that also get the other lazy depth as a run-time schedule
 # variant (kernel configuration `schedule` = 1), for the autotuner
 SCHEDULE_ALTS = ("gg_ttg", "gg_ttgg")
 
 
-def _node_call(n, mslot, dslot, den="s.den"):
-    """C++ expression evaluating sub-current n from its children."""
-    ch = ["v%d" % c.id for c in n.children]
-    Q = "s.Q[%d]" % mslot[n.legs]
-    D = "%s[%d]" % (den, dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")])
+def _qref(slot, opq):
+    return ("oq(s.Q[%d])" if opq else "s.Q[%d]") % slot
+
+
+def _node_call(n, mslot, dslot, den="s.den", opq=False, wrap=None):
+    """C++ expression evaluating sub-current n from its children (opq: read
+    the momenta through the optimisation barrier; wrap(c): also child c)."""
+    ch = [("ow(v%d)" if wrap and wrap(c) else "v%d") % c.id for c in n.children]
+    Q = _qref(mslot[n.legs], opq)
+    dk = dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")]
+    D = "%s(s.den[%d])" % (den[1:], dk) if den.startswith("@") else "%s[%d]" % (den, dk)
     if n.kind == "ffv_vec":
         return "ffv_vec(%s, %s, %s)" % (ch[0], ch[1], D)
     if n.kind in ("ffv_col", "ffv_row"):
@@ -846,8 +859,8 @@ def _node_call(n, mslot, dslot, den="s.den"):
             return "%s(%s, %s, %s, %s, mt)" % (n.kind, ch[0], ch[1], Q, D)
         return "%s0(%s, %s, %s, %s)" % (n.kind, ch[0], ch[1], Q, D)
     if n.kind == "vvv_vec":
-        QA = "s.Q[%d]" % mslot[n.children[0].legs]
-        QB = "s.Q[%d]" % mslot[n.children[1].legs]
+        QA = _qref(mslot[n.children[0].legs], opq)
+        QB = _qref(mslot[n.children[1].legs], opq)
         return "vvv_vec(%s, %s, %s, %s, %s)" % (ch[0], QA, ch[1], QB, D)
     return "%s(%s, %s, %s, %s)" % (n.kind, ch[0], ch[1], ch[2], D)
 
@@ -862,7 +875,7 @@ def _ext_call(p, k, bit, nin):
     return "wf_bar(%s(s.x%d, %s))" % ("wf_u" if out else "wf_v", k, bit)
 
 
-def _amp_call(a, ch, mslot, rootv):
+def _amp_call(a, ch, mslot, rootv, opq=False):
     """C++ expression of amplitude a with the root wavefunction rootv."""
     ch = ch[:-1] + [rootv]
     if a.kind == "ffv_amp":
@@ -872,7 +885,7 @@ def _amp_call(a, ch, mslot, rootv):
     if a.kind == "ffv_amp_rootrow":
         return "ffv_amp(%s, %s, %s)" % (ch[2], ch[1], ch[0])
     if a.kind == "vvv_amp":
-        Qs = ["s.Q[%d]" % mslot[c.legs] for c in a.children]
+        Qs = [_qref(mslot[c.legs], opq) for c in a.children]
         return "vvv_amp(%s, %s, %s, %s, %s, %s)" % (ch[0], Qs[0], ch[1], Qs[1], ch[2], Qs[2])
     return "%s(%s, %s, %s, %s)" % (a.kind, ch[0], ch[1], ch[2], ch[3])
 
@@ -890,6 +903,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
     order = helicity_order(p)
     lev = {k: i for i, k in enumerate(order)}
     root = order[-1]
+    opq = p.name in OPAQUE_MOMENTA
     fixed = _fixed_leg(p, order)                    # held at one helicity (HEL_SYM)
     deep = N - 2                                    # deepest emitted loop
     if jit_extra is None:
@@ -923,7 +937,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
             elif n.kind == "ext":
                 L.append(ind + "const w4<T> v%d = %s;" % (n.id, _ext_call(p, min(n.legs), "b%d" % level, nin)))
             else:
-                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot)))
+                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot, opq=opq)))
     # deepest loop: root wavefunctions, then amplitudes with just-in-time
     # sub-currents.  A massless-fermion root whose chirality partner is fixed
     # has one allowed helicity: evaluate only that one.
@@ -956,10 +970,14 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
         # (they do not depend on its helicity), undoing the trade of flops for
         # registers.  Their propagator factors are read through a copy that the
         # compiler must treat as changing every iteration.
-        lazy_den = "dl"
-        L.append(ind + "T dl[NDEN];")
-        L.append(ind + "#pragma unroll")
-        L.append(ind + "for (int q = 0; q < NDEN; ++q) { dl[q] = s.den[q]; opaque(dl[q]); }")
+        if opq:
+            # each factor read through the barrier where it is used
+            lazy_den = "@oval"
+        else:
+            lazy_den = "dl"
+            L.append(ind + "T dl[NDEN];")
+            L.append(ind + "#pragma unroll")
+            L.append(ind + "for (int q = 0; q < NDEN; ++q) { dl[q] = s.den[q]; opaque(dl[q]); }")
     done = set()
 
     def need(n):
@@ -989,7 +1007,10 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
         pending.remove(a)
         for c in a.children[:-1]:
             for n in need(c):
-                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot, lazy_den)))
+                # a sub-current from above the deepest loop has only operands
+                # that do not change in it: read them through the barrier too
+                wrap = (lambda c: True) if opq and level_of[id(n)] < deep else None
+                L.append(ind + "const w4<T> v%d = %s;" % (n.id, _node_call(n, mslot, dslot, lazy_den, opq, wrap)))
         ch = ["v%d" % c.id for c in a.children]
         kcur = None
         if root_linear and a.kind == "ffv_amp":
@@ -999,7 +1020,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
             L.append(ind + "const w4<T> %s = ffv_cur(%s, %s);" % (kcur, ch[0], ch[1]))
         for rv, J in roots:
             av = "a%d_%s" % (k, rv)
-            expr = "mdot(%s, %s)" % (kcur, rv) if kcur else _amp_call(a, ch, mslot, rv)
+            expr = "mdot(%s, %s)" % (kcur, rv) if kcur else _amp_call(a, ch, mslot, rv, opq)
             L.append(ind + "const cx<T> %s = %s;" % (av, expr))
             for f in range(nflow):
                 c = _phase_coef(a.coef[f], a.phase, a.qfac)
@@ -1338,7 +1359,7 @@ def generate(out_dir):
         p.enumerate()
         p.colour()
         incs = ["#include <type_traits>", '#include "../helas.hpp"']
-        if JIT_EXTRA_LEVELS.get(p.name, 0) or p.name in SCHEDULE_ALTS:
+        if JIT_EXTRA_LEVELS.get(p.name, 0) or p.name in SCHEDULE_ALTS or p.name in OPAQUE_MOMENTA:
             incs.append('#include "../opaque.hpp"')
         hdr = "\n".join(["// GENERATED by codegen.py -- do not edit.", "#pragma once"] + incs +
                          ["namespace nlo {", emit_process(p), "}  // namespace nlo", ""])

@@ -13,4 +13,26 @@ template <class T> NLO_HD void opaque(T& x) {
   (void)x;
 #endif
 }
+// a copy of a value behind the barrier
+template <class T> NLO_HD T oval(T x) {
+  opaque(x);
+  return x;
+}
+// a copy of a momentum behind the barrier (every component)
+template <class T> NLO_HD r4<T> oq(const r4<T>& q) {
+  r4<T> r = q;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) opaque(r.v[m]);
+  return r;
+}
+// a copy of a wavefunction behind the barrier (every component)
+template <class T> NLO_HD w4<T> ow(const w4<T>& w) {
+  w4<T> r = w;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    opaque(r.c[m].r);
+    opaque(r.c[m].i);
+  }
+  return r;
+}
 }  // namespace nlo

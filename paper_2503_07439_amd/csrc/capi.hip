@@ -75,6 +75,11 @@ struct nlo_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int64_t ws_events = 0;
+  // MIXED FKS evaluation runs its FP64 bucket on this stream beside the FP32
+  // bucket on the caller's stream (fork and join through the two events), so
+  // that the tail of one bucket's launch overlaps the other's
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -225,12 +230,30 @@ nlo_status nlo_create(nlo_ctx** out, const nlo_params* params) {
     for (auto& k : row) k = nlo_kernel_config{256, 0, 0};
   for (auto& row : c->fks_cfg)
     for (auto& k : row) k = nlo_fks_config{256, 0, 256};
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || (cur != params->device && hipSetDevice(params->device) != hipSuccess)) {
+    delete c;
+    return fail(NLO_EDEVICE, "nlo_create: cannot make device %d current", params->device);
+  }
+  const bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
+  if (cur != params->device) (void)hipSetDevice(cur);
+  if (!ok) {
+    nlo_destroy(c);
+    return fail(NLO_EDEVICE, "nlo_create: stream or event creation failed");
+  }
   *out = c;
   return NLO_OK;
 }
 
 nlo_status nlo_destroy(nlo_ctx* ctx) {
-  if (ctx && ctx->ws) (void)hipFree(ctx->ws);
+  if (!ctx) return NLO_OK;
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
   return NLO_OK;
 }
@@ -412,16 +435,39 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   }
   la.ovv = a.pinv;
   const bool mfma = (fc.colour_mode ? fc.colour_mode : auto_colour_mode(real_proc, prec)) == 2;
+  // the two buckets write disjoint events: in MIXED mode the FP64 one runs on
+  // the side stream, forked after the map and joined before the sum, so that
+  // each bucket's last, partly filled wave of blocks overlaps the other's.
+  // Only for batches large enough to gain (the fork and join cost about as
+  // much as the small kernels of 2^16 events), and not under stream capture:
+  // there both stay on s (a batch-plan capture with the fork ended the
+  // process inside the plan call, cause not identified)
+  constexpr int64_t FORK_MIN_EVENTS = 1 << 18;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusActive;
+  const bool fork = err == hipSuccess && a.mode == 2 && n >= FORK_MIN_EVENTS && ctx->side &&
+                    hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+  hipStream_t s64 = fork ? ctx->side : s;
+  if (fork) {
+    err = hipEventRecord(ctx->fork_ev, s);
+    if (err == hipSuccess) err = hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0);
+  }
   if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
   if (err == hipSuccess && a.mode != 0) {
     la.which = 1;
+    la.stream = s64;
     err = ME2_LAUNCH[real_proc][VAR_F64](la);
   }
   if (err == hipSuccess && a.mode != 1) err = sec->born_fn[1](a, 0, block, s);
-  if (err == hipSuccess && a.mode != 0) err = sec->born_fn[0](a, 1, block, s);
+  if (err == hipSuccess && a.mode != 0) err = sec->born_fn[0](a, 1, block, s64);
   // compact mode: counterterms of the events that skipped the real |M|^2
   if (err == hipSuccess && a.compact && a.mode != 1) err = sec->born_fn[1](a, 2, block, s);
-  if (err == hipSuccess && a.compact && a.mode != 0) err = sec->born_fn[0](a, 3, block, s);
+  if (err == hipSuccess && a.compact && a.mode != 0) err = sec->born_fn[0](a, 3, block, s64);
+  if (fork) {
+    // join even after an error, so that a capture in progress stays whole
+    hipError_t e2 = hipEventRecord(ctx->join_ev, ctx->side);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(s, ctx->join_ev, 0);
+    if (err == hipSuccess) err = e2;
+  }
   if (err == hipSuccess && out->w_sum) {
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, s, n, (const double*)out->W, out->w_sum);
     err = hipGetLastError();

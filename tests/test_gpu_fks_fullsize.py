@@ -62,3 +62,31 @@ def test_fks_full_size_sampled(gpu, orc, real, i, j, born, rs, n):
         assert np.all(dW[~unres] <= 1e-3 * np.abs(ref["W"][~unres]))
         print(real, i, j, prec, "n", n, "routed %.3f unresolved %.4f" % (((st & 2) != 0).mean(), ((st & 8) != 0).mean()),
               flush=True)
+
+
+def test_mixed_buckets_bitwise(gpu):
+    """At 2^18 events MIXED runs its FP64 bucket beside the FP32 one on a
+    second stream: every event's W equals, bit for bit, its value from the
+    all-FP64 call (routed events) or the all-FP32 call (the others), and the
+    fixed-order sum of W taken after the join equals the sum of those W."""
+    import torch
+    real, i, j, born, rs, n = "gg_ttg", 4, -1, "gg_tt", (400.0, 2000.0), 1 << 18
+    mom, _ = events(born, n, rs, stream=43)
+    xt, y, phi = fks_variables(n, stream=43, initial_state=True, spread="flat")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    M, X, Y, P = t(mom), t(xt), t(y), t(phi)
+    got = {}
+    for prec in ("mixed", "fp64", "fp32"):
+        r = gpu.subtracted(real, i, j, M, X, Y, P, prec=prec, want_sum=True)
+        torch.cuda.synchronize()
+        got[prec] = {k: r[k].cpu().numpy() for k in ("W", "status", "w_sum")}
+    routed = (got["mixed"]["status"] & 2) != 0
+    assert 0.1 < routed.mean() < 0.5
+    expect = np.where(routed, got["fp64"]["W"], got["fp32"]["W"])
+    assert np.array_equal(got["mixed"]["W"], expect)
+    again = gpu.subtracted(real, i, j, M, X, Y, P, prec="mixed", want_sum=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(again["W"].cpu().numpy(), got["mixed"]["W"])
+    assert again["w_sum"].cpu().numpy()[0] == got["mixed"]["w_sum"][0]
+    W = got["mixed"]["W"]
+    assert abs(got["mixed"]["w_sum"][0] - W.sum()) <= 1e-12 * np.abs(W).sum()

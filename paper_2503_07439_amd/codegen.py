@@ -836,20 +836,29 @@ KEEP_LAZY_IN_LOOP = True
 # differences of the three-gluon vertex) out of all the loops and keep them
 # live across the whole helicity sum.
 OPAQUE_MOMENTA = ("gg_ttgg",)
+# of those, processes whose FP64 helicity loops form each internal momentum
+# from the external ones where it is used (same legs, same order of the sum
+# as the prologue, so the same bits), instead of holding all of them in
+# registers: 31 momenta cost 248 registers in FP64
+FP64_MOMENTUM_SUMS = ("gg_ttgg",)
 # processes that also get the other lazy depth as a run-time schedule
 # variant (kernel configuration `schedule` = 1), for the autotuner
 SCHEDULE_ALTS = ("gg_ttg", "gg_ttgg")
 
 
-def _qref(slot, opq):
-    return ("oq(s.Q[%d])" if opq else "s.Q[%d]") % slot
+def _qref(S, mslot, opq):
+    """the momentum of leg set S: the stored slot, through the barrier if opq;
+    opq == 2: FP64 sums the external momenta at each use instead"""
+    if opq == 2 and len(S) > 1:
+        return "qlegs<T, %s>(s.Q, %d)" % (", ".join(str(mslot[frozenset([k])]) for k in sorted(S)), mslot[S])
+    return ("oq(s.Q[%d])" if opq else "s.Q[%d]") % mslot[S]
 
 
 def _node_call(n, mslot, dslot, den="s.den", opq=False, wrap=None):
     """C++ expression evaluating sub-current n from its children (opq: read
     the momenta through the optimisation barrier; wrap(c): also child c)."""
     ch = [("ow(v%d)" if wrap and wrap(c) else "v%d") % c.id for c in n.children]
-    Q = _qref(mslot[n.legs], opq)
+    Q = _qref(n.legs, mslot, opq)
     dk = dslot[(n.legs, n.mass if n.kind in ("ffv_col", "ffv_row") else "0")]
     D = "%s(s.den[%d])" % (den[1:], dk) if den.startswith("@") else "%s[%d]" % (den, dk)
     if n.kind == "ffv_vec":
@@ -859,8 +868,8 @@ def _node_call(n, mslot, dslot, den="s.den", opq=False, wrap=None):
             return "%s(%s, %s, %s, %s, mt)" % (n.kind, ch[0], ch[1], Q, D)
         return "%s0(%s, %s, %s, %s)" % (n.kind, ch[0], ch[1], Q, D)
     if n.kind == "vvv_vec":
-        QA = _qref(mslot[n.children[0].legs], opq)
-        QB = _qref(mslot[n.children[1].legs], opq)
+        QA = _qref(n.children[0].legs, mslot, opq)
+        QB = _qref(n.children[1].legs, mslot, opq)
         return "vvv_vec(%s, %s, %s, %s, %s)" % (ch[0], QA, ch[1], QB, D)
     return "%s(%s, %s, %s, %s)" % (n.kind, ch[0], ch[1], ch[2], D)
 
@@ -885,7 +894,7 @@ def _amp_call(a, ch, mslot, rootv, opq=False):
     if a.kind == "ffv_amp_rootrow":
         return "ffv_amp(%s, %s, %s)" % (ch[2], ch[1], ch[0])
     if a.kind == "vvv_amp":
-        Qs = [_qref(mslot[c.legs], opq) for c in a.children]
+        Qs = [_qref(c.legs, mslot, opq) for c in a.children]
         return "vvv_amp(%s, %s, %s, %s, %s, %s)" % (ch[0], Qs[0], ch[1], Qs[1], ch[2], Qs[2])
     return "%s(%s, %s, %s, %s)" % (a.kind, ch[0], ch[1], ch[2], ch[3])
 
@@ -903,7 +912,7 @@ def emit_nested(p, mslot, dslot, N, nin, jit_extra=None, fname="helicity_sum"):
     order = helicity_order(p)
     lev = {k: i for i, k in enumerate(order)}
     root = order[-1]
-    opq = p.name in OPAQUE_MOMENTA
+    opq = (2 if p.name in FP64_MOMENTUM_SUMS else 1) if p.name in OPAQUE_MOMENTA else 0
     fixed = _fixed_leg(p, order)                    # held at one helicity (HEL_SYM)
     deep = N - 2                                    # deepest emitted loop
     if jit_extra is None:

@@ -167,6 +167,10 @@ def gg_ttgg_leg(ctx, steps):
 
 
 # FKS stress sets: Born points, xi_tilde and 1-|y| log-uniform in [1e-6, 1]
+# IR-safe cuts of the event loop (the paper defines none): jets by anti-kT
+# with R = 0.5, pT >= 40 GeV, |y| <= 2; tops pT >= 50 GeV, |y| <= 2.5
+GEN_CUTS = {"gg_ttg": dict(jet_r=0.5, jet_ptmin=40.0, jet_ymax=2.0, njet_min=1, top_ptmin=50.0, top_ymax=2.5)}
+
 FKS_SETS = [("ee_uug", 4, 2, "ee_uu", 1000.0, 1 << 16), ("gg_ttg", 4, -1, "gg_tt", (400.0, 2000.0), 1 << 20),
             ("gg_ttgg", 4, 5, "gg_ttg", (400.0, 2000.0), 1 << 18)]
 
@@ -556,6 +560,38 @@ def main():
                "same_points_as_host_batch": same}
         print("device generation: %.3f ms, with |M|^2 %.3f ms" % (gms["generate"], gms["generate_and_me2"]),
               file=sys.stderr, flush=True)
+        if proc in GEN_CUTS:
+            # Algorithm 2 on the device: the cut mask of the batch, and n
+            # points that pass the cuts by regenerating candidates (stream
+            # compaction; the call returns the candidate count, so it ends
+            # with a synchronisation: wall time per call)
+            cuts = GEN_CUTS[proc]
+            ms_mask = timed_fn(lambda: ctx.cut_mask(proc, gmom, cuts), max(3, args.steps // 4))
+            pass_frac = float(ctx.cut_mask(proc, gmom, cuts).double().mean())
+            ctx.generate_passing(proc, n, rs, 7, cuts)
+            torch.cuda.synchronize()
+            reps = 3
+            t = time.perf_counter()
+            for _ in range(reps):
+                pm, pw, trials = ctx.generate_passing(proc, n, rs, 7, cuts)
+            ms_pass = (time.perf_counter() - t) * 1e3 / reps
+
+            def loop():
+                pm, pw, _ = ctx.generate_passing(proc, n, rs, 7, cuts)
+                ctx.me2(proc, pm, "mixed", out=out)
+                torch.cuda.synchronize()
+            loop()
+            t = time.perf_counter()
+            for _ in range(reps):
+                loop()
+            ms_loop = (time.perf_counter() - t) * 1e3 / reps
+            gen.update({"cuts": cuts, "ms_cut_mask": ms_mask, "pass_fraction": pass_frac,
+                        "ms_generate_passing": ms_pass, "candidates_per_passing_event": trials / n,
+                        "ms_generate_passing_and_me2": ms_loop,
+                        "passing_events_per_s": n / (ms_loop * 1e-3)})
+            print("cuts: mask %.3f ms (pass %.3f), %d passing points %.3f ms, with |M|^2 %.3f ms" % (
+                ms_mask, pass_frac, n, ms_pass, ms_loop), file=sys.stderr, flush=True)
+            del pm, pw
         del gmom, gw
 
     # FP16 amplitudes (FP32 pass for near-pole events) on the same batch, for the record

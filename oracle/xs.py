@@ -1,4 +1,6 @@
-"""Reference partonic cross sections for the tests (oracle side only).
+"""Reference partonic cross sections -- ORACLE, TEST INFRASTRUCTURE ONLY (the
+same rules as the rest of oracle/: only tests/, the smoke check and the
+benchmark's CPU-baseline leg use it).
 
 sigma(sqrt_s) of a 2 -> 2 process by Gauss-Legendre quadrature of the
 oracle's |M|^2 over the scattering angle, sigma = (1/(2s)) (beta/(16 pi))

@@ -177,7 +177,8 @@ nlo_status use_device(const nlo_ctx* ctx, const char* fn) {
 // address, found once per device by hipGetSymbolAddress at nlo_create; host
 // code uses that address, never the array's name.
 constexpr int64_t SCRATCH_EVENTS = 65536;
-constexpr size_t SCRATCH_BYTES = (size_t)SCRATCH_EVENTS * ((6 * 4 + 3) * sizeof(double) + 2 * sizeof(unsigned)) + 256;
+constexpr size_t SCRATCH_BYTES = (size_t)SCRATCH_EVENTS * ((6 * 4 + 3) * sizeof(double) + 2 * sizeof(unsigned)) + 256 +
+                                 FKS_SUM_PARTS * sizeof(double);
 static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 namespace {
@@ -305,7 +306,8 @@ nlo_status check_subtracted(const nlo_ctx* ctx, int real_proc, int fks_i, int fk
 
 size_t fks_ws_bytes(int real_proc, int64_t n) {
   const int nr = PROC_STATIC[real_proc].npart;
-  return (size_t)n * (nr * 4 + 3) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128;
+  return (size_t)n * (nr * 4 + 3) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128 +
+         FKS_SUM_PARTS * sizeof(double);
 }
 
 // cross-section chunk of m events: momenta, weights, |M|^2, partial sums,
@@ -469,7 +471,10 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
     if (err == hipSuccess) err = e2;
   }
   if (err == hipSuccess && out->w_sum) {
-    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, s, n, (const double*)out->W, out->w_sum);
+    // partial sums after the bucket counters (which take the first 64 bytes)
+    double* part = reinterpret_cast<double*>(a.cnt + 16);
+    hipLaunchKernelGGL(k_sum_part, dim3(FKS_SUM_PARTS), dim3(256), 0, s, n, (const double*)out->W, part);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, (const double*)part, out->w_sum);
     err = hipGetLastError();
   }
   return err;

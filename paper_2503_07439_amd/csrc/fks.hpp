@@ -647,17 +647,39 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
 }
 
 // fixed-order FP64 sum (single block; deterministic for a given n)
-static __global__ __launch_bounds__(1024) void k_sum_fixed(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
-  __shared__ double part[1024];
+// Fixed-order FP64 sum of x[0, n): block b of FKS_SUM_PARTS reduces its
+// contiguous share into part[b] (strided per thread, then a tree), and one
+// block adds the parts the same way.  The order depends on n only, so the sum
+// is reproducible bit for bit.
+constexpr int FKS_SUM_PARTS = 512;
+
+static __global__ __launch_bounds__(256) void k_sum_part(int64_t n, const double* __restrict__ x,
+                                                         double* __restrict__ part) {
+  __shared__ double t[256];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) s += x[i];
-  part[threadIdx.x] = s;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += x[i];
+  t[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) t[threadIdx.x] += t[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = part[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = t[0];
+}
+
+static __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double t[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < FKS_SUM_PARTS; i += blockDim.x) s += part[i];
+  t[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) t[threadIdx.x] += t[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = t[0];
 }
 
 // ---------------------------------------------------------------------------

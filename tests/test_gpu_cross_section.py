@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from test_oracle_xs_pins import MT, closed_form
-from xs_reference import sigma_mc
+from oracle.xs import sigma_mc
 
 pytestmark = pytest.mark.gpu
 

@@ -12,7 +12,7 @@ import math
 
 import pytest
 
-from xs_reference import GEV2_PB, sigma_mc, sigma_quadrature
+from oracle.xs import GEV2_PB, sigma_mc, sigma_quadrature
 
 ALPHA, ALPHA_S, MT = 1.0 / 132.507, 0.118, 173.0
 

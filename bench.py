@@ -204,6 +204,7 @@ def fks_leg(ctx, steps):
                      "ms_mixed": ms["mixed"], "ms_fp64": ms["fp64"], "ms_fp32": ms["fp32"],
                      "mixed_speedup_vs_fp64": ms["fp64"] / ms["mixed"],
                      "routed_to_fp64": float(((st & 2) != 0).mean()),
+                     "reevaluated_in_fp64": float(((st & 16) != 0).mean()),
                      "unresolved_mixed": float(((st & 8) != 0).mean()),
                      "unresolved_fp64": float(((out["fp64"]["status"] & 8) != 0).mean()),
                      "mixed_rel_err_vs_gpu_fp64": {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),

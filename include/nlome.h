@@ -246,7 +246,9 @@ typedef struct {
   uint8_t* status;    /* [n] bit0 non-finite W, bit1 evaluated in FP64, bit2 a mask zeroed a term,
                           bit3 W not resolved to 1e-3 in its working precision (its rounding
                           bound, 1e-12 D in FP64 and 32 eps_32 (1 + 1/sqrt(1-|y|)) D in FP32
-                          with D = sum|g_X| / kappa, exceeds 1e-3 |W|) */
+                          with D = sum|g_X| / kappa, exceeds 1e-3 |W|), bit4 (MIXED) evaluated
+                          in FP32 first and again in FP64 because W came out unresolved or
+                          non-finite (bit1 is then set too) */
   double* real_mom;   /* [npart_real][4][ld] real-emission momenta in event order */
   double* w_sum;      /* [1] fixed-order FP64 sum of W over the batch */
   /* [n] the subtracted cross section per unit Born phase space and per unit
@@ -333,7 +335,10 @@ nlo_status nlo_subtracted_static(nlo_ctx* ctx, int real_proc, int fks_i, int fks
  * FP64 when kappa = xi (1-y) (final-state fks_j) or xi (1-y^2) (beams) is below
  * it, in FP32 otherwise.  Default 0.1: the FP32 rounding of the real |M|^2
  * reaches W amplified by about 1/kappa, and at kappa >= 0.1 FP32 keeps
- * |dW|/|W| below 1e-4 on every event measured.  threshold in [0, 1]. */
+ * |dW|/|W| below 1e-4 on every event measured.  An FP32 event whose W comes
+ * out unresolved or non-finite (status bits 3, 0) is evaluated again in FP64
+ * within the same call (status bit 4), so MIXED flags bit 3 on the events FP64
+ * flags.  threshold in [0, 1]. */
 nlo_status nlo_set_fks_threshold(nlo_ctx* ctx, double threshold);
 
 /* ---- batched mixes: one graph launch for many (process, contribution) items ----

@@ -177,7 +177,7 @@ nlo_status use_device(const nlo_ctx* ctx, const char* fn) {
 // address, found once per device by hipGetSymbolAddress at nlo_create; host
 // code uses that address, never the array's name.
 constexpr int64_t SCRATCH_EVENTS = 65536;
-constexpr size_t SCRATCH_BYTES = (size_t)SCRATCH_EVENTS * ((6 * 4 + 3) * sizeof(double) + 2 * sizeof(unsigned)) + 256 +
+constexpr size_t SCRATCH_BYTES = (size_t)SCRATCH_EVENTS * ((6 * 4 + 3) * sizeof(double) + 3 * sizeof(unsigned)) + 256 +
                                  FKS_SUM_PARTS * sizeof(double);
 static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
@@ -306,7 +306,7 @@ nlo_status check_subtracted(const nlo_ctx* ctx, int real_proc, int fks_i, int fk
 
 size_t fks_ws_bytes(int real_proc, int64_t n) {
   const int nr = PROC_STATIC[real_proc].npart;
-  return (size_t)n * (nr * 4 + 3) * sizeof(double) + 2 * (size_t)n * sizeof(unsigned) + 128 +
+  return (size_t)n * (nr * 4 + 3) * sizeof(double) + 3 * (size_t)n * sizeof(unsigned) + 128 +
          FKS_SUM_PARTS * sizeof(double);
 }
 
@@ -397,7 +397,8 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   a.pinv = a.me2r + n;
   a.inv = reinterpret_cast<unsigned*>(a.pinv + 2 * (size_t)n);
   a.skip_inv = a.inv + n;
-  uintptr_t c = reinterpret_cast<uintptr_t>(a.skip_inv + n);
+  a.redo = a.skip_inv + n;
+  uintptr_t c = reinterpret_cast<uintptr_t>(a.redo + n);
   a.cnt = reinterpret_cast<unsigned*>((c + 63) & ~uintptr_t(63));
   a.compact = ((ctx->fks_compact || force_compact) && mask) ? 1 : 0;
   a.thr = ctx->fks_thr;
@@ -469,6 +470,20 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
     hipError_t e2 = hipEventRecord(ctx->join_ev, ctx->side);
     if (e2 == hipSuccess) e2 = hipStreamWaitEvent(s, ctx->join_ev, 0);
     if (err == hipSuccess) err = e2;
+  }
+  // MIXED: the FP32 events whose W came out unresolved or non-finite (listed
+  // by the FP32 counterterm kernel) again in FP64: real |M|^2 at their bucket
+  // positions, then counterterms and W (and those of the listed events whose
+  // real emission compact mode skipped)
+  if (err == hipSuccess && a.mode == 2) {
+    LaunchArgs lr = la;
+    lr.stream = s;
+    lr.which = 2;
+    lr.list = a.redo;
+    lr.cnt = a.cnt + 4;
+    err = ME2_LAUNCH[real_proc][VAR_F64](lr);
+    if (err == hipSuccess) err = sec->born_fn[0](a, 5, block, s);
+    if (err == hipSuccess && a.compact) err = sec->born_fn[0](a, 7, block, s);
   }
   if (err == hipSuccess && out->w_sum) {
     // partial sums after the bucket counters (which take the first 64 bytes)

@@ -269,10 +269,15 @@ struct FksArgs {
   double* pinv;                        // workspace [2][n], bucket order: the FKS pair invariants
   double* me2r;                        // workspace [n], bucket order
   unsigned* inv;                       // workspace [n]: bucket position -> event
-  unsigned* cnt;                       // workspace [4]: FP32 and FP64 bucket sizes, then the same
-                                       // for the events whose real emission is skipped
+  unsigned* cnt;                       // workspace [8]: FP32 and FP64 bucket sizes, then the same
+                                       // for the events whose real emission is skipped, then the
+                                       // length of redo
   unsigned* skip_inv;                  // workspace [n]: skipped events (compact mode), FP32 from
                                        // the front, FP64 from the back
+  unsigned* redo;                      // workspace [n] (MIXED): positions of FP32 events whose W
+                                       // came out unresolved or non-finite, evaluated again in
+                                       // FP64: bucket positions from the front (cnt[4]), skipped-
+                                       // list positions from the back (cnt[5])
   int compact;                         // 1: events failing the R cut skip the real |M|^2
   double thr;                          // route to FP64 when kappa = xi (1-y) (final-state J) or
                                        // xi (1-y^2) (beams) is below thr
@@ -296,7 +301,7 @@ __device__ __forceinline__ void load_born(const FksArgs& a, int64_t e, double (&
 }
 
 static __global__ void k_fks_zero(unsigned* cnt) {
-  if (threadIdx.x < 4) cnt[threadIdx.x] = 0u;
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
 }
 
 // 1. map and route.  Every event goes to the FP32 or the FP64 bucket; in
@@ -404,10 +409,11 @@ __device__ double born_spin(const typename BP::template Pre<T>& s, const double*
 // Algorithm-2 masks (a failed cut zeroes its contribution after evaluation),
 // the subtracted weight and the per-event outputs
 template <class S>
-__device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e, double B, double gR, double gS,
-                                          double gC, double gCm, double gSC, double gSCm, const FksKin& K) {
+__device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t pos, int64_t e, double B, double gR,
+                                          double gS, double gC, double gCm, double gSC, double gSCm, const FksKin& K) {
   const double xi = K.xi, y = K.y;
-  uint8_t st = (which & 1) ? 2 : 0;
+  // which & 1: evaluated in FP64 (buckets 1, 3 and the redo lists 5, 7)
+  uint8_t st = (which & 1) ? (which >= 5 ? 2 | 16 : 2) : 0;
   double Bo = B;
   if (a.mask) {
     const bool mB = a.mask[0 * a.ld + e], mR = a.mask[1 * a.ld + e], mS = a.mask[2 * a.ld + e];
@@ -442,6 +448,22 @@ __device__ __forceinline__ void fks_store(const FksArgs& a, int which, int64_t e
     const double D = (fabs(gR) + fabs(gS) + fabs(gC) + fabs(gCm) + fabs(gSC) + fabs(gSCm)) / kap;
     const double c = (which & 1) ? 1e-12 : 32.0 * 0x1p-24 * (1.0 + 1.0 / sqrt(1.0 - fabs(y)));
     if (!(c * D <= 1e-3 * fabs(W))) st |= 8;
+  }
+  // MIXED: an FP32 event whose W is unresolved or not finite goes on the redo
+  // list (wave-aggregated append; the FP64 pass overwrites every output of
+  // the event): bucket positions from the front, skipped ones from the back
+  if ((which == 0 || which == 2) && a.mode == 2) {
+    const bool redo = (st & 9) != 0;
+    const unsigned long long m = __ballot(redo);
+    if (m) {
+      const int lane = __lane_id();
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned base = 0u;
+      if (lane == leader) base = atomicAdd(&a.cnt[which == 0 ? 4 : 5], (unsigned)__popcll(m));
+      base = __shfl(base, leader);
+      const int64_t k = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+      if (redo) a.redo[which == 0 ? k : a.n - 1 - k] = (unsigned)pos;
+    }
   }
   a.W[e] = W;
   if (a.dsig || a.jac) {
@@ -504,8 +526,9 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
   const double Bminus = born_sum<BM, T>(kb, a.mt) * a.scale_bm;
   const double Pp = FKS_CF * (x * Bplus + 4.0 * xi / x * Bperp);
   const double Pm = 0.5 * (x * x + xi * xi) * Bminus;
-  const double gR = which >= 2 ? 0.0 : xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
-  fks_store<S>(a, which, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, K);
+  const bool skipped = which == 2 || which == 3 || which == 7;
+  const double gR = skipped ? 0.0 : xi * xi * (1.0 - y) * (1.0 + y) * a.me2r[pos] * S_real;
+  fks_store<S>(a, which, pos, e, Bplus, gR, 0.0, 8.0 * xi * g2 / K.sb * Pp, 8.0 * xi * g2 / K.sb * Pm, 0.0, 0.0, K);
 }
 
 // 3. Born correlations, counterterms and subtracted weight for one bucket
@@ -513,13 +536,22 @@ template <class S, class T>
 __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which) {
   using BP = typename S::Born;
   // which: 0 / 1 the FP32 / FP64 bucket of evaluated real emissions, 2 / 3 the
-  // FP32 / FP64 part of the skipped list (no real |M|^2: its R cut failed)
-  const bool skipped = which >= 2;
-  const bool back = which & 1;
-  const int64_t lo = back ? a.n - (int64_t)a.cnt[which] : 0;
-  const int64_t hi = back ? a.n : (int64_t)a.cnt[which];
-  const int64_t pos = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= hi) return;
+  // FP32 / FP64 part of the skipped list (no real |M|^2: its R cut failed),
+  // 5 / 7 the FP32 bucket / skipped positions on the redo list (MIXED,
+  // evaluated in FP64)
+  const bool skipped = which == 2 || which == 3 || which == 7;
+  int64_t pos;
+  if (which == 5 || which == 7) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)a.cnt[which == 5 ? 4 : 5]) return;
+    pos = a.redo[which == 5 ? i : a.n - 1 - i];
+  } else {
+    const bool back = which & 1;
+    const int64_t lo = back ? a.n - (int64_t)a.cnt[which] : 0;
+    const int64_t hi = back ? a.n : (int64_t)a.cnt[which];
+    pos = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= hi) return;
+  }
   const int64_t e = skipped ? a.skip_inv[pos] : a.inv[pos];
   double kb[S::NB][4], kr[S::NR][4];
   FksKin K;
@@ -540,7 +572,7 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
       const double me2r = skipped ? 0.0 : a.me2r[pos];
       const double gR = S::J >= 0 ? K.xi * K.xi * (1.0 - K.y) * me2r * S_real
                                   : K.xi * K.xi * (1.0 - K.y) * (1.0 + K.y) * me2r * S_real;
-      fks_store<S>(a, which, e, 0.0, gR, 0.0, 0.0, 0.0, 0.0, 0.0, K);
+      fks_store<S>(a, which, pos, e, 0.0, gR, 0.0, 0.0, 0.0, 0.0, 0.0, K);
       return;
     }
   }
@@ -642,11 +674,10 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which
     gSC = 16.0 * g2 * Cp / K.sb * B;
     gSCm = 16.0 * g2 * Cm / K.sb * B;
   }
-  fks_store<S>(a, which, e, B, gR, gS, gC, gCm, gSC, gSCm, K);
+  fks_store<S>(a, which, pos, e, B, gR, gS, gC, gCm, gSC, gSCm, K);
   }
 }
 
-// fixed-order FP64 sum (single block; deterministic for a given n)
 // Fixed-order FP64 sum of x[0, n): block b of FKS_SUM_PARTS reduces its
 // contiguous share into part[b] (strided per thread, then a tree), and one
 // block adds the parts the same way.  The order depends on n only, so the sum

@@ -35,7 +35,7 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
 // vector-ALU kernel: any arithmetic type T
 // ---------------------------------------------------------------------------
 // event range of a launch: all of [0, n), or one bucket of a bucketed batch
-// (which = 0: [0, cnt[0]), 1: [n - cnt[1], n)); which = 2 (vector-ALU kernel
+// (which = 0: [0, cnt[0]), 1: [n - cnt[1], n)); which = 2 (vector-ALU kernels
 // only) takes the events listed in list[0, cnt[0]) instead
 __device__ __forceinline__ void event_range(int64_t n, const unsigned* cnt, int which, int64_t& lo, int64_t& hi) {
   lo = 0;
@@ -325,7 +325,7 @@ hipError_t launch_me2(const LaunchArgs& a) {
   if constexpr (VARIANT == VAR_F64 || VARIANT == VAR_F64_ALT) {
     constexpr int SCHED = VARIANT == VAR_F64_ALT ? 1 : 0;
     hipLaunchKernelGGL((k_me2_valu<P, double, SCHED>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld,
-                       a.mom, a.out, a.scale, a.mt, a.cnt, a.which, (const unsigned*)nullptr, a.ovp, a.ovv);
+                       a.mom, a.out, a.scale, a.mt, a.cnt, a.which, a.list, a.ovp, a.ovv);
   } else if constexpr (VARIANT == VAR_F32 || VARIANT == VAR_F32_ALT) {
     constexpr int SCHED = VARIANT == VAR_F32_ALT ? 1 : 0;
     hipLaunchKernelGGL((k_me2_valu<P, float, SCHED>), dim3((unsigned)grid), dim3(a.block), 0, a.stream, a.n, a.ld,

@@ -3,7 +3,9 @@ pushed in uneven pieces join a real-emission queue and a counterterm queue by
 their cuts, each queue is evaluated on its own terms when it holds enough
 events, and after the flush every slot holds the subtracted weight W of
 nlo_subtracted with the same masks, within 1e-12 (|W| + D) (the two-part sum
-rounds differently), and bit for bit the same whatever the push pattern."""
+rounds differently; in MIXED, on the events that the direct call evaluates
+again in FP64, within the FP32 rounding bound), and bit for bit the same
+whatever the push pattern."""
 import numpy as np
 import pytest
 
@@ -76,10 +78,19 @@ def test_buffer_matches_subtracted(gpu, case):
     den = np.abs(d["W"]) + D
     off = den == 0                      # every term masked: W = 0 on both sides
     assert np.all(a[off] == 0.0) and np.all(d["W"][off] == 0.0)
-    r = np.abs(a - d["W"])[~off] / den[~off]
-    print("%s (%d,%d) %s: %d events all masked; max |dW| / (|W| + D) %.2e" % (real, i, j, prec, off.sum(), r.max()),
-          flush=True)
-    assert np.all(r <= 1e-12)
+    # MIXED evaluates an FP32 event again in FP64 when W, the difference of
+    # its real and counterterm parts, is not resolved (status bit 4).  The
+    # queues evaluate the two parts apart, each resolved on its own, so they
+    # keep FP32 there: on those events the two differ by up to the FP32
+    # rounding bound 32 eps_32 (1 + 1/sqrt(1-|y|)) D.
+    redone = (d["status"] & 16) != 0
+    c32 = 32 * 2.0 ** -24 * (1 + 1 / np.sqrt(1 - np.abs(y)))
+    bound = np.where(redone, c32 * D, 1e-12 * den)
+    dW = np.abs(a - d["W"])
+    r = dW[~off] / den[~off]
+    print("%s (%d,%d) %s: %d events all masked; max |dW| / (|W| + D) %.2e on the %d events the direct call did "
+          "not re-evaluate" % (real, i, j, prec, off.sum(), r[~redone[~off]].max(), (~redone).sum()), flush=True)
+    assert np.all(dW[~off] <= bound[~off])
     assert np.array_equal(a, b)
 
 

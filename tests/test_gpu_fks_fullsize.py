@@ -56,7 +56,8 @@ def test_fks_full_size_sampled(gpu, orc, real, i, j, born, rs, n):
             assert np.all(routed)
             assert np.all(dW <= fp64_bound)
         else:
-            assert np.array_equal(routed, kappa < 0.1)
+            redone = (st[idx] & 16) != 0
+            assert np.array_equal(routed & ~redone, kappa < 0.1)
             assert np.all(dW[~routed] <= 1e-3 * np.abs(ref["W"][~routed]))
             assert np.all(dW[routed] <= fp64_bound[routed])
         assert np.all(dW[~unres] <= 1e-3 * np.abs(ref["W"][~unres]))
@@ -67,8 +68,10 @@ def test_fks_full_size_sampled(gpu, orc, real, i, j, born, rs, n):
 def test_mixed_buckets_bitwise(gpu):
     """At 2^18 events MIXED runs its FP64 bucket beside the FP32 one on a
     second stream: every event's W equals, bit for bit, its value from the
-    all-FP64 call (routed events) or the all-FP32 call (the others), and the
-    fixed-order sum of W taken after the join equals the sum of those W."""
+    all-FP64 call (routed or re-evaluated events) or the all-FP32 call (the
+    others); exactly the FP32 events with an unresolved or non-finite W are
+    re-evaluated; and the fixed-order sum of W taken after the join equals
+    the sum of those W."""
     import torch
     real, i, j, born, rs, n = "gg_ttg", 4, -1, "gg_tt", (400.0, 2000.0), 1 << 18
     mom, _ = events(born, n, rs, stream=43)
@@ -79,11 +82,19 @@ def test_mixed_buckets_bitwise(gpu):
     for prec in ("mixed", "fp64", "fp32"):
         r = gpu.subtracted(real, i, j, M, X, Y, P, prec=prec, want_sum=True)
         torch.cuda.synchronize()
-        got[prec] = {k: r[k].cpu().numpy() for k in ("W", "status", "w_sum")}
+        got[prec] = {k: r[k].cpu().numpy() for k in ("W", "status", "w_sum", "xi")}
     routed = (got["mixed"]["status"] & 2) != 0
     assert 0.1 < routed.mean() < 0.5
     expect = np.where(routed, got["fp64"]["W"], got["fp32"]["W"])
     assert np.array_equal(got["mixed"]["W"], expect)
+    # the FP32 events whose W came out unresolved were evaluated again in FP64
+    redone = (got["mixed"]["status"] & 16) != 0
+    kap = got["mixed"]["xi"] * (1 - y) * (1 + y)
+    near = np.abs(kap / 0.1 - 1) < 1e-12
+    expect_redo = (kap >= 0.1) & ((got["fp32"]["status"] & 9) != 0)
+    assert np.array_equal(redone[~near], expect_redo[~near])
+    assert np.array_equal(got["mixed"]["status"] & 8, got["fp64"]["status"] & 8)
+    print("re-evaluated in FP64: %.4f of the events" % redone.mean(), flush=True)
     again = gpu.subtracted(real, i, j, M, X, Y, P, prec="mixed", want_sum=True)
     torch.cuda.synchronize()
     assert np.array_equal(again["W"].cpu().numpy(), got["mixed"]["W"])

@@ -11,7 +11,10 @@ cancels, D = sum|g_X| / kappa, with no further power of kappa:
          (Measured: at most 3.3e-13 sum|g_X|, the rounding of the real
          |M|^2; counterterms within 1.2e-13.)
   MIXED: FP32 where kappa >= 0.1, FP64 below: |dW| <= 1e-3 |W| on every
-         FP32-routed event (measured <= 1.5e-5), the FP64 bound on the others.
+         FP32-routed event (measured <= 1.5e-5), the FP64 bound on the others;
+         an FP32 event whose W comes out unresolved is evaluated again in
+         FP64 (status bits 1 and 4), so MIXED flags bit 3 exactly where FP64
+         does.
   FP32 : all events in FP32: |dW| <= 1e-3 D (FP32 is accurate only away
          from the limits; MIXED is the mode for near-singular sets).
 Every event without status bit 3 (W resolved in its precision) is within
@@ -136,15 +139,20 @@ def test_fks_mixed_parity(gpu, orc, sector):
     dW = np.abs(got["W"] - ref["W"])
     rel = dW / np.abs(ref["W"])
     routed = (got["status"] & 2) != 0
+    redone = (got["status"] & 16) != 0
     unres = (got["status"] & 8) != 0
     kap = got["xi"] * ((1 - y) if j >= 0 else (1 - y) * (1 + y))
     # routing: FP64 exactly below the threshold (kappa as the kernel forms it
-    # may differ in the last bit near the threshold)
+    # may differ in the last bit near the threshold), plus the re-evaluated
     near = np.abs(kap / THR - 1) < 1e-12
-    assert np.array_equal(routed[~near], kap[~near] < THR)
-    print(real, i, j, "mixed: routed %.3f, FP32 |dW|/|W| max %.2e, unresolved %.3f, all |dW|/|W| p99.9 %.2e" % (
-        routed.mean(), rel[~routed].max() if np.any(~routed) else 0.0, unres.mean(), np.quantile(rel, 0.999)),
-        flush=True)
+    assert np.array_equal((routed & ~redone)[~near], kap[~near] < THR)
+    assert np.all(routed[redone]) and not np.any(redone & (kap < THR) & ~near)
+    fp64 = _gpu_run(gpu, sector, mom, xt, y, phi, "fp64")
+    assert np.array_equal(unres, (fp64["status"] & 8) != 0)
+    assert np.array_equal(got["W"][routed], fp64["W"][routed])
+    print(real, i, j, "mixed: routed %.3f (re-evaluated %.3f), FP32 |dW|/|W| max %.2e, unresolved %.3f, "
+          "all |dW|/|W| p99.9 %.2e" % (routed.mean(), redone.mean(), rel[~routed].max() if np.any(~routed) else 0.0,
+                                       unres.mean(), np.quantile(rel, 0.999)), flush=True)
     bound = np.where(routed, 1e-12 * (np.abs(ref["W"]) + D), 1e-3 * np.abs(ref["W"]))
     assert np.all(dW <= bound)
     assert np.all(rel[~unres] <= 1e-3)
@@ -158,8 +166,8 @@ def test_fks_mixed_parity(gpu, orc, sector):
 def test_fks_mixed_parity_flat(gpu, orc, sector):
     """MIXED on radiation variables drawn flat over the radiation phase space,
     where most events sit away from the limits and run in FP32: the same
-    bounds as on the stress sets (1e-3 |W| where FP32 resolves W, 1e-3 D where
-    it does not, the FP64 bound on the events routed to FP64)."""
+    bounds as on the stress sets (1e-3 |W| where FP32 resolves W, the FP64
+    bound on the events routed to FP64 or evaluated again there)."""
     real, i, j = sector[:3]
     n = _n(sector)
     mom, xt, y, phi = _inputs(sector, n, 205, "flat")
@@ -169,13 +177,16 @@ def test_fks_mixed_parity_flat(gpu, orc, sector):
     dW = np.abs(got["W"] - ref["W"])
     rel = dW / np.abs(ref["W"])
     routed = (got["status"] & 2) != 0
+    redone = (got["status"] & 16) != 0
     unres = (got["status"] & 8) != 0
     kap = got["xi"] * ((1 - y) if j >= 0 else (1 - y) * (1 + y))
     near = np.abs(kap / THR - 1) < 1e-12
-    assert np.array_equal(routed[~near], kap[~near] < THR)
-    print(real, i, j, "flat mixed: routed %.3f, FP32 |dW|/|W| max %.2e, |dW|/D max %.2e, unresolved %.3f" % (
-        routed.mean(), rel[~routed & ~unres].max(), (dW / D)[~routed].max(), unres.mean()), flush=True)
+    assert np.array_equal((routed & ~redone)[~near], kap[~near] < THR)
+    print(real, i, j, "flat mixed: routed %.3f (re-evaluated %.3f), FP32 |dW|/|W| max %.2e, |dW|/D max %.2e, "
+          "unresolved %.3f" % (routed.mean(), redone.mean(), rel[~routed].max(), (dW / D)[~routed].max(),
+                               unres.mean()), flush=True)
     assert routed.mean() < 0.5                  # most of a flat set runs in FP32
+    assert not np.any(unres & ~routed)          # an unresolved FP32 W was evaluated again
     fp32_bound = np.where(unres, 1e-3 * D, 1e-3 * np.abs(ref["W"]))
     bound = np.where(routed, 1e-12 * (np.abs(ref["W"]) + D), fp32_bound)
     assert np.all(dW <= bound)

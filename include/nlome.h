@@ -25,8 +25,7 @@
  *    internally.  Distinct contexts are independent.
  *  - Device memory is allocated only by nlo_reserve (the context workspace),
  *    nlo_batch_plan (its own workspaces) and nlo_create (nothing beyond HIP's
- *    context, one stream and two events of the context).  Evaluation calls
- *    never allocate or synchronise the device; one
+ *    context).  Evaluation calls never allocate or synchronise the device; one
  *    that needs more workspace than reserved returns NLO_EINVAL.  Calls that
  *    overlap on different streams with the same context share its workspace
  *    and race on it: order them on one stream, or use one context per stream.
@@ -289,12 +288,7 @@ typedef struct {
  *              y = -1 end (g_Cm, g_SCm) (nlo_fks_cut_masks writes these).
  *   prec:      NLO_FP64, NLO_FP32 (real amplitudes in float, kinematics and
  *              assembly in double) or NLO_MIXED (float unless the event is
- *              near a singular limit, see nlo_set_fks_threshold).  For
- *              n >= 2^18, unless hip_stream is being captured, MIXED
- *              evaluates its FP64 events on the context's own stream, forked
- *              from hip_stream after the map and joined back to it (work on
- *              hip_stream stays ordered); otherwise both buckets run on
- *              hip_stream.
+ *              near a singular limit, see nlo_set_fks_threshold).
  * The Born point is on shell and conserves momentum by definition: the
  * final-state three-momenta are shifted by a common amount to sum to zero,
  * their energies put on the mass shell, and the beams (along +-z) carry half

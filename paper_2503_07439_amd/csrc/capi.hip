@@ -75,11 +75,6 @@ struct nlo_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int64_t ws_events = 0;
-  // MIXED FKS evaluation runs its FP64 bucket on this stream beside the FP32
-  // bucket on the caller's stream (fork and join through the two events), so
-  // that the tail of one bucket's launch overlaps the other's
-  hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -231,30 +226,12 @@ nlo_status nlo_create(nlo_ctx** out, const nlo_params* params) {
     for (auto& k : row) k = nlo_kernel_config{256, 0, 0};
   for (auto& row : c->fks_cfg)
     for (auto& k : row) k = nlo_fks_config{256, 0, 256};
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess || (cur != params->device && hipSetDevice(params->device) != hipSuccess)) {
-    delete c;
-    return fail(NLO_EDEVICE, "nlo_create: cannot make device %d current", params->device);
-  }
-  const bool ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
-                  hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
-  if (cur != params->device) (void)hipSetDevice(cur);
-  if (!ok) {
-    nlo_destroy(c);
-    return fail(NLO_EDEVICE, "nlo_create: stream or event creation failed");
-  }
   *out = c;
   return NLO_OK;
 }
 
 nlo_status nlo_destroy(nlo_ctx* ctx) {
-  if (!ctx) return NLO_OK;
-  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
-  if (ctx->ws) (void)hipFree(ctx->ws);
-  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
-  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx && ctx->ws) (void)hipFree(ctx->ws);
   delete ctx;
   return NLO_OK;
 }
@@ -438,53 +415,22 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   }
   la.ovv = a.pinv;
   const bool mfma = (fc.colour_mode ? fc.colour_mode : auto_colour_mode(real_proc, prec)) == 2;
-  // the two buckets write disjoint events: in MIXED mode the FP64 one runs on
-  // the side stream, forked after the map and joined before the sum, so that
-  // each bucket's last, partly filled wave of blocks overlaps the other's.
-  // Only for batches large enough to gain (the fork and join cost about as
-  // much as the small kernels of 2^16 events), and not under stream capture:
-  // there both stay on s (a batch-plan capture with the fork ended the
-  // process inside the plan call, cause not identified)
-  constexpr int64_t FORK_MIN_EVENTS = 1 << 18;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusActive;
-  const bool fork = err == hipSuccess && a.mode == 2 && n >= FORK_MIN_EVENTS && ctx->side &&
-                    hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
-  hipStream_t s64 = fork ? ctx->side : s;
-  if (fork) {
-    err = hipEventRecord(ctx->fork_ev, s);
-    if (err == hipSuccess) err = hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0);
-  }
+  // FP32 bucket first (real |M|^2, then counterterms and W, which list the
+  // events whose W came out unresolved or non-finite), then one FP64 launch of
+  // each kernel over the FP64 bucket followed by that list (MIXED; a launch
+  // of the largest FP64 kernels costs about 1.6 ms before any work, so the
+  // re-evaluation gets no launch of its own)
   if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
-  if (err == hipSuccess && a.mode != 0) {
-    la.which = 1;
-    la.stream = s64;
-    err = ME2_LAUNCH[real_proc][VAR_F64](la);
-  }
   if (err == hipSuccess && a.mode != 1) err = sec->born_fn[1](a, 0, block, s);
-  if (err == hipSuccess && a.mode != 0) err = sec->born_fn[0](a, 1, block, s64);
   // compact mode: counterterms of the events that skipped the real |M|^2
   if (err == hipSuccess && a.compact && a.mode != 1) err = sec->born_fn[1](a, 2, block, s);
-  if (err == hipSuccess && a.compact && a.mode != 0) err = sec->born_fn[0](a, 3, block, s64);
-  if (fork) {
-    // join even after an error, so that a capture in progress stays whole
-    hipError_t e2 = hipEventRecord(ctx->join_ev, ctx->side);
-    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(s, ctx->join_ev, 0);
-    if (err == hipSuccess) err = e2;
+  if (err == hipSuccess && a.mode != 0) {
+    la.which = a.mode == 2 ? 3 : 1;
+    la.list = a.redo;
+    err = ME2_LAUNCH[real_proc][VAR_F64](la);
   }
-  // MIXED: the FP32 events whose W came out unresolved or non-finite (listed
-  // by the FP32 counterterm kernel) again in FP64: real |M|^2 at their bucket
-  // positions, then counterterms and W (and those of the listed events whose
-  // real emission compact mode skipped)
-  if (err == hipSuccess && a.mode == 2) {
-    LaunchArgs lr = la;
-    lr.stream = s;
-    lr.which = 2;
-    lr.list = a.redo;
-    lr.cnt = a.cnt + 4;
-    err = ME2_LAUNCH[real_proc][VAR_F64](lr);
-    if (err == hipSuccess) err = sec->born_fn[0](a, 5, block, s);
-    if (err == hipSuccess && a.compact) err = sec->born_fn[0](a, 7, block, s);
-  }
+  if (err == hipSuccess && a.mode != 0) err = sec->born_fn[0](a, a.mode == 2 ? 9 : 1, block, s);
+  if (err == hipSuccess && a.compact && a.mode != 0) err = sec->born_fn[0](a, a.mode == 2 ? 11 : 3, block, s);
   if (err == hipSuccess && out->w_sum) {
     // partial sums after the bucket counters (which take the first 64 bytes)
     double* part = reinterpret_cast<double*>(a.cnt + 16);

@@ -533,25 +533,37 @@ __device__ __forceinline__ void fks_quark_isr(const FksArgs& a, int which, int64
 
 // 3. Born correlations, counterterms and subtracted weight for one bucket
 template <class S, class T>
-__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int which) {
+__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_fks_born(FksArgs a, int launch) {
   using BP = typename S::Born;
-  // which: 0 / 1 the FP32 / FP64 bucket of evaluated real emissions, 2 / 3 the
-  // FP32 / FP64 part of the skipped list (no real |M|^2: its R cut failed),
-  // 5 / 7 the FP32 bucket / skipped positions on the redo list (MIXED,
-  // evaluated in FP64)
-  const bool skipped = which == 2 || which == 3 || which == 7;
+  // launch: 0 / 1 the FP32 / FP64 bucket of evaluated real emissions, 2 / 3
+  // the FP32 / FP64 part of the skipped list (no real |M|^2: its R cut
+  // failed); MIXED, in FP64: 9 the FP64 bucket, then the FP32-bucket
+  // positions on the redo list, 11 the FP64 part of the skipped list, then
+  // the skipped positions on the redo list.  Each event is evaluated and
+  // stored as `which`: 0 to 3 as above, 5 / 7 a re-evaluated bucket /
+  // skipped event.
+  int which = launch;
   int64_t pos;
-  if (which == 5 || which == 7) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)a.cnt[which == 5 ? 4 : 5]) return;
-    pos = a.redo[which == 5 ? i : a.n - 1 - i];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (launch == 9 || launch == 11) {
+    const int64_t c = a.cnt[launch == 9 ? 1 : 3];
+    if (i < c) {
+      pos = a.n - c + i;
+      which = launch == 9 ? 1 : 3;
+    } else {
+      const int64_t j = i - c;
+      if (j >= (int64_t)a.cnt[launch == 9 ? 4 : 5]) return;
+      pos = a.redo[launch == 9 ? j : a.n - 1 - j];
+      which = launch == 9 ? 5 : 7;
+    }
   } else {
-    const bool back = which & 1;
-    const int64_t lo = back ? a.n - (int64_t)a.cnt[which] : 0;
-    const int64_t hi = back ? a.n : (int64_t)a.cnt[which];
-    pos = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool back = launch & 1;
+    const int64_t lo = back ? a.n - (int64_t)a.cnt[launch] : 0;
+    const int64_t hi = back ? a.n : (int64_t)a.cnt[launch];
+    pos = lo + i;
     if (pos >= hi) return;
   }
+  const bool skipped = which == 2 || which == 3 || which == 7;
   const int64_t e = skipped ? a.skip_inv[pos] : a.inv[pos];
   double kb[S::NB][4], kr[S::NR][4];
   FksKin K;
@@ -792,9 +804,9 @@ hipError_t launch_fks_map(const FksArgs& a, int block, hipStream_t st) {
 }
 
 template <class S, class T>
-hipError_t launch_fks_born(const FksArgs& a, int which, int block, hipStream_t st) {
+hipError_t launch_fks_born(const FksArgs& a, int launch, int block, hipStream_t st) {
   const int64_t grid = (a.n + block - 1) / block;
-  hipLaunchKernelGGL((k_fks_born<S, T>), dim3((unsigned)grid), dim3(block), 0, st, a, which);
+  hipLaunchKernelGGL((k_fks_born<S, T>), dim3((unsigned)grid), dim3(block), 0, st, a, launch);
   return hipGetLastError();
 }
 

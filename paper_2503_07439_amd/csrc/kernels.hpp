@@ -35,8 +35,10 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
 // vector-ALU kernel: any arithmetic type T
 // ---------------------------------------------------------------------------
 // event range of a launch: all of [0, n), or one bucket of a bucketed batch
-// (which = 0: [0, cnt[0]), 1: [n - cnt[1], n)); which = 2 (vector-ALU kernels
-// only) takes the events listed in list[0, cnt[0]) instead
+// (which = 0: [0, cnt[0]), 1: [n - cnt[1], n)); which = 2 (vector-ALU
+// kernels only) takes the events listed in list[0, cnt[0]) instead, and
+// which = 3 (FP64 vector-ALU kernel) [n - cnt[1], n) followed by the events
+// listed in list[0, cnt[4])
 __device__ __forceinline__ void event_range(int64_t n, const unsigned* cnt, int which, int64_t& lo, int64_t& hi) {
   lo = 0;
   hi = n;
@@ -67,6 +69,16 @@ __global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t l
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)cnt[0]) return;
     e = list[i];
+  } else if (std::is_same<T, double>::value && which == 3) {
+    // the FP64 bucket [n - cnt[1], n), then the events listed in list[0, cnt[4])
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c1 = cnt[1];
+    if (i < c1) {
+      e = n - c1 + i;
+    } else {
+      if (i - c1 >= (int64_t)cnt[4]) return;
+      e = list[i - c1];
+    }
   } else {
     int64_t lo, hi;
     event_range(n, cnt, which, lo, hi);

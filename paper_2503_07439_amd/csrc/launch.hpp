@@ -28,7 +28,9 @@ struct LaunchArgs {
   // all of [0, n); 0: [0, cnt[0]); 1: [n - cnt[1], n)
   const unsigned* cnt = nullptr;
   int which = -1;
-  // which = 2: the events listed in list[0, cnt[0]) (FP32 and FP64 variants)
+  // which = 2: the events listed in list[0, cnt[0]) (vector-ALU variants);
+  // which = 3 (FP64 vector-ALU variant): [n - cnt[1], n), then the events
+  // listed in list[0, cnt[4])
   const unsigned* list = nullptr;
   // FP16 / BF16 variants: workspace for the list of events evaluated again in
   // FP32 (fb_list: n entries, fb_cnt: one counter), and the FP32 launcher of

@@ -841,6 +841,10 @@ OPAQUE_MOMENTA = ("gg_ttgg",)
 # as the prologue, so the same bits), instead of holding all of them in
 # registers: 31 momenta cost 248 registers in FP64
 FP64_MOMENTUM_SUMS = ("gg_ttgg",)
+# waves per SIMD the FP32 |M|^2 kernel (default schedule) and the FP16/BF16
+# pair kernels are compiled for: the register budget then is 512 / waves per
+# lane (g g -> t tbar g needs 266 for one wave and spills 11 dwords at two)
+WAVES_F32 = {"gg_ttg": 2}
 # processes that also get the other lazy depth as a run-time schedule
 # variant (kernel configuration `schedule` = 1), for the autotuner
 SCHEDULE_ALTS = ("gg_ttg", "gg_ttgg")
@@ -1088,6 +1092,7 @@ def emit_process(p):
     # helicity_sum (and the first NGOOD / HEL_SYM entries of good()) cover one
     # helicity of each pair (h, -h); callers multiply their sums by HEL_SYM
     L.append("  static constexpr int HEL_SYM = %d;" % (2 if HEL_SYMMETRY else 1))
+    L.append("  static constexpr int WAVES_F32 = %d;   // waves per SIMD of the FP32 and pair kernels" % WAVES_F32.get(p.name, 1))
     L.append("  static constexpr int NMOM = %d, NDEN = %d;" % (len(msets), len(dens)))
     L.append("  static constexpr const char* NAME = \"%s\";" % nm)
     L.append("  static constexpr unsigned TOP_LEGS = 0x%x;   // bit k: leg k is a top quark"

@@ -60,7 +60,9 @@ __device__ __forceinline__ PairOv pair_ov(const PairOv& ovp, const double* __res
 }
 
 template <class P, class T, int SCHED = 0>
-__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
+__global__ __launch_bounds__(NLO_MAX_BLOCK)
+__attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value && SCHED == 0 ? P::WAVES_F32 : 1)))
+void k_me2_valu(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
                                                   const unsigned* cnt, int which, const unsigned* list,
                                                   PairOv ovp, const double* __restrict__ ovv) {
@@ -110,7 +112,8 @@ struct MfmaShape {
 };
 
 template <class P>
-__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_mfma(int64_t n, int64_t ld, const double* __restrict__ mom,
+__global__ __launch_bounds__(NLO_MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(P::WAVES_F32)))
+void k_me2_mfma(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
                                                   const unsigned* cnt, int which, PairOv ovp,
                                                   const double* __restrict__ ovv) {
@@ -259,7 +262,8 @@ __device__ __forceinline__ double scaled_prologue(const double* __restrict__ mom
 }
 
 template <class P, class V2>
-__global__ __launch_bounds__(NLO_MAX_BLOCK) void k_me2_pair(int64_t n, int64_t ld, const double* __restrict__ mom,
+__global__ __launch_bounds__(NLO_MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(P::WAVES_F32)))
+void k_me2_pair(int64_t n, int64_t ld, const double* __restrict__ mom,
                                                   double* __restrict__ out, double scale, double mt,
                                                   const unsigned* cnt, int which, unsigned* fb_list,
                                                   unsigned* fb_cnt) {

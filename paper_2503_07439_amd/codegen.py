@@ -843,7 +843,9 @@ OPAQUE_MOMENTA = ("gg_ttgg",)
 FP64_MOMENTUM_SUMS = ("gg_ttgg",)
 # waves per SIMD the FP32 |M|^2 kernel (default schedule) and the FP16/BF16
 # pair kernels are compiled for: the register budget then is 512 / waves per
-# lane (g g -> t tbar g needs 266 for one wave and spills 11 dwords at two)
+# lane (g g -> t tbar g needs 266 for one wave and spills 11 dwords at two;
+# its FP64 kernel, 472 registers, spills 1.1 KB at two waves and ran 2.1x
+# slower, so the FP64 kernels keep one)
 WAVES_F32 = {"gg_ttg": 2}
 # processes that also get the other lazy depth as a run-time schedule
 # variant (kernel configuration `schedule` = 1), for the autotuner

@@ -410,7 +410,10 @@ nlo_status nlo_fks_variables(nlo_ctx* ctx, int64_t n, uint32_t seed, uint32_t st
  * evaluation adds its contribution to W to w_out[slot] (device float64,
  * caller-owned, zeroed by the caller; one slot per event), so that after the
  * flush w_out[slot] = W of nlo_subtracted with the same masks (up to the
- * rounding of the two-part sum, within 1e-12 of D in FP64).  Each slot
+ * rounding of the two-part sum, within 1e-12 of D in FP64; in MIXED a queue
+ * sees the real and counterterm parts apart, not their cancellation, so the
+ * events that nlo_subtracted evaluates again in FP64 keep FP32 parts here,
+ * within the FP32 rounding bound).  Each slot
  * receives at most one contribution per queue, added in stream order, so the
  * result does not depend on how events were pushed.  create allocates the
  * queues and their own FKS workspace (2 threshold events); push and flush

@@ -66,12 +66,12 @@ def test_fks_full_size_sampled(gpu, orc, real, i, j, born, rs, n):
 
 
 def test_mixed_buckets_bitwise(gpu):
-    """At 2^18 events MIXED runs its FP64 bucket beside the FP32 one on a
-    second stream: every event's W equals, bit for bit, its value from the
-    all-FP64 call (routed or re-evaluated events) or the all-FP32 call (the
-    others); exactly the FP32 events with an unresolved or non-finite W are
-    re-evaluated; and the fixed-order sum of W taken after the join equals
-    the sum of those W."""
+    """MIXED at 2^18 events (FP32 bucket, then one FP64 launch over the FP64
+    bucket and the re-evaluation list): every event's W equals, bit for bit,
+    its value from the all-FP64 call (routed or re-evaluated events) or the
+    all-FP32 call (the others); exactly the FP32 events with an unresolved or
+    non-finite W are re-evaluated; the result is the same on a second call;
+    and the fixed-order sum of W equals the sum of those W."""
     import torch
     real, i, j, born, rs, n = "gg_ttg", 4, -1, "gg_tt", (400.0, 2000.0), 1 << 18
     mom, _ = events(born, n, rs, stream=43)

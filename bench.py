@@ -397,11 +397,11 @@ def mask_study(ctx, steps):
     return {"sector": "gg_ttgg (4,5)", "events": n, "precision": "mixed", "buffer_pieces": n // piece, "rows": rows}
 
 
-def measured_traffic(kernel, n):
-    """HBM bytes per launch from the committed rocprofv3 counter passes
-    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), scaled to
-    n events -- or None when the kernel sources or compile flags (build.py)
-    have changed since the counters were taken, or for another kernel."""
+def measured_counters(kernel):
+    """The machine-readable record of the committed rocprofv3 counter passes
+    of the headline kernel (dict), or None when the kernel sources or compile
+    flags (build.py) have changed since the counters were taken, or for
+    another kernel."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "gg_ttg_2p22_counters.md")
     if not os.path.exists(path):
@@ -416,6 +416,16 @@ def measured_traffic(kernel, n):
         with open(os.path.join(ROOT, "paper_2503_07439_amd", f), "rb") as fh:
             h.update(fh.read())
     if not rec or rec.get("sources") != h.hexdigest()[:16] or rec.get("kernel") != kernel.replace(" ", ""):
+        return None
+    return rec
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch from the counter passes (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a copy kernel), scaled to n events, or
+    None (see measured_counters)."""
+    rec = measured_counters(kernel)
+    if rec is None:
         return None
     return (int(rec["fetch_bytes"]) + int(rec["write_bytes"])) * n / int(rec["events"])
 
@@ -638,6 +648,15 @@ def main():
         # packed FP32 instructions are not generated (compiler flag), so the
         # single-issue vector FP32 rate is the attainable ceiling
         roofline["frac_of_unpacked_fp32_peak"] = achieved / PEAK["fp64"]
+        # the executed FP32 flops from the counters (the algorithmic count keeps
+        # common subexpressions that the compiler removes, so its rate can pass
+        # the single-issue ceiling)
+        rec = measured_counters(kernel)
+        if rec is not None and "fp32_flops_per_event" in rec:
+            ex = float(rec["fp32_flops_per_event"]) * n / (ms * 1e-3) / 1e12
+            roofline["executed_fp32_flops_per_event"] = float(rec["fp32_flops_per_event"])
+            roofline["executed_fp32_tflops"] = ex
+            roofline["executed_frac_of_unpacked_fp32_peak"] = ex / PEAK["fp64"]
 
     study = None if args.no_mask_study else mask_study(ctx, 2)
 

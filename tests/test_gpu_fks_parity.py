@@ -257,13 +257,15 @@ def test_fks_argument_errors(gpu):
     assert e.value.status == 1
 
 
+@pytest.mark.parametrize("spread", ["log", "flat"])
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 @pytest.mark.parametrize("sector", [SECTORS[0], SECTORS[2], SECTORS[4], SECTORS[8]], ids=lambda s: "%s_%d_%d" % s[:3])
-def test_fks_compact_masks_bitwise(gpu, sector, prec):
+def test_fks_compact_masks_bitwise(gpu, sector, prec, spread):
     """Compact mode (events failing the R cut skip the real |M|^2) gives
-    bit for bit the results of the branch-free mode."""
+    bit for bit the results of the branch-free mode, also where MIXED
+    evaluates FP32 events again in FP64 (frequent on the flat sets)."""
     n = 500 if sector[0] != "gg_ttgg" else 120
-    mom, xt, y, phi = _inputs(sector, n, 204)
+    mom, xt, y, phi = _inputs(sector, n, 204, spread)
     rng = np.random.default_rng(11)
     mask = (rng.uniform(size=(4, n)) > np.array([[0.1], [0.5], [0.1], [0.1]])).astype(np.uint8)
     ref = _gpu_run(gpu, sector, mom, xt, y, phi, prec, mask=mask, want_sum=True)

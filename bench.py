@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-fks", action="store_true", help="skip the subtracted-weight legs")
     ap.add_argument("--no-integrate", action="store_true", help="skip the device integration leg")
     ap.add_argument("--no-mask-study", action="store_true", help="skip the cut-mask study")
+    ap.add_argument("--no-probe", action="store_true", help="skip the attainable-FMA probe")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -397,6 +398,32 @@ def mask_study(ctx, steps):
     return {"sector": "gg_ttgg (4,5)", "events": n, "precision": "mixed", "buffer_pieces": n // piece, "rows": rows}
 
 
+def attainable_fma():
+    """Attainable vector FMA throughput of this device (TFLOP/s, FP32 and
+    FP64) from the probe library: 2048 blocks of 256 threads, eight
+    independent FMA chains per thread, timed with HIP events on the current
+    stream.  The published peaks assume the 2.4 GHz engine clock; this is
+    what the vector ALU delivers at the clock it runs."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2503_07439_amd", "libnlome_probe.so"))
+    lib.nlo_probe_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    blocks, iters = 2048, 20000
+    res = {}
+    for prec, dt in ((0, torch.float32), (1, torch.float64)):
+        out = torch.empty(blocks * 256, dtype=dt, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+
+        def run():
+            rc = lib.nlo_probe_fma(prec, blocks, iters, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream))
+            if rc != 0:
+                raise RuntimeError("FMA probe launch failed (%d)" % rc)
+        ms = timed_fn(run, 5, warmup=2)
+        res["fp32" if prec == 0 else "fp64"] = blocks * 256 * 16.0 * iters / (ms * 1e-3) / 1e12
+    return {"fp32_tflops": res["fp32"], "fp64_tflops": res["fp64"],
+            "probe": "2048 x 256 threads, 8 independent FMA chains each, 20000 iterations"}
+
+
 def measured_counters(kernel):
     """The machine-readable record of the committed rocprofv3 counter passes
     of the headline kernel (dict), or None when the kernel sources or compile
@@ -637,6 +664,10 @@ def main():
     with open(os.path.join(ROOT, "paper_2503_07439_amd", "flops.json")) as f:
         fl = json.load(f)[proc]
     flops_event = fl["nested_flops_per_event_folded"]
+    att = None if args.no_probe else attainable_fma()
+    if att is not None:
+        print("attainable FMA: fp32 %.1f TFLOP/s, fp64 %.1f TFLOP/s" % (att["fp32_tflops"], att["fp64_tflops"]),
+              file=sys.stderr, flush=True)
     achieved = flops_event * n / (ms * 1e-3) / 1e12
     peak = PEAK[args.prec if args.prec in PEAK else "fp32"]
     kernel = kernel_name(ctx, proc, args.prec)
@@ -657,6 +688,8 @@ def main():
             roofline["executed_fp32_flops_per_event"] = float(rec["fp32_flops_per_event"])
             roofline["executed_fp32_tflops"] = ex
             roofline["executed_frac_of_unpacked_fp32_peak"] = ex / PEAK["fp64"]
+            if att is not None:
+                roofline["executed_frac_of_attainable_fp32_fma"] = ex / att["fp32_tflops"]
 
     study = None if args.no_mask_study else mask_study(ctx, 2)
 
@@ -705,7 +738,8 @@ def main():
                    "sqrt_s_hat_GeV": list(rs) if isinstance(rs, tuple) else rs, "m_top_GeV": 173.0,
                    "precision": args.prec, "diagrams": info.ndiagrams, "colour_flows": info.ncolour,
                    "helicities": info.ngood_hel},
-        "roofline": roofline, "cpu_baseline": cpu, "fp64_gpu": fp64, "other_colour_unit": other,
+        "roofline": roofline, "attainable_valu_peak": att, "cpu_baseline": cpu, "fp64_gpu": fp64,
+        "other_colour_unit": other,
         "half_precision": half, "device_generation": gen, "batch_mix": mix, "mask_study": study,
         "other_configs": others, "gg_ttgg_2p20": ttgg, "fks_subtracted": fks_rows, "integrated_subtracted": integ,
     }

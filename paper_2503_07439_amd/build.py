@@ -11,6 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnlome.so")
+PROBE_LIB = os.path.join(HERE, "libnlome_probe.so")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -139,8 +140,20 @@ def build(verbose=True, extra_flags=(), jobs=None, force=True):
     os.replace(tmp, LIB)
     if verbose:
         print("linked", LIB, flush=True)
+    build_probe()
     count_flops(verbose)
     return LIB
+
+
+def build_probe():
+    """The FMA-throughput probe the benchmark uses to quote the attainable
+    vector-ALU peak (a library of its own: no part of the C ABI)."""
+    src = os.path.join(CSRC, "probe.hip")
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [_hipcc()] + HIPCC_FLAGS + ["-shared", "-o", tmp, src]
+    subprocess.run(cmd, check=True, capture_output=True)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 def count_flops(verbose=True):

@@ -418,7 +418,8 @@ hipError_t launch_subtracted(const nlo_ctx* ctx, const FksSector* sec, int real_
   // FP32 bucket first (real |M|^2, then counterterms and W, which list the
   // events whose W came out unresolved or non-finite), then one FP64 launch of
   // each kernel over the FP64 bucket followed by that list (MIXED; a launch
-  // of the largest FP64 kernels costs about 1.6 ms before any work, so the
+  // that has any event at all takes at least one wave's time for one event's
+  // whole helicity sum, about 1.7 ms in FP64 for g g -> t tbar g g, so the
   // re-evaluation gets no launch of its own)
   if (err == hipSuccess && a.mode != 1) err = ME2_LAUNCH[real_proc][mfma ? VAR_MFMA : VAR_F32](la);
   if (err == hipSuccess && a.mode != 1) err = sec->born_fn[1](a, 0, block, s);

@@ -105,9 +105,11 @@ typedef struct {
   int colour_mode;  /* 0 = automatic, 1 = vector ALU, 2 = matrix cores (FP32 family only) */
   int schedule;     /* helicity schedule of the vector-ALU FP64/FP32 kernels: 0 = the
                        generator's choice for the precision, 1 = the alternative lazy
-                       depth (one sub-current level more or less evaluated inside the
-                       deepest loop: fewer live registers or fewer flops), where the
-                       process has one (nlo_process_info: nschedules = 2) */
+                       depth (sub-currents evaluated once per helicity of their own
+                       legs where the default evaluates some of them inside the
+                       deepest loop, else one level of them inside it: fewer flops or
+                       fewer live registers), where the process has one
+                       (nlo_process_info: nschedules = 2) */
 } nlo_kernel_config;
 
 /* Launch configuration of one FKS sector's subtracted evaluation in one

@@ -824,10 +824,14 @@ def _linear(p, leg, fixed):
 # processes whose sub-currents one level above the deepest loop are also
 # evaluated lazily inside it (more flops, far fewer live registers)
 JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
-# the same for the FP64 instantiation where it differs (measured: FP64
-# g g -> t tbar g g is faster without the extra lazy level, FP32 with it;
-# FP64 g g -> t tbar g with it, 2.35 against 2.44 ms per 2^22 events)
-JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 0, "gg_ttg": 1}
+# the same for the FP64 instantiation where it differs.  Measured per 2^20
+# g g -> t tbar g g events: FP64 with 0, 1, 2 and 3 extra lazy levels 54.6,
+# 60, 48.2 and 40.8 ms (FP64 values take twice the registers; with three,
+# every sub-current is evaluated in the deepest loop, which spills least:
+# 1.3 against 4.7 KB per lane); FP32 with 1, 2 and 3 levels 11.0, 12.0 and
+# 11.9 ms.  FP64
+# g g -> t tbar g: with one level 2.35, without 2.44 ms per 2^22 events.
+JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 3, "gg_ttg": 1}
 # stop the compiler from hoisting those lazily emitted sub-currents back out
 KEEP_LAZY_IN_LOOP = True
 # processes whose helicity loops read the internal momenta through the
@@ -1246,16 +1250,25 @@ def emit_process(p):
     j_def = JIT_EXTRA_LEVELS.get(p.name, 0)
     j_f64 = JIT_EXTRA_LEVELS_FP64.get(p.name, j_def)
     if p.name in SCHEDULE_ALTS:
-        # both lazy depths under their own names; schedule 0 takes each
-        # precision's default depth, schedule 1 the other one
-        L.extend(emit_nested(p, mslot, dslot, N, nin, 0, "helicity_sum_lazy0"))
-        L.extend(emit_nested(p, mslot, dslot, N, nin, 1, "helicity_sum_lazy1"))
+        # each lazy depth in use under its own name; schedule 0 takes each
+        # precision's default depth, schedule 1 an alternative: no extra lazy
+        # level where the default has some, else one
+        alt = lambda d: 0 if d else 1
+        depths = sorted({j_def, alt(j_def), j_f64, alt(j_f64)})
+        for d in depths:
+            L.extend(emit_nested(p, mslot, dslot, N, nin, d, "helicity_sum_lazy%d" % d))
         L.append("  static constexpr int NSCHED = 2;")
         L.append("  template <int SCHED, class T, class F> NLO_HD static void helicity_sum_sched(const Pre<T>& s, T mt, "
                  "F&& body) {")
         L.append("    constexpr int def = std::is_same<T, double>::value ? %d : %d;" % (j_f64, j_def))
-        L.append("    if constexpr ((SCHED == 0 ? def : 1 - def) == 0) helicity_sum_lazy0(s, mt, body);")
-        L.append("    else helicity_sum_lazy1(s, mt, body);")
+        if depths == [0, 1]:
+            L.append("    if constexpr ((SCHED == 0 ? def : 1 - def) == 0) helicity_sum_lazy0(s, mt, body);")
+            L.append("    else helicity_sum_lazy1(s, mt, body);")
+        else:
+            L.append("    constexpr int depth = SCHED == 0 ? def : (def ? 0 : 1);")
+            for i, d in enumerate(depths):
+                L.append("    %sif constexpr (depth == %d) helicity_sum_lazy%d(s, mt, body);"
+                         % ("else " if i else "", d, d))
         L.append("  }")
     else:
         L.append("  static constexpr int NSCHED = 1;")

@@ -829,8 +829,8 @@ JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
 # 60, 48.2 and 40.8 ms (FP64 values take twice the registers; with three,
 # every sub-current is evaluated in the deepest loop, which spills least:
 # 1.3 against 4.7 KB per lane); FP32 with 1, 2 and 3 levels 11.0, 12.0 and
-# 11.9 ms.  FP64
-# g g -> t tbar g: with one level 2.35, without 2.44 ms per 2^22 events.
+# 11.9 ms.  FP64 g g -> t tbar g: with one level 2.35, without 2.44 ms per
+# 2^22 events.
 JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 3, "gg_ttg": 1}
 # stop the compiler from hoisting those lazily emitted sub-currents back out
 KEEP_LAZY_IN_LOOP = True

@@ -23,9 +23,11 @@ HIPCC_FLAGS = [
 
 # Per-unit overrides.  The BF16 variant of g g -> t tbar g g (an accuracy study:
 # gfx950 has no BF16 arithmetic, so every operation is widened to FP32 and
-# rounded back) takes about 7.5 minutes to optimise at -O3, far longer than
-# every other unit together.
-UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-O1",)}
+# rounded back) takes 7.5 minutes to optimise at -O3, far longer than every
+# other unit together, almost all of it in unrolling the short inner loops.
+# Without loop unrolling it takes 2 minutes and runs 104 ms per 2^20 events
+# (at -O1: 122 ms; fully unrolled at -O3: 62.5 ms).
+UNIT_FLAGS = {"tu_gg_ttgg_4.hip": ("-fno-unroll-loops",)}
 
 # |M|^2 units in FP64, FP32 and with MFMA colour (tu_<process>_<0|1|2>.hip,
 # and 5, 6 for the alternative helicity schedule in FP64 and FP32):

@@ -832,6 +832,11 @@ JIT_EXTRA_LEVELS = {"gg_ttgg": 1}
 # 11.9 ms.  FP64 g g -> t tbar g: with one level 2.35, without 2.44 ms per
 # 2^22 events.
 JIT_EXTRA_LEVELS_FP64 = {"gg_ttgg": 3, "gg_ttg": 1}
+# the same for the BF16 pair kernels (bf16x2: every operation is widened to
+# FP32 and rounded back, so their code is the longest): g g -> t tbar g g
+# with three levels 104 against 131 ms per 2^20 events (FP16 gains nothing:
+# 8.4 against 8.1 ms)
+JIT_EXTRA_LEVELS_BF16 = {"gg_ttgg": 3}
 # stop the compiler from hoisting those lazily emitted sub-currents back out
 KEEP_LAZY_IN_LOOP = True
 # processes whose helicity loops read the internal momenta through the
@@ -1274,19 +1279,27 @@ def emit_process(p):
         L.append("  static constexpr int NSCHED = 1;")
         L.append("  template <int SCHED, class T, class F> NLO_HD static void helicity_sum_sched(const Pre<T>& s, T mt, "
                  "F&& body) { helicity_sum(s, mt, body); }")
-    if j_f64 == j_def:
+    j_bf16 = JIT_EXTRA_LEVELS_BF16.get(p.name, j_def)
+    special = []
+    if j_f64 != j_def:
+        special.append(("double", j_f64, "helicity_sum_fp64"))
+    if j_bf16 != j_def:
+        special.append(("bf16x2", j_bf16, "helicity_sum_bf16"))
+    if not special:
         L.extend(emit_nested(p, mslot, dslot, N, nin))
     else:
-        # two schedules: the FP64 instantiation takes its own lazy depth; the
+        # the FP64 (and BF16) instantiations take their own lazy depths; the
         # others run the default schedule in helicity_sum itself
-        L.extend(emit_nested(p, mslot, dslot, N, nin, j_f64, "helicity_sum_fp64"))
+        for ty, d, name in special:
+            L.extend(emit_nested(p, mslot, dslot, N, nin, d, name))
         main = emit_nested(p, mslot, dslot, N, nin, j_def)
         L.append(main[0])
         L.append(main[1])
-        L.append("    if constexpr (std::is_same<T, double>::value) {")
-        L.append("      helicity_sum_fp64(s, mt, body);")
-        L.append("      return;")
-        L.append("    }")
+        for ty, d, name in special:
+            L.append("    if constexpr (std::is_same<T, %s>::value) {" % ty)
+            L.append("      %s(s, mt, body);" % name)
+            L.append("      return;")
+            L.append("    }")
         L.extend(main[2:])
     # colour sum: J^dagger C J = |L^T Re J|^2 + |L^T Im J|^2, C = L L^T
     Lc = cholesky_lower(p.colour_matrix)
